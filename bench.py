@@ -1,0 +1,149 @@
+"""Benchmark: particle-steps/s of the boosted-frame PIC step on one MI355X.
+
+Prints ONE JSON line.  The timed region is K full steps of ``pic_step`` (every
+step: injection, periodic sort, gather/push/deposit, current fold + filter,
+Yee update) on the gamma_boost = 130, 8192 x 512 cell, 8 particles/cell
+workload (33.5 M electrons with implicit ion partners) in the FP32 split
+precision form, all inputs resident in HBM.  Beside it: the same workload in
+FP64, per-kernel HIP-event times of the dominant kernel against the HBM
+roofline, and the FP64 oracle timed on the host cores on a bounded sample.
+"""
+import argparse
+import json
+import math
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0   # MI355X HBM3E, vendor nominal
+# Algorithmic bytes (compulsory traffic) of the gather-push-deposit kernel:
+# each particle's state read and written once, each field array of the
+# particle step read once and the current written once.
+BYTES_PER_PARTICLE = {"fp32": 52.0, "fp64": 96.0}   # 2D: read 28 + write 24 (FP32)
+BYTES_PER_CELL_GPD = {"fp32": 36.0, "fp64": 72.0}   # E, B read (24) + J write (12)
+BYTES_PER_CELL_STEP = {"fp32": 72.0, "fp64": 144.0}  # whole step: E, B r+w, J w+r
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def run_gpu(name, precision, steps, warmup, sort_interval, with_kernel_times=True):
+    import torch
+    import paper_1011_0917_amd as P
+    from workloads import WORKLOADS, resolve_gpu
+    W = WORKLOADS[name]
+    cfg, init, _ = resolve_gpu(W, precision=precision, sort_interval=sort_interval)
+    sim = P.Simulation(cfg, capacity=init["capacity"])
+    sim.init_boosted_plasma(init["gamma_b"], n_uniform=init["n_lab"], laser=init["laser"])
+    sim.pic_step(warmup)
+    d0 = sim.diagnostics()
+    torch.cuda.synchronize()
+    if with_kernel_times:
+        sim.kernel_timing(True)
+    start = torch.cuda.Event(enable_timing=True)
+    end = torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    start.record()
+    sim.pic_step(steps)
+    end.record()
+    torch.cuda.synchronize()
+    ms = start.elapsed_time(end)
+    kt = {}
+    if with_kernel_times:
+        for k in P.TIMER:
+            t, n = sim.kernel_time(k)
+            kt[k] = {"ms": t, "launches": n}
+    d1 = sim.diagnostics()
+    cells = W["nz"] * W["nx"] * W.get("ny", 1)
+    nparts = 0.5 * (d0["live"] + d1["live"])
+    sim.close()
+    del sim
+    torch.cuda.empty_cache()
+    return {"ms": ms, "steps": steps, "particles": nparts, "cells": cells, "kernels": kt,
+            "diag_end": d1, "W": W}
+
+
+def cpu_baseline(name, nz_sample=256, steps=6):
+    """The FP64 oracle, single-threaded, on a slab of the same workload."""
+    import oracle as O
+    from workloads import WORKLOADS, resolve_oracle, small
+    W = small(name, nz=nz_sample, steps=steps)
+    kw, init = resolve_oracle(W)
+    s = O.Sim(**kw)
+    s.init(n_uniform=init["n_lab"], laser=init["laser"])
+    s.step(1)
+    n = s.num_pairs()
+    t = time.perf_counter()
+    s.step(steps)
+    el = time.perf_counter() - t
+    return {"value": n * steps / el, "unit": "particle-steps/s", "cores": 1, "kind": "oracle",
+            "sample": f"{name} physics on a {nz_sample} x {W['nx']} cell slab "
+                      f"({n} electrons + partners), {steps} steps, {el:.1f} s, 1 thread"}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=200)
+    ap.add_argument("--warmup", type=int, default=20)
+    ap.add_argument("--workload", default="boost130_2d")
+    ap.add_argument("--sort-interval", type=int, default=50)
+    ap.add_argument("--no-fp64", action="store_true")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print("bench.py measures one GPU: this build runs on a single MI355X "
+              "(multi-GPU sharding is a design note, not built)", file=sys.stderr)
+        sys.exit(2)
+    import torch
+    torch.cuda.set_device(0)
+    log(f"bench: {args.workload} fp32 split, {args.warmup} warmup + {args.steps} timed steps")
+    r32 = run_gpu(args.workload, "fp32", args.steps, args.warmup, args.sort_interval)
+    ms_step = r32["ms"] / r32["steps"]
+    pps = r32["particles"] * r32["steps"] / (r32["ms"] * 1e-3)
+    cups = r32["cells"] * r32["steps"] / (r32["ms"] * 1e-3)
+    # dominant kernel: tiled gather-push-deposit
+    kt = r32["kernels"]["gpd_tiled"]
+    gpd_ms = kt["ms"] / max(kt["launches"], 1)
+    gpd_bytes = (BYTES_PER_PARTICLE["fp32"] * r32["particles"] +
+                 BYTES_PER_CELL_GPD["fp32"] * r32["cells"])
+    achieved = gpd_bytes / (gpd_ms * 1e-3) / 1e9
+    step_bytes = BYTES_PER_PARTICLE["fp32"] * r32["particles"] + \
+        BYTES_PER_CELL_STEP["fp32"] * r32["cells"]
+    out = {
+        "metric": "particle-steps/s (FP32 split boosted-frame PIC step) + % HBM roofline",
+        "value": pps, "unit": "particle-steps/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": ms_step, "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": "f32",
+        "data": "synthetic (seeded SplitMix64 plasma, analytic laser)",
+        "config": {"workload": args.workload, "grid": [r32["W"]["nz"], r32["W"]["nx"]],
+                   "ppc": r32["W"]["ppc"], "gamma_boost": r32["W"]["gamma_b"],
+                   "particles": int(r32["particles"]), "sort_interval": args.sort_interval,
+                   "parallelism": "1 GPU"},
+        "cell_updates_per_s": cups,
+        "step_roofline_frac": step_bytes / (ms_step * 1e-3) / 1e9 / HBM_PEAK_GBS,
+        "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS,
+                     "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS, "traffic": None,
+                     "kernel": "k_gpd_tiled", "kernel_ms": gpd_ms},
+        "kernel_ms_per_step": {k: v["ms"] / args.steps for k, v in r32["kernels"].items()},
+    }
+    if not args.no_fp64:
+        log("bench: fp64 plain form")
+        r64 = run_gpu(args.workload, "fp64", max(args.steps // 2, 10), args.warmup,
+                      args.sort_interval, with_kernel_times=False)
+        pps64 = r64["particles"] * r64["steps"] / (r64["ms"] * 1e-3)
+        out["fp64"] = {"value": pps64, "unit": "particle-steps/s",
+                       "ms_per_step": r64["ms"] / r64["steps"]}
+        out["fp32_over_fp64"] = pps / pps64
+    if not args.no_cpu_baseline:
+        log("bench: oracle cpu baseline")
+        out["cpu_baseline"] = cpu_baseline(args.workload)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

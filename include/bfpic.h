@@ -1,0 +1,240 @@
+/*
+ * bfpic.h -- C ABI of the MI355X boosted-frame particle-in-cell library.
+ *
+ * One explicit electromagnetic PIC step in a Lorentz-boosted calculation frame
+ * (Vay, Geddes, Cormier-Michel, Grote, "Effects of hyperbolic rotation in
+ * Minkowski space on the modeling of plasma accelerators in a Lorentz boosted
+ * frame"): field gather, relativistic Boris push, charge-conserving
+ * (Esirkepov) current deposit, binomial current filter with compensation, Yee
+ * FDTD update, with the boosted-frame laser and plasma initialisation, the
+ * continuous plasma injection and the moving window around it.  The paper
+ * motivates the frame (introduction; section "Effect of the hyperbolic
+ * rotation") and the filtering (section "Mitigation of a numerical
+ * instability") and defers the scheme itself to companion papers; the
+ * textbook steps used are named at each entry point below.
+ *
+ * Units (normalised): time 1/omega0, length c/omega0 (lambda0 = 2 pi),
+ * momentum u = gamma beta, E in m c omega0 / e, B in m omega0 / e, density in
+ * n_crit.  Electrons carry q = -1, m = 1; each has a co-located ion partner of
+ * opposite charge that moves rigidly with the lab-rest plasma.
+ *
+ * Conventions shared by every call
+ *   - Every call returns a status: BFPIC_OK (0) or a negative BFPIC_ERR_*.
+ *     On error nothing on the device has been modified and the message is
+ *     available from bfpic_last_error().
+ *   - All device memory is owned by the caller.  bfpic_query_sizes() reports
+ *     one workspace size; the caller allocates that many bytes of device
+ *     memory (256-byte aligned) and passes the pointer to bfpic_create().  The
+ *     library keeps the pointer and never frees it; the workspace must outlive
+ *     the context.
+ *   - All device work is enqueued on the HIP stream given to bfpic_create()
+ *     and is asynchronous unless a call says it synchronises.
+ *   - One context per stream; a context is not thread-safe.
+ *   - Field layout on the grid: component arrays indexed [i][j][k] with k (y)
+ *     fastest, i over the z rows 0..nz, j over x, k over y (ny = 1 in 2D).
+ *     Node (i, j, k) of a component sits at ((i+sz) dz, (j+sx) dx, (k+sy) dy)
+ *     with the Yee offsets (sz, sx, sy): Ex (0,1/2,0), Ey (0,0,1/2),
+ *     Ez (1/2,0,0), Bx (1/2,0,1/2), By (1/2,1/2,0), Bz (0,1/2,1/2); the y
+ *     offsets are absent in 2D.
+ */
+#ifndef BFPIC_H
+#define BFPIC_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define BFPIC_OK 0
+#define BFPIC_ERR_ARG (-1)         /* bad argument, config or size */
+#define BFPIC_ERR_CAPACITY (-2)    /* particle capacity too small */
+#define BFPIC_ERR_HIP (-3)         /* a HIP runtime call failed */
+#define BFPIC_ERR_STATE (-4)       /* call out of order (e.g. step before init) */
+#define BFPIC_ERR_UNSUPPORTED (-5) /* option not implemented */
+
+enum { BFPIC_FP64 = 0, BFPIC_FP32_SPLIT = 1 };
+enum { BFPIC_BC_PERIODIC = 0, BFPIC_BC_MUR = 1 };
+enum { BFPIC_LOAD_RANDOM = 0, BFPIC_LOAD_CENTERED = 1 };
+
+/* Field component ids for bfpic_get_field / bfpic_set_field. */
+enum { BFPIC_EX = 0, BFPIC_EY, BFPIC_EZ, BFPIC_BX, BFPIC_BY, BFPIC_BZ,
+       BFPIC_JX, BFPIC_JY, BFPIC_JZ };
+
+typedef struct bfpic_config {
+  int32_t dim;               /* 2: plane (z, x), y invariant; 3: (z, x, y) */
+  int32_t nz, nx, ny;        /* cells per axis (ny ignored in 2D) */
+  double dz, dx, dy;         /* cell sizes in the calculation frame */
+  double cfl;                /* dt = cfl / sqrt(sum 1/d^2), 0 < cfl < 1 */
+  int32_t shape_order;       /* 1 linear, 2 quadratic */
+  int32_t filter_passes;     /* N binomial (1/4,1/2,1/4) passes per axis */
+  int32_t filter_compensate; /* 1: one (-N/4, 1+N/2, -N/4) pass per axis */
+  int32_t precision;         /* BFPIC_FP64 or BFPIC_FP32_SPLIT */
+  int32_t deterministic;     /* must be 0 (fixed-point deposit not built) */
+  int32_t z_boundary;        /* BFPIC_BC_PERIODIC or BFPIC_BC_MUR */
+  int32_t ppc;               /* macro-particles per lattice cell */
+  int32_t load;              /* BFPIC_LOAD_RANDOM (SplitMix64) or _CENTERED */
+  int32_t sort_interval;     /* steps between particle sorts; 0: never re-sort */
+  uint64_t seed;             /* generator key of the in-cell positions */
+  double beta_window;        /* window speed along +z (calculation frame) */
+  int32_t auto_window;       /* 1: pic_step shifts the window on schedule */
+} bfpic_config;
+
+/* Lab-frame plasma density.  nknots == 0: n_uniform everywhere.  nknots >= 2:
+ * piecewise linear through (z_lab[m], n[m]) (host arrays, increasing z_lab),
+ * zero outside.  du is a uniform momentum added to every electron at birth
+ * (x, y, z order; zero for a cold plasma). */
+typedef struct bfpic_density {
+  double n_uniform;
+  int32_t nknots;
+  const double* z_lab;
+  const double* n;
+  double du[3];
+} bfpic_density;
+
+/* Lab-frame laser: y-polarised paraxial Gaussian pulse along +z, given by its
+ * vector potential A_y = a0 G(xi) Im[U(r, zeta) exp(i (xi + phase))],
+ * xi = z - t - z_center, zeta = z - z_focus, G = exp(-xi^2/L^2) (cut at
+ * |xi| > 4 L; L <= 0: no envelope), U the paraxial beam of 1/e waist w0
+ * (w0 <= 0: plane; collimated = 1: exp(-r^2/w0^2) without diffraction).
+ * The transverse axis is the box centre.  images_* > 0 sums that many
+ * periodic images on each side (for periodic boxes). */
+typedef struct bfpic_laser {
+  double a0, w0, L, z_center, z_focus, phase;
+  int32_t collimated;
+  int32_t images_z, images_x, images_y;
+} bfpic_laser;
+
+typedef struct bfpic_sizes {
+  int64_t workspace_bytes;   /* total device bytes to allocate */
+  int64_t field_bytes;       /* of which: fields */
+  int64_t particle_bytes;    /* of which: particle arrays (both sort buffers) */
+  int64_t scratch_bytes;     /* of which: tile, sort and diagnostic scratch */
+} bfpic_sizes;
+
+typedef struct bfpic_diag {
+  int64_t step;
+  double t;                  /* calculation-frame time */
+  double window_cells;       /* total window displacement [cells] */
+  double drift_cells;        /* D = step * beta_b dt / dz + window_cells */
+  double ue, ub;             /* 1/2 sum E^2 dV, 1/2 sum B^2 dV over the domain */
+  double ukin;               /* sum over electrons w (gamma - 1) */
+  double ukin_drift;         /* sum over electrons w (gamma - gamma_b) */
+  double wake_amp;           /* max |Ez| on the axis row */
+  double gauss_res;          /* max |div E - F rho| over the checked nodes */
+  double charge;             /* sum over electrons q w */
+  int64_t live;              /* live electrons */
+  int32_t nan_flag;          /* 1 if any field or particle value is not finite */
+} bfpic_diag;
+
+typedef struct bfpic_ctx bfpic_ctx;
+
+/* ---- boost helper (host FP64, section "Effect of the hyperbolic rotation":
+ *      the frame change is a rotation by rapidity artanh(beta_b)) ---- */
+double bfpic_beta(double gamma);                 /* sqrt(gamma^2 - 1) / gamma */
+double bfpic_drift_u(double gamma_b);            /* -gamma_b beta_b */
+/* gamma_g = 1/sqrt(n_lab) (cold plasma, 1D) and the boosted group velocity
+ * (beta_g - beta_b)/(1 - beta_g beta_b) without cancellation. */
+double bfpic_group_gamma(double n_lab);
+double bfpic_boosted_group_beta(double gamma_b, double n_lab);
+/* Longitudinal resolution against the vacuum laser wavelength (section
+ * "Mitigation of a numerical instability"): gamma_b (1 + beta_b) lambda0 / cells. */
+double bfpic_boosted_dz(double gamma_b, double lambda0, double cells_per_wavelength);
+double bfpic_yee_dt(int32_t dim, double dz, double dx, double dy, double cfl);
+
+/* ---- lifecycle ---- */
+
+/* Pure host.  Sizes of the device workspace for cfg and a particle capacity
+ * (number of electrons; partners are implicit).  ERR_ARG on a bad config. */
+int bfpic_query_sizes(const bfpic_config* cfg, int64_t particle_capacity, bfpic_sizes* out);
+
+/* Creates a context on the current HIP device.  workspace: device pointer of
+ * at least sizes.workspace_bytes, owned by the caller.  hip_stream: a
+ * hipStream_t (NULL = the null stream).  ERR_ARG if the workspace is too small. */
+int bfpic_create(const bfpic_config* cfg, int64_t particle_capacity, void* workspace,
+                 int64_t workspace_bytes, void* hip_stream, bfpic_ctx** out);
+void bfpic_destroy(bfpic_ctx* h);
+const char* bfpic_last_error(const bfpic_ctx* h);
+
+/* Sets the fields and particles at t' = 0 in the frame boosted by gamma_boost
+ * along +z (gamma_boost = 1: lab frame).  Laser: the lab potential above is
+ * evaluated on the t' = 0 hyperplane, i.e. at lab (t, z) = (gamma beta z',
+ * gamma z'); Ey' = -dA/dt' there, B' = curl_h A' on the grid, and in 3D Ez'
+ * from discrete div E' = 0 integrated from the low z end.  Plasma: every
+ * lattice cell of the box gets ppc electrons with co-located ion partners,
+ * u = (0, 0, -gamma_b beta_b) + du, weight gamma_b n_lab(z_lab) dV / ppc at
+ * the lab birth coordinate z_lab = gamma_b z'.  n_e may be NULL (vacuum),
+ * laser may be NULL (no laser).  Resets step, window and injection counters.
+ * ERR_CAPACITY if the initial particles do not fit. */
+int init_boosted_plasma(bfpic_ctx* h, double gamma_boost, const bfpic_density* n_e,
+                        const bfpic_laser* laser);
+
+/* Advances nsteps full steps.  Each step: inject the lattice columns whose low
+ * edge has entered the box (k - D < nz), re-sort the particles if the sort
+ * interval is due, then gather -> Boris (split drift form) -> move ->
+ * Esirkepov deposit of each electron and its drifting partner -> filter J ->
+ * B half step, E full step (+ Mur), B half step; then drop pairs more than
+ * order+1 cells outside [0, nz] along z.  With auto_window the window shifts
+ * after a step by floor(beta_window t / dz) - window_cells.  Asynchronous.
+ * ERR_CAPACITY (before any launch) if the injections would not fit. */
+int pic_step(bfpic_ctx* h, int32_t nsteps);
+
+/* Shifts the window by ncells (either sign): field rows move by ncells,
+ * the rows that enter are zero, particles keep their lab positions (their
+ * grid coordinates drop by ncells).  Columns that become due are injected by
+ * the next pic_step.  ERR_ARG on a periodic z boundary.  Asynchronous. */
+int moving_window_shift(bfpic_ctx* h, int32_t ncells);
+
+/* Host FP64 schedule: floor(beta_window t / dz) - window_cells. */
+int bfpic_window_due(bfpic_ctx* h, int32_t* ncells);
+
+/* Fills *out (host) with FP64 diagnostics.  lineout_dev (may be NULL): device
+ * buffer of nz doubles that receives Ez on the axis row (j = nx/2, k = ny/2).
+ * mask is reserved (pass 0xffffffff).  Synchronises the stream. */
+int diagnostics(bfpic_ctx* h, uint32_t mask, bfpic_diag* out, double* lineout_dev);
+
+/* ---- state access (tests and tools; asynchronous unless stated) ---- */
+
+/* Copies component comp at integer time (domain rows 0..nz; row nz is zero
+ * where the component has no node there) into out_dev, FP64, shape
+ * (nz+1) x nx x ny.  For J the last step's filtered current. */
+int bfpic_get_field(bfpic_ctx* h, int32_t comp, double* out_dev);
+/* Overwrites E or B component comp from in_dev (same layout). */
+int bfpic_set_field(bfpic_ctx* h, int32_t comp, const double* in_dev);
+
+/* Number of particle slots in use (live + not yet compacted).  Synchronises. */
+int bfpic_num_slots(bfpic_ctx* h, int64_t* n);
+
+/* Exports every slot as absolute FP64 state into device arrays of at least
+ * bfpic_num_slots entries: electron position z, x, y (grid cells, relative to
+ * the window), momentum (ux, uy, uz), weight, id (-1: removed). */
+int bfpic_get_particles(bfpic_ctx* h, double* z, double* x, double* y, double* ux,
+                        double* uy, double* uz, double* w, int32_t* id);
+
+/* Forces a particle sort now (co-moving tile-major keys, ties by id). */
+int bfpic_sort(bfpic_ctx* h);
+
+/* The last sort: the key and id of every source slot, and perm[d] = source
+ * slot of destination d (live particles only).  Device arrays of at least
+ * bfpic_num_slots entries before that sort.  *n (host) receives the number of
+ * source slots and *n_live the number of sorted live particles; *tz_min,
+ * *ntz (host) the co-moving tile rows used for the keys.  Synchronises. */
+int bfpic_last_sort(bfpic_ctx* h, int32_t* key_dev, int32_t* id_dev, int32_t* perm_dev,
+                    int64_t* n, int64_t* n_live, int64_t* tz_min, int32_t* ntz);
+
+/* Tile geometry used by the sort key: tile sizes along z, x, y in cells. */
+int bfpic_tile_shape(const bfpic_ctx* h, int32_t* tz, int32_t* tx, int32_t* ty);
+
+/* Per-kernel timing with HIP events on the context's stream.  enable = 1
+ * starts recording (and clears totals).  bfpic_kernel_time synchronises and
+ * returns the summed milliseconds and launch count of a kernel class:
+ * 0 gather-push-deposit (tiled), 1 the same on the global path (unsorted tail
+ * and stragglers), 2 current fold + filter, 3 Yee (both half steps, E, Mur),
+ * 4 sort, 5 injection, 6 window shift. */
+int bfpic_kernel_timing(bfpic_ctx* h, int32_t enable);
+int bfpic_kernel_time(bfpic_ctx* h, int32_t cls, double* total_ms, int64_t* launches);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

@@ -41,12 +41,13 @@ class Config(C.Structure):
                 ("order", C.c_int32), ("filter_passes", C.c_int32),
                 ("filter_compensate", C.c_int32), ("zbc", C.c_int32), ("ppc", C.c_int32),
                 ("seed", C.c_uint64), ("gamma_b", C.c_double), ("beta_window", C.c_double),
-                ("auto_window", C.c_int32), ("ions", C.c_int32)]
+                ("auto_window", C.c_int32), ("ions", C.c_int32), ("load", C.c_int32)]
 
 
 class Density(C.Structure):
     _fields_ = [("n_uniform", C.c_double), ("nknots", C.c_int32),
-                ("z_lab", C.POINTER(C.c_double)), ("n", C.POINTER(C.c_double))]
+                ("z_lab", C.POINTER(C.c_double)), ("n", C.POINTER(C.c_double)),
+                ("du", C.c_double * 3)]
 
 
 class Laser(C.Structure):
@@ -169,11 +170,12 @@ class Sim:
 
     def __init__(self, dim=2, nz=16, nx=16, ny=1, dz=1.0, dx=1.0, dy=1.0, dt=0.5, order=1,
                  filter_passes=0, filter_compensate=0, zbc=0, ppc=1, seed=0, gamma_b=1.0,
-                 beta_window=0.0, auto_window=0, ions=1):
+                 beta_window=0.0, auto_window=0, ions=1, load=0):
         c = Config(dim=dim, nz=nz, nx=nx, ny=ny if dim == 3 else 1, dz=dz, dx=dx, dy=dy, dt=dt,
                    order=order, filter_passes=filter_passes,
                    filter_compensate=filter_compensate, zbc=zbc, ppc=ppc, seed=seed,
-                   gamma_b=gamma_b, beta_window=beta_window, auto_window=auto_window, ions=ions)
+                   gamma_b=gamma_b, beta_window=beta_window, auto_window=auto_window, ions=ions,
+                   load=load)
         self.cfg = c
         self.h = lib().orc_create(C.byref(c))
         self.shape = (nz + 1, nx, (ny if dim == 3 else 1))
@@ -185,12 +187,13 @@ class Sim:
             self.h = None
 
     def init(self, n_uniform=None, knots_z=None, knots_n=None, laser: Laser | None = None,
-             fill=True):
+             fill=True, du=(0.0, 0.0, 0.0)):
         dens = None
         self._keep = []
         if n_uniform is not None or knots_z is not None:
             dens = Density()
             dens.n_uniform = 0.0 if n_uniform is None else float(n_uniform)
+            dens.du[:] = [float(v) for v in du]
             if knots_z is not None:
                 kz = np.ascontiguousarray(knots_z, dtype=np.float64)
                 kn = np.ascontiguousarray(knots_n, dtype=np.float64)

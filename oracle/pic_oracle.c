@@ -61,6 +61,7 @@ struct orc_sim {
   int nknots;
   double* kz;
   double* kn;
+  double du0[3];
 };
 
 /* ------------------------------------------------------------------------ */
@@ -718,14 +719,17 @@ static void add_column(orc_sim* s, int64_t k, double D) {
   for (int64_t l = 0; l < s->nyy; l++)
     for (int64_t j = 0; j < c->nx; j++)
       for (int32_t q = 0; q < c->ppc; q++) {
-        double rz = orc_cell_offset(c->seed, k, l, j, q, 0, c->nx, s->nyy, c->ppc);
-        double rx = orc_cell_offset(c->seed, k, l, j, q, 1, c->nx, s->nyy, c->ppc);
-        double ry = d3 ? orc_cell_offset(c->seed, k, l, j, q, 2, c->nx, s->nyy, c->ppc) : 0.0;
+        double rz = 0.5, rx = 0.5, ry = d3 ? 0.5 : 0.0;
+        if (!c->load) {
+          rz = orc_cell_offset(c->seed, k, l, j, q, 0, c->nx, s->nyy, c->ppc);
+          rx = orc_cell_offset(c->seed, k, l, j, q, 1, c->nx, s->nyy, c->ppc);
+          ry = d3 ? orc_cell_offset(c->seed, k, l, j, q, 2, c->nx, s->nyy, c->ppc) : 0.0;
+        }
         double zl = c->gamma_b * ((double)k + rz) * c->dz;
         double w = c->gamma_b * lab_density(s, zl) * dV / (double)c->ppc;
         double z = ((double)k + rz) - D, x = (double)j + rx, y = (double)l + ry;
         int64_t id = ((k * s->nyy + l) * c->nx + j) * c->ppc + q;
-        orc_add_pair(s, z, x, y, ub, 0.0, 0.0, z, x, y, w, id);
+        orc_add_pair(s, z, x, y, ub + s->du0[2], s->du0[0], s->du0[1], z, x, y, w, id);
       }
 }
 
@@ -779,7 +783,9 @@ int orc_init(orc_sim* s, const orc_density* dens, const orc_laser* laser, int32_
   free(s->kn);
   s->kz = s->kn = NULL;
   s->nknots = 0;
+  s->du0[0] = s->du0[1] = s->du0[2] = 0.0;
   if (dens) {
+    for (int a = 0; a < 3; a++) s->du0[a] = dens->du[a];
     s->n_uniform = dens->n_uniform;
     s->nknots = dens->nknots;
     if (dens->nknots >= 2) {

@@ -58,6 +58,7 @@ typedef struct orc_config {
   double beta_window;        /* window speed (+z) in the calculation frame */
   int32_t auto_window;       /* 1: shift after each step per the schedule */
   int32_t ions;              /* 1: every electron has a co-located ion partner */
+  int32_t load;              /* 0: SplitMix64 in-cell offsets; 1: every slot at the cell centre */
 } orc_config;
 
 typedef struct orc_density {
@@ -65,6 +66,7 @@ typedef struct orc_density {
   int32_t nknots;            /* >= 2: piecewise-linear through knots, 0 outside */
   const double* z_lab;       /* knot positions, lab frame [c/omega0], increasing */
   const double* n;           /* knot densities [n_crit] */
+  double du[3];              /* momentum added to every electron at birth (x, y, z) */
 } orc_density;
 
 typedef struct orc_laser {

@@ -1,0 +1,1118 @@
+// bfpic.hip -- host side of the C ABI declared in include/bfpic.h.
+//
+// The context borrows one caller-owned device workspace, carves it into the
+// field, particle, sort, tile and diagnostic buffers, and enqueues every step
+// on the caller's stream with no host synchronisation inside pic_step.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "../../include/bfpic.h"
+#include "device_common.hpp"
+#include "kernels_diag.hpp"
+#include "kernels_fields.hpp"
+#include "kernels_particles.hpp"
+#include "kernels_sort.hpp"
+
+using namespace bfpic;
+
+// ---------------------------------------------------------------------------
+// Boost helper (host FP64).  Frame change along +z by rapidity artanh(beta_b).
+// ---------------------------------------------------------------------------
+extern "C" double bfpic_beta(double gamma) { return std::sqrt(gamma * gamma - 1.0) / gamma; }
+extern "C" double bfpic_drift_u(double gamma_b) { return -std::sqrt(gamma_b * gamma_b - 1.0); }
+extern "C" double bfpic_group_gamma(double n_lab) { return 1.0 / std::sqrt(n_lab); }
+extern "C" double bfpic_boosted_group_beta(double gamma_b, double n_lab) {
+  // (beta_g - beta_b) / (1 - beta_g beta_b) with
+  // beta_g - beta_b = (gamma_b^-2 - gamma_g^-2) / (beta_g + beta_b) and
+  // 1 - beta_g beta_b = (gamma_g^-2 + gamma_b^-2 + (beta_g - beta_b)^2) / 2
+  double gg = bfpic_group_gamma(n_lab);
+  double bg = bfpic_beta(gg), bb = bfpic_beta(gamma_b);
+  double a = 1.0 / (gamma_b * gamma_b), c = 1.0 / (gg * gg);
+  double diff = (a - c) / (bg + bb);
+  return diff / (0.5 * (c + a + diff * diff));
+}
+extern "C" double bfpic_boosted_dz(double gamma_b, double lambda0, double cells) {
+  return gamma_b * (1.0 + bfpic_beta(gamma_b)) * lambda0 / cells;
+}
+extern "C" double bfpic_yee_dt(int32_t dim, double dz, double dx, double dy, double cfl) {
+  double s = 1.0 / (dz * dz) + 1.0 / (dx * dx) + (dim == 3 ? 1.0 / (dy * dy) : 0.0);
+  return cfl / std::sqrt(s);
+}
+
+// ---------------------------------------------------------------------------
+// Tile shapes: 2D 16 x 32 cells, 3D 8 x 8 x 8 cells; excursion margin 1 cell.
+// ---------------------------------------------------------------------------
+constexpr int kExc = 1;
+constexpr int kT2Z = 16, kT2X = 32;
+constexpr int kT3 = 8;
+constexpr int kF2Z = 16, kF2X = 64;  // filter output tiles
+constexpr int kF3 = 8;
+constexpr int kNumTimers = 7;
+
+static inline int64_t align256(int64_t b) { return (b + 255) & ~int64_t(255); }
+static inline int64_t cdiv(int64_t a, int64_t b) { return (a + b - 1) / b; }
+
+struct bfpic_ctx {
+  bfpic_config cfg;
+  hipStream_t stream = nullptr;
+  std::string err;
+  int dim = 2, nz = 0, nx = 0, ny = 1, order = 1;
+  bool fp64 = false;
+  Geo g{};
+  double dt = 0, dz = 0, dx = 0, dy = 1;
+  double gamma_b = 1, beta_b = 0, u_b = 0, sb = 0;
+  bool inited = false;
+  int64_t step = 0, window_cells = 0, next_col = 0;
+  bool has_plasma = false;
+  int64_t cap = 0, slots_bound = 0, tail_bound = 0;
+  DensityK dens{};
+  // tiles
+  bool tiled = false;
+  int TZ = 1, TX = 1, TY = 1, ntx = 1, nty = 1, ntz = 0, ntz_max = 0, zc0 = 0;
+  int LZ = 1, LX = 1, LY = 1, LV = 1;
+  int64_t maxtiles = 0, maxkeys = 0;
+  size_t lds_tiled = 0, lds_limit = 65536;
+  // device buffers
+  uint8_t* ws = nullptr;
+  int64_t ws_bytes = 0;
+  void* F[6] = {};
+  void* Fs[6] = {};
+  void* Jf[3] = {};
+  void* Jo[3] = {};
+  void* pid[2] = {};
+  void* pxi[2][3] = {};
+  void* pdu[2][3] = {};
+  void* pw[2] = {};
+  int cur = 0;
+  int* counts = nullptr;   // [0] slots in use, [1] sorted prefix, [2] slots at last sort
+  int* ovf_rows = nullptr;
+  int* tile_start = nullptr;
+  void* scratch = nullptr;
+  int* key = nullptr;
+  int* rank = nullptr;
+  int* perm = nullptr;
+  int* cnt = nullptr;
+  int* off = nullptr;
+  int* bsum = nullptr;
+  double* g64a = nullptr;  // FP64 grid scratch (laser potential, rho)
+  double* g64b = nullptr;  // FP64 grid scratch (laser Ey, filtered rho)
+  double* partials = nullptr;
+  double* dout = nullptr;
+  int* nanflag = nullptr;
+  void* mur_save = nullptr;
+  int64_t last_sort_nkeys = 0;
+  int last_sort_tzmin = 0, last_sort_ntz = 0;
+  bool have_sort = false;
+  // timing
+  bool timing = false;
+  std::vector<std::pair<hipEvent_t, hipEvent_t>> ev[kNumTimers];
+  std::vector<hipEvent_t> pool;
+};
+
+#define HIPCHK(h, call)                                                           \
+  do {                                                                            \
+    hipError_t e_ = (call);                                                       \
+    if (e_ != hipSuccess) {                                                       \
+      (h)->err = std::string(#call) + ": " + hipGetErrorString(e_);               \
+      return BFPIC_ERR_HIP;                                                       \
+    }                                                                             \
+  } while (0)
+
+static int fail(bfpic_ctx* h, int code, const std::string& m) {
+  if (h) h->err = m;
+  return code;
+}
+
+// ---------------------------------------------------------------------------
+// Timing helpers
+// ---------------------------------------------------------------------------
+static hipEvent_t take_event(bfpic_ctx* h) {
+  if (!h->pool.empty()) {
+    hipEvent_t e = h->pool.back();
+    h->pool.pop_back();
+    return e;
+  }
+  hipEvent_t e;
+  if (hipEventCreate(&e) != hipSuccess) return nullptr;
+  return e;
+}
+struct Timer {
+  bfpic_ctx* h;
+  int cls;
+  hipEvent_t a = nullptr;
+  Timer(bfpic_ctx* h_, int c) : h(h_), cls(c) {
+    if (h->timing) {
+      a = take_event(h);
+      if (a) hipEventRecord(a, h->stream);
+    }
+  }
+  ~Timer() {
+    if (h->timing && a) {
+      hipEvent_t b = take_event(h);
+      if (b) {
+        hipEventRecord(b, h->stream);
+        h->ev[cls].push_back({a, b});
+      }
+    }
+  }
+};
+
+// ---------------------------------------------------------------------------
+// Geometry and layout
+// ---------------------------------------------------------------------------
+static int check_cfg(const bfpic_config* c, std::string& why) {
+  if (!c) return (why = "null config", 0);
+  if (c->dim != 2 && c->dim != 3) return (why = "dim must be 2 or 3", 0);
+  if (c->nz < 4 || c->nx < 2 || (c->dim == 3 && c->ny < 2)) return (why = "grid too small", 0);
+  if (!(c->dz > 0 && c->dx > 0 && (c->dim == 2 || c->dy > 0))) return (why = "cell sizes", 0);
+  if (!(c->cfl > 0 && c->cfl < 1)) return (why = "cfl must be in (0, 1)", 0);
+  if (c->shape_order != 1 && c->shape_order != 2) return (why = "shape_order 1 or 2", 0);
+  if (c->filter_passes < 0 || c->filter_passes > 16) return (why = "filter_passes", 0);
+  if (c->precision != BFPIC_FP64 && c->precision != BFPIC_FP32_SPLIT) return (why = "precision", 0);
+  if (c->z_boundary != BFPIC_BC_PERIODIC && c->z_boundary != BFPIC_BC_MUR) return (why = "z_boundary", 0);
+  if (c->ppc < 1) return (why = "ppc", 0);
+  if (c->sort_interval < 0) return (why = "sort_interval", 0);
+  return 1;
+}
+
+static void derive(bfpic_ctx* h, const bfpic_config* c) {
+  h->cfg = *c;
+  h->dim = c->dim;
+  h->nz = c->nz;
+  h->nx = c->nx;
+  h->ny = c->dim == 3 ? c->ny : 1;
+  h->order = c->shape_order;
+  h->fp64 = c->precision == BFPIC_FP64;
+  h->dz = c->dz;
+  h->dx = c->dx;
+  h->dy = c->dim == 3 ? c->dy : 1.0;
+  h->dt = bfpic_yee_dt(c->dim, c->dz, c->dx, c->dy, c->cfl);
+  Geo& g = h->g;
+  g.nz = h->nz;
+  g.nx = h->nx;
+  g.ny = h->ny;
+  g.periodic_z = c->z_boundary == BFPIC_BC_PERIODIC;
+  g.plane = (int64_t)h->nx * h->ny;
+  g.rows = h->nz + 2 * kGuard + 1;
+  // tiles
+  const int o = h->order;
+  // must agree with TileGeom: LZ = T + 2 E + 1 + o + (o + 2), LX = T + 2 E + o + (o + 2)
+  if (h->dim == 2) {
+    h->TZ = kT2Z;
+    h->TX = kT2X;
+    h->TY = 1;
+    h->LZ = kT2Z + 2 * kExc + 2 * o + 3;
+    h->LX = kT2X + 2 * kExc + 2 * o + 2;
+    h->LY = 1;
+  } else {
+    h->TZ = h->TX = h->TY = kT3;
+    h->LZ = kT3 + 2 * kExc + 2 * o + 3;
+    h->LX = h->LY = kT3 + 2 * kExc + 2 * o + 2;
+  }
+  h->LV = h->LZ * h->LX * h->LY;
+  bool fit_x = h->nx % h->TX == 0 && h->LX <= h->nx && h->LX <= 2 * h->TX;
+  bool fit_y = h->dim == 2 || (h->ny % h->TY == 0 && h->LY <= h->ny && h->LY <= 2 * h->TY);
+  bool fit_z = !g.periodic_z || (h->nz % h->TZ == 0 && h->LZ <= h->nz && h->LZ <= 2 * h->TZ);
+  h->tiled = fit_x && fit_y && fit_z;
+  // key tile shape when the LDS path is off: whole transverse planes
+  if (!fit_x) h->TX = h->nx;
+  if (!fit_y) h->TY = h->ny;
+  if (g.periodic_z && h->nz % h->TZ != 0) h->TZ = h->nz;
+  h->ntx = h->nx / h->TX;
+  h->nty = h->ny / h->TY;
+  int lim = o + 1;
+  h->ntz_max = g.periodic_z ? h->nz / h->TZ : (int)cdiv(h->nz + 2 * lim + 6, h->TZ) + 2;
+  h->maxtiles = (int64_t)h->ntz_max * h->ntx * h->nty;
+  h->maxkeys = h->maxtiles * h->TZ * h->TX * h->TY;
+  size_t rs = h->fp64 ? 8 : 4;
+  h->lds_tiled = (size_t)9 * h->LV * rs;
+}
+
+struct Layout {
+  int64_t off[64];
+  int n = 0;
+  int64_t total = 0;
+  int64_t add(int64_t bytes) {
+    int64_t o = total;
+    off[n++] = o;
+    total += align256(bytes > 0 ? bytes : 1);
+    return o;
+  }
+};
+
+// Offsets of every buffer inside the workspace (same order in query and create).
+static int64_t plan(bfpic_ctx* h, int64_t cap, bfpic_ctx* fill, bfpic_sizes* sz) {
+  Layout L;
+  const int64_t rs = h->fp64 ? 8 : 4;
+  const int64_t grid = h->g.rows * h->g.plane;
+  auto P = [&](int64_t bytes) -> void* {
+    int64_t o = L.add(bytes);
+    return fill ? (void*)(fill->ws + o) : nullptr;
+  };
+  void* p;
+  for (int c = 0; c < 6; c++) {
+    p = P(grid * rs);
+    if (fill) fill->F[c] = p;
+    p = P(grid * rs);
+    if (fill) fill->Fs[c] = p;
+  }
+  for (int c = 0; c < 3; c++) {
+    p = P(grid * rs);
+    if (fill) fill->Jf[c] = p;
+    p = P(grid * rs);
+    if (fill) fill->Jo[c] = p;
+  }
+  int64_t fields = L.total;
+  for (int s = 0; s < 2; s++) {
+    p = P(cap * 4);
+    if (fill) fill->pid[s] = p;
+    for (int a = 0; a < 3; a++) {
+      p = P(a < h->dim ? cap * rs : 0);
+      if (fill) fill->pxi[s][a] = a < h->dim ? p : nullptr;
+    }
+    for (int a = 0; a < 3; a++) {
+      p = P(cap * rs);
+      if (fill) fill->pdu[s][a] = p;
+    }
+    p = P(cap * rs);
+    if (fill) fill->pw[s] = p;
+  }
+  int64_t parts = L.total - fields;
+  p = P(16 * 4);
+  if (fill) fill->counts = (int*)p;
+  p = P(4 * 4);
+  if (fill) fill->ovf_rows = (int*)p;
+  p = P((h->maxtiles + 1) * 4);
+  if (fill) fill->tile_start = (int*)p;
+  p = P(h->tiled ? h->maxtiles * 3 * (int64_t)h->LV * rs : 0);
+  if (fill) fill->scratch = p;
+  p = P(cap * 4);
+  if (fill) fill->key = (int*)p;
+  p = P(cap * 4);
+  if (fill) fill->rank = (int*)p;
+  p = P(cap * 4);
+  if (fill) fill->perm = (int*)p;
+  p = P((h->maxkeys + 1) * 4);
+  if (fill) fill->cnt = (int*)p;
+  p = P((h->maxkeys + 1) * 4);
+  if (fill) fill->off = (int*)p;
+  p = P((cdiv(h->maxkeys + 1, kScanBlock * kScanPer) + 1) * 4);
+  if (fill) fill->bsum = (int*)p;
+  p = P(grid * 8);
+  if (fill) fill->g64a = (double*)p;
+  p = P(grid * 8);
+  if (fill) fill->g64b = (double*)p;
+  p = P(4096 * 4 * 8);
+  if (fill) fill->partials = (double*)p;
+  p = P(16 * 8);
+  if (fill) fill->dout = (double*)p;
+  p = P(4 * 4);
+  if (fill) fill->nanflag = (int*)p;
+  p = P(4 * h->g.plane * rs);
+  if (fill) fill->mur_save = p;
+  if (sz) {
+    sz->workspace_bytes = L.total;
+    sz->field_bytes = fields;
+    sz->particle_bytes = parts;
+    sz->scratch_bytes = L.total - fields - parts;
+  }
+  return L.total;
+}
+
+// ---------------------------------------------------------------------------
+// Typed implementation
+// ---------------------------------------------------------------------------
+template <typename R, int DIM, int ORDER>
+struct Impl {
+  using TG2 = TileGeom<2, ORDER, kT2Z, kT2X, 1, kExc>;
+  using TG3 = TileGeom<3, ORDER, kT3, kT3, kT3, kExc>;
+  static constexpr int TZc = DIM == 2 ? kT2Z : kT3;
+  static constexpr int TXc = DIM == 2 ? kT2X : kT3;
+  static constexpr int TYc = DIM == 2 ? 1 : kT3;
+
+  static PSoA<R> soa(bfpic_ctx* h, int s) {
+    PSoA<R> S;
+    S.id = (int*)h->pid[s];
+    for (int a = 0; a < 3; a++) {
+      S.xi[a] = (R*)h->pxi[s][a];
+      S.du[a] = (R*)h->pdu[s][a];
+    }
+    S.w = (R*)h->pw[s];
+    return S;
+  }
+  static Fields<R> fields(bfpic_ctx* h) {
+    Fields<R> f;
+    for (int c = 0; c < 6; c++) f.F[c] = (R*)h->F[c];
+    return f;
+  }
+  static LatticeP lattice(bfpic_ctx* h) {
+    LatticeP L;
+    L.seed = h->cfg.seed;
+    L.ppc = h->cfg.ppc;
+    L.nx = h->nx;
+    L.nyy = h->ny;
+    L.load = h->cfg.load;
+    return L;
+  }
+  static Ovf<R> ovf(bfpic_ctx* h) {
+    Ovf<R> o;
+    for (int c = 0; c < 3; c++) o.J[c] = (R*)h->Jo[c];
+    o.rows = h->ovf_rows;
+    return o;
+  }
+  // D = n beta_b dt / dz + window, split into integer and fractional parts.
+  static Drift<R> drift(bfpic_ctx* h, int64_t n) {
+    double D = (double)n * h->sb + (double)h->window_cells;
+    double fl = std::floor(D);
+    double fr = D - fl;
+    Drift<R> d;
+    d.Dint = (int)fl;
+    if (sizeof(R) == 4) {
+      // quantise to 2^-24 so that birth offset - Dfrac is exact in FP32
+      double q = std::nearbyint(fr * 16777216.0) / 16777216.0;
+      if (q >= 1.0) {
+        q = 0.0;
+        d.Dint += 1;
+      }
+      d.Dfrac = (R)q;
+    } else {
+      d.Dfrac = (R)fr;
+    }
+    return d;
+  }
+  static double drift_cells(bfpic_ctx* h) {
+    return (double)h->step * h->sb + (double)h->window_cells;
+  }
+
+  static int create_columns(bfpic_ctx* h, int64_t k0, int64_t ncols) {
+    int64_t count = ncols * h->nx * h->ny * h->cfg.ppc;
+    if (count <= 0) return BFPIC_OK;
+    {
+      Timer t(h, 5);
+      k_create<R><<<(unsigned)cdiv(count, 256), 256, 0, h->stream>>>(
+          soa(h, h->cur), lattice(h), h->dens, (int)k0, count, h->counts);
+      k_bump_slots<<<1, 1, 0, h->stream>>>(h->counts, (int)count);
+    }
+    HIPCHK(h, hipGetLastError());
+    h->slots_bound += count;
+    h->tail_bound += count;
+    return BFPIC_OK;
+  }
+
+  static int refresh_bound(bfpic_ctx* h) {
+    int c[2];
+    HIPCHK(h, hipMemcpyAsync(c, h->counts, sizeof(c), hipMemcpyDeviceToHost, h->stream));
+    HIPCHK(h, hipStreamSynchronize(h->stream));
+    h->slots_bound = c[0];
+    h->tail_bound = c[0] - c[1];
+    return BFPIC_OK;
+  }
+
+  // Columns due at the current step: k - D < nz.
+  static int64_t due_columns(bfpic_ctx* h) {
+    if (!h->has_plasma || h->g.periodic_z) return 0;
+    double D = drift_cells(h);
+    int64_t k = h->next_col, m = 0;
+    while ((double)(k + m) - D < (double)h->nz) m++;
+    return m;
+  }
+
+  static int inject(bfpic_ctx* h) {
+    int64_t m = due_columns(h);
+    if (m == 0) return BFPIC_OK;
+    int64_t count = m * h->nx * h->ny * h->cfg.ppc;
+    if (h->slots_bound + count > h->cap) {
+      int rc = refresh_bound(h);
+      if (rc) return rc;
+      if (h->slots_bound + count > h->cap)
+        return fail(h, BFPIC_ERR_CAPACITY,
+                    "particle capacity " + std::to_string(h->cap) + " < " +
+                        std::to_string(h->slots_bound + count));
+    }
+    int rc = create_columns(h, h->next_col, m);
+    if (rc) return rc;
+    h->next_col += m;
+    return BFPIC_OK;
+  }
+
+  static int sort(bfpic_ctx* h) {
+    Timer t(h, 4);
+    const Geo& g = h->g;
+    int tzmin, ntz;
+    if (g.periodic_z) {
+      tzmin = 0;
+      ntz = h->nz / h->TZ;
+    } else {
+      double D = drift_cells(h);
+      int lim = h->order + 1;
+      tzmin = (int)std::floor((D - lim - 2.0) / h->TZ);
+      int tzmax = (int)std::floor((D + h->nz + lim + 2.0) / h->TZ);
+      ntz = tzmax - tzmin + 1;
+      if (ntz > h->ntz_max) return fail(h, BFPIC_ERR_STATE, "tile rows exceed plan");
+    }
+    SortK K;
+    K.TZ = h->TZ;
+    K.TX = h->TX;
+    K.TY = h->TY;
+    K.ntz = ntz;
+    K.ntx = h->ntx;
+    K.nty = h->nty;
+    K.zc0 = tzmin * h->TZ;
+    int64_t cpt = (int64_t)h->TZ * h->TX * h->TY;
+    int64_t nkeys = (int64_t)ntz * h->ntx * h->nty * cpt;
+    K.nkeys = (int)nkeys;
+    int64_t nb = std::max<int64_t>(1, cdiv(h->slots_bound, 256));
+    PSoA<R> src = soa(h, h->cur), dst = soa(h, 1 - h->cur);
+    HIPCHK(h, hipMemsetAsync(h->cnt, 0, (nkeys + 1) * 4, h->stream));
+    HIPCHK(h, hipMemcpyAsync(h->counts + 2, h->counts, 4, hipMemcpyDeviceToDevice, h->stream));
+    k_sort_keys<R, DIM><<<(unsigned)nb, 256, 0, h->stream>>>(src, lattice(h), g, K, h->counts,
+                                                             h->key, h->rank, h->cnt);
+    int64_t n = nkeys + 1;
+    int64_t nsb = cdiv(n, kScanBlock * kScanPer);
+    k_scan_blocks<<<(unsigned)nsb, kScanBlock, 0, h->stream>>>(h->cnt, h->off, h->bsum, n);
+    k_scan_sums<<<1, kScanBlock, 0, h->stream>>>(h->bsum, (int)nsb);
+    k_scan_add<<<(unsigned)cdiv(n, 256), 256, 0, h->stream>>>(h->off, h->bsum, n);
+    k_sort_scatter<<<(unsigned)nb, 256, 0, h->stream>>>(h->counts, h->key, h->rank, h->off,
+                                                        h->perm);
+    k_sort_cells<<<(unsigned)cdiv(nkeys, 256), 256, 0, h->stream>>>(h->off, src.id, h->perm,
+                                                                    (int)nkeys);
+    k_permute<R><<<(unsigned)nb, 256, 0, h->stream>>>(src, dst, h->perm, h->off + nkeys);
+    int ntiles = ntz * h->ntx * h->nty;
+    k_tile_starts<<<(unsigned)cdiv(ntiles + 1, 256), 256, 0, h->stream>>>(
+        h->off, h->tile_start, ntiles, (int)cpt, h->counts, (int)nkeys);
+    HIPCHK(h, hipGetLastError());
+    h->cur = 1 - h->cur;
+    h->ntz = ntz;
+    h->zc0 = K.zc0;
+    h->tail_bound = 0;
+    h->last_sort_nkeys = nkeys;
+    h->last_sort_tzmin = tzmin;
+    h->last_sort_ntz = ntz;
+    h->have_sort = true;
+    return BFPIC_OK;
+  }
+
+  static StepK<R> step_consts(bfpic_ctx* h) {
+    StepK<R> P;
+    P.g = h->g;
+    P.L = lattice(h);
+    P.push.ub = (R)h->u_b;
+    P.push.gb = (R)h->gamma_b;
+    P.push.gb2 = (R)(h->gamma_b * h->gamma_b);
+    P.push.qdt2 = (R)(-0.5 * h->dt);
+    P.D0 = drift(h, h->step);
+    P.D1 = drift(h, h->step + 1);
+    P.dtd[0] = (R)(h->dt / h->dz);
+    P.dtd[1] = (R)(h->dt / h->dx);
+    P.dtd[2] = (R)(h->dt / h->dy);
+    if (DIM == 2) {
+      P.kj[0] = (R)(1.0 / (h->dx * h->dt));
+      P.kj[1] = (R)(1.0 / (h->dz * h->dt));
+      P.kj[2] = (R)0;
+    } else {
+      P.kj[0] = (R)(1.0 / (h->dx * h->dy * h->dt));
+      P.kj[1] = (R)(1.0 / (h->dz * h->dy * h->dt));
+      P.kj[2] = (R)(1.0 / (h->dz * h->dx * h->dt));
+    }
+    P.ky2d = (R)(1.0 / (h->dz * h->dx));
+    P.ion_moves = h->sb != 0.0;
+    P.remove = !h->g.periodic_z;
+    P.lim = ORDER + 1;
+    return P;
+  }
+
+  static FoldK<R> fold_consts(bfpic_ctx* h, const StepK<R>& P) {
+    FoldK<R> K;
+    K.scratch = (const R*)h->scratch;
+    K.ntz = h->ntz;
+    K.ntx = h->ntx;
+    K.nty = h->nty;
+    K.ntiles = h->tiled ? h->ntz * h->ntx * h->nty : 0;
+    K.gz0 = h->zc0 - P.D0.Dint - 1 - kExc - ORDER;
+    K.gx0 = -kExc - ORDER;
+    K.gy0 = DIM == 3 ? -kExc - ORDER : 0;
+    K.TZ = h->TZ;
+    K.TX = h->TX;
+    K.TY = h->TY;
+    K.LZ = h->LZ;
+    K.LX = h->LX;
+    K.LY = h->LY;
+    K.LV = h->LV;
+    K.o = ovf(h);
+    return K;
+  }
+
+  static FiltK filt(bfpic_ctx* h) {
+    FiltK f;
+    f.passes = h->cfg.filter_passes;
+    f.comp = h->cfg.filter_compensate ? 1 : 0;
+    f.H = f.passes + (f.comp && f.passes > 0 ? 1 : 0);
+    double N = (double)f.passes;
+    f.a_c = (float)(-0.25 * N);
+    f.b_c = (float)(1.0 + 0.5 * N);
+    return f;
+  }
+
+  static int one_step(bfpic_ctx* h) {
+    int rc = inject(h);
+    if (rc) return rc;
+    bool sort_due = h->cfg.sort_interval > 0 && h->step > 0 &&
+                    h->step % h->cfg.sort_interval == 0;
+    if (sort_due) {
+      rc = sort(h);
+      if (rc) return rc;
+    }
+    const Geo& g = h->g;
+    StepK<R> P = step_consts(h);
+    Fields<R> F = fields(h);
+    PSoA<R> S = soa(h, h->cur);
+    Ovf<R> O = ovf(h);
+    if (h->tiled && h->ntz > 0) {
+      Timer t(h, 0);
+      TileK T;
+      T.start = h->tile_start;
+      T.ntiles = h->ntz * h->ntx * h->nty;
+      T.ntx = h->ntx;
+      T.nty = h->nty;
+      T.zc0 = h->zc0;
+      if (DIM == 2)
+        k_gpd_tiled<R, 2, ORDER, kT2Z, kT2X, 1, kExc>
+            <<<T.ntiles, 256, h->lds_tiled, h->stream>>>(P, F, S, O, T, (R*)h->scratch);
+      else
+        k_gpd_tiled<R, 3, ORDER, kT3, kT3, kT3, kExc>
+            <<<T.ntiles, 256, h->lds_tiled, h->stream>>>(P, F, S, O, T, (R*)h->scratch);
+      HIPCHK(h, hipGetLastError());
+    }
+    int64_t nglob = h->tiled && h->ntz > 0 ? h->tail_bound : h->slots_bound;
+    if (nglob > 0) {
+      Timer t(h, 1);
+      k_gpd_global<R, DIM, ORDER><<<(unsigned)cdiv(nglob, 256), 256, 0, h->stream>>>(
+          P, F, S, O, h->counts, h->tiled && h->ntz > 0 ? 1 : 0);
+      HIPCHK(h, hipGetLastError());
+    }
+    {
+      Timer t(h, 2);
+      FoldK<R> K = fold_consts(h, P);
+      FiltK fk = filt(h);
+      Fields<R> Jf;
+      for (int c = 0; c < 3; c++) Jf.F[c] = (R*)h->Jf[c];
+      for (int c = 3; c < 6; c++) Jf.F[c] = nullptr;
+      if (DIM == 2) {
+        int nbz = (int)cdiv(h->nz + 1, kF2Z), nbx = (int)cdiv(h->nx, kF2X);
+        size_t lds = 2 * sizeof(R) * (kF2Z + 2 * fk.H) * (kF2X + 2 * fk.H);
+        k_fold_filter<R, 2, kF2Z, kF2X, 1><<<nbz * nbx, 256, lds, h->stream>>>(g, K, fk, Jf, nbz,
+                                                                             nbx, 1);
+      } else {
+        int nbz = (int)cdiv(h->nz + 1, kF3), nbx = (int)cdiv(h->nx, kF3),
+            nby = (int)cdiv(h->ny, kF3);
+        size_t lds = 2 * sizeof(R) * (size_t)(kF3 + 2 * fk.H) * (kF3 + 2 * fk.H) * (kF3 + 2 * fk.H);
+        k_fold_filter<R, 3, kF3, kF3, kF3><<<nbz * nbx * nby, 256, lds, h->stream>>>(
+            g, K, fk, Jf, nbz, nbx, nby);
+      }
+      k_ovf_clear<R><<<1024, 256, 0, h->stream>>>(g, O);
+      k_ovf_reset<<<1, 1, 0, h->stream>>>(h->ovf_rows);
+      HIPCHK(h, hipGetLastError());
+    }
+    {
+      Timer t(h, 3);
+      YeeK<R> Y;
+      for (int c = 0; c < 3; c++) {
+        Y.E[c] = (R*)h->F[c];
+        Y.B[c] = (R*)h->F[3 + c];
+        Y.J[c] = (const R*)h->Jf[c];
+      }
+      Y.idz = (R)(1.0 / h->dz);
+      Y.idx = (R)(1.0 / h->dx);
+      Y.idy = (R)(1.0 / h->dy);
+      Y.mur = (R)((h->dt - h->dz) / (h->dt + h->dz));
+      Y.save = (R*)h->mur_save;
+      int64_t nrow = g.periodic_z ? h->nz : h->nz + 1;
+      unsigned nb = (unsigned)cdiv(nrow * g.plane, 256);
+      Y.h = (R)(0.5 * h->dt);
+      k_yee_b<R, DIM><<<nb, 256, 0, h->stream>>>(g, Y);
+      Y.h = (R)h->dt;
+      k_yee_e<R, DIM><<<nb, 256, 0, h->stream>>>(g, Y);
+      if (!g.periodic_z) k_mur<R><<<(unsigned)cdiv(g.plane, 256), 256, 0, h->stream>>>(g, Y);
+      Y.h = (R)(0.5 * h->dt);
+      k_yee_b<R, DIM><<<nb, 256, 0, h->stream>>>(g, Y);
+      HIPCHK(h, hipGetLastError());
+    }
+    h->step++;
+    if (h->cfg.auto_window && !g.periodic_z) {
+      double t = (double)h->step * h->dt;
+      double due = std::floor((h->cfg.beta_window * t) / h->dz) - (double)h->window_cells;
+      if (due != 0.0) {
+        rc = shift(h, (int)due);
+        if (rc) return rc;
+      }
+    }
+    return BFPIC_OK;
+  }
+
+  static int steps(bfpic_ctx* h, int n) {
+    for (int s = 0; s < n; s++) {
+      int rc = one_step(h);
+      if (rc) return rc;
+    }
+    return BFPIC_OK;
+  }
+
+  static int shift(bfpic_ctx* h, int n) {
+    if (n == 0) return BFPIC_OK;
+    Timer t(h, 6);
+    unsigned nb = (unsigned)cdiv(h->g.rows * h->g.plane, 256);
+    for (int c = 0; c < 6; c++) {
+      int half = c == 2 || c == 3 || c == 4;
+      k_shift<R><<<nb, 256, 0, h->stream>>>(h->g, (const R*)h->F[c], (R*)h->Fs[c], n, half);
+      std::swap(h->F[c], h->Fs[c]);
+    }
+    HIPCHK(h, hipGetLastError());
+    h->window_cells += n;
+    return BFPIC_OK;
+  }
+
+  static int init(bfpic_ctx* h, double gamma_boost, const bfpic_density* d,
+                  const bfpic_laser* laser) {
+    const Geo& g = h->g;
+    h->gamma_b = gamma_boost;
+    h->beta_b = bfpic_beta(gamma_boost);
+    h->u_b = bfpic_drift_u(gamma_boost);
+    h->sb = (h->beta_b * h->dt) / h->dz;
+    h->step = 0;
+    h->window_cells = 0;
+    h->next_col = 0;
+    h->has_plasma = d != nullptr;
+    h->slots_bound = 0;
+    h->tail_bound = 0;
+    h->have_sort = false;
+    const int64_t rs = h->fp64 ? 8 : 4;
+    const int64_t grid = g.rows * g.plane;
+    for (int c = 0; c < 6; c++) HIPCHK(h, hipMemsetAsync(h->F[c], 0, grid * rs, h->stream));
+    for (int c = 0; c < 3; c++) {
+      HIPCHK(h, hipMemsetAsync(h->Jf[c], 0, grid * rs, h->stream));
+      HIPCHK(h, hipMemsetAsync(h->Jo[c], 0, grid * rs, h->stream));
+    }
+    HIPCHK(h, hipMemsetAsync(h->counts, 0, 16 * 4, h->stream));
+    k_ovf_reset<<<1, 1, 0, h->stream>>>(h->ovf_rows);
+    if (laser) {
+      LaserK K;
+      K.a0 = laser->a0;
+      K.w0 = laser->w0;
+      K.L = laser->L;
+      K.zc = laser->z_center;
+      K.zf = laser->z_focus;
+      K.phase = laser->phase;
+      K.collimated = laser->collimated;
+      K.iz = laser->images_z;
+      K.ix = laser->images_x;
+      K.iy = laser->images_y;
+      K.dim = DIM;
+      K.gamma_b = gamma_boost;
+      K.gomb = 1.0 / (gamma_boost * (1.0 + h->beta_b));  // gamma (1 - beta)
+      K.gbeta = gamma_boost * h->beta_b;
+      K.Lz = h->nz * h->dz;
+      K.Lx = h->nx * h->dx;
+      K.Ly = h->ny * h->dy;
+      K.xa = 0.5 * h->nx * h->dx;
+      K.ya = DIM == 3 ? 0.5 * h->ny * h->dy : 0.0;
+      K.dz = h->dz;
+      K.dx = h->dx;
+      K.dy = h->dy;
+      HIPCHK(h, hipMemsetAsync(h->g64a, 0, grid * 8, h->stream));
+      HIPCHK(h, hipMemsetAsync(h->g64b, 0, grid * 8, h->stream));
+      int64_t nrow = g.periodic_z ? h->nz : h->nz + 1;
+      unsigned nb = (unsigned)cdiv(nrow * g.plane, 256);
+      k_laser_a<R><<<nb, 256, 0, h->stream>>>(g, K, (R*)h->F[1], h->g64a, h->g64b);
+      k_laser_b<R><<<nb, 256, 0, h->stream>>>(g, h->g64a, h->dz, h->dx, (R*)h->F[3], (R*)h->F[5]);
+      if (DIM == 3)
+        k_laser_ez<R><<<(unsigned)cdiv(g.plane, 256), 256, 0, h->stream>>>(g, h->g64b, h->dz,
+                                                                         h->dy, (R*)h->F[2]);
+      HIPCHK(h, hipGetLastError());
+    }
+    if (d) {
+      DensityK& D = h->dens;
+      D.n_uniform = d->n_uniform;
+      D.nknots = d->nknots >= 2 ? d->nknots : 0;
+      if (D.nknots > 32) return fail(h, BFPIC_ERR_ARG, "at most 32 density knots");
+      for (int m = 0; m < D.nknots; m++) {
+        D.kz[m] = d->z_lab[m];
+        D.kn[m] = d->n[m];
+      }
+      D.gamma_b = gamma_boost;
+      D.dz = h->dz;
+      D.dV_over_ppc = h->dz * h->dx * (DIM == 3 ? h->dy : 1.0) / h->cfg.ppc;
+      for (int a = 0; a < 3; a++) D.du0[a] = d->du[a];
+      int64_t count = (int64_t)h->nz * h->nx * h->ny * h->cfg.ppc;
+      if (count > h->cap)
+        return fail(h, BFPIC_ERR_CAPACITY, "initial particles " + std::to_string(count) +
+                                               " exceed capacity " + std::to_string(h->cap));
+      int rc = create_columns(h, 0, h->nz);
+      if (rc) return rc;
+      h->next_col = h->nz;
+      rc = sort(h);
+      if (rc) return rc;
+    }
+    h->inited = true;
+    return BFPIC_OK;
+  }
+
+  static int diag(bfpic_ctx* h, bfpic_diag* o, double* lineout) {
+    const Geo& g = h->g;
+    Fields<R> F = fields(h);
+    PSoA<R> S = soa(h, h->cur);
+    double* pf = h->partials;
+    double* pp = h->partials + 2 * 1024;
+    double* pg = h->partials + 6 * 1024;
+    HIPCHK(h, hipMemsetAsync(h->nanflag, 0, 4, h->stream));
+    const int nbf = 512, nbp = 512, nbg = 512;
+    k_diag_fields<R><<<nbf, kDiagBlock, 0, h->stream>>>(g, F, pf, h->nanflag);
+    k_diag_particles<R, DIM><<<nbp, kDiagBlock, 0, h->stream>>>(S, h->counts, h->u_b, h->gamma_b,
+                                                                pp, h->nanflag);
+    const int64_t grid = g.rows * g.plane;
+    HIPCHK(h, hipMemsetAsync(h->g64a, 0, grid * 8, h->stream));
+    HIPCHK(h, hipMemsetAsync(h->g64b, 0, grid * 8, h->stream));
+    double dV = h->dz * h->dx * (DIM == 3 ? h->dy : 1.0);
+    if (h->slots_bound > 0)
+      k_rho<R, DIM, ORDER><<<(unsigned)cdiv(h->slots_bound, 256), 256, 0, h->stream>>>(
+          S, lattice(h), drift(h, h->step), g, h->counts, 1.0 / dV, h->g64a);
+    FiltK fk = filt(h);
+    if (DIM == 2) {
+      int nbz = (int)cdiv(h->nz + 1, kF2Z), nbx = (int)cdiv(h->nx, kF2X);
+      size_t lds = 2 * 8 * (size_t)(kF2Z + 2 * fk.H) * (kF2X + 2 * fk.H);
+      k_filter_grid<2, kF2Z, kF2X, 1><<<nbz * nbx, 256, lds, h->stream>>>(g, fk, h->g64a,
+                                                                          h->g64b, nbz, nbx, 1);
+    } else {
+      int nbz = (int)cdiv(h->nz + 1, kF3), nbx = (int)cdiv(h->nx, kF3), nby = (int)cdiv(h->ny, kF3);
+      size_t lds = 2 * 8 * (size_t)(kF3 + 2 * fk.H) * (kF3 + 2 * fk.H) * (kF3 + 2 * fk.H);
+      k_filter_grid<3, kF3, kF3, kF3><<<nbz * nbx * nby, 256, lds, h->stream>>>(
+          g, fk, h->g64a, h->g64b, nbz, nbx, nby);
+    }
+    int lo, hi;
+    if (g.periodic_z) {
+      lo = 0;
+      hi = h->nz - 1;
+    } else {
+      int b = h->cfg.filter_passes + h->order + 4;
+      lo = b;
+      hi = h->nz - b;
+    }
+    if (hi >= lo)
+      k_gauss<R, DIM><<<nbg, kDiagBlock, 0, h->stream>>>(g, F, h->g64b, 1.0 / h->dz, 1.0 / h->dx,
+                                                         1.0 / h->dy, lo, hi, pg);
+    else
+      HIPCHK(h, hipMemsetAsync(pg, 0, nbg * 8, h->stream));
+    k_diag_final<R><<<1, kDiagBlock, 0, h->stream>>>(g, (const R*)h->F[2], pf, nbf, pp, nbp, pg,
+                                                     nbg, h->dout, lineout);
+    HIPCHK(h, hipGetLastError());
+    double out[8];
+    int nanf = 0;
+    HIPCHK(h, hipMemcpyAsync(out, h->dout, sizeof(out), hipMemcpyDeviceToHost, h->stream));
+    HIPCHK(h, hipMemcpyAsync(&nanf, h->nanflag, 4, hipMemcpyDeviceToHost, h->stream));
+    HIPCHK(h, hipStreamSynchronize(h->stream));
+    o->step = h->step;
+    o->t = (double)h->step * h->dt;
+    o->window_cells = (double)h->window_cells;
+    o->drift_cells = drift_cells(h);
+    o->ue = 0.5 * out[0] * dV;
+    o->ub = 0.5 * out[1] * dV;
+    o->ukin = out[2];
+    o->ukin_drift = out[3];
+    o->charge = out[4];
+    o->live = (int64_t)std::llround(out[5]);
+    o->gauss_res = out[6];
+    o->wake_amp = out[7];
+    o->nan_flag = nanf || !std::isfinite(out[0]) || !std::isfinite(out[1]);
+    return BFPIC_OK;
+  }
+
+  static int get_field(bfpic_ctx* h, int comp, double* out) {
+    const Geo& g = h->g;
+    const R* A;
+    int half;
+    if (comp < 6) {
+      A = (const R*)h->F[comp];
+      half = comp == 2 || comp == 3 || comp == 4;
+    } else {
+      A = (const R*)h->Jf[comp - 6];
+      half = comp == 8;
+    }
+    k_get_field<R><<<(unsigned)cdiv((h->nz + 1) * g.plane, 256), 256, 0, h->stream>>>(g, A, out,
+                                                                                     half);
+    HIPCHK(h, hipGetLastError());
+    return BFPIC_OK;
+  }
+
+  static int set_field(bfpic_ctx* h, int comp, const double* in) {
+    const Geo& g = h->g;
+    int half = comp == 2 || comp == 3 || comp == 4;
+    k_set_field<R><<<(unsigned)cdiv((h->nz + 1) * g.plane, 256), 256, 0, h->stream>>>(
+        g, (R*)h->F[comp], in, half);
+    HIPCHK(h, hipGetLastError());
+    return BFPIC_OK;
+  }
+
+  static int export_particles(bfpic_ctx* h, double* z, double* x, double* y, double* ux,
+                              double* uy, double* uz, double* w, int* id) {
+    if (h->slots_bound == 0) return BFPIC_OK;
+    k_export<R, DIM><<<(unsigned)cdiv(h->slots_bound, 256), 256, 0, h->stream>>>(
+        soa(h, h->cur), lattice(h), drift(h, h->step), h->u_b, h->counts, z, x, y, ux, uy, uz, w,
+        id);
+    HIPCHK(h, hipGetLastError());
+    return BFPIC_OK;
+  }
+};
+
+// Dispatch on (precision, dim, order).
+#define BFPIC_DISPATCH(h, EXPR)                                                    \
+  do {                                                                             \
+    if ((h)->fp64) {                                                               \
+      if ((h)->dim == 2) {                                                         \
+        if ((h)->order == 1) { using I = Impl<double, 2, 1>; return EXPR; }        \
+        else { using I = Impl<double, 2, 2>; return EXPR; }                        \
+      } else {                                                                     \
+        if ((h)->order == 1) { using I = Impl<double, 3, 1>; return EXPR; }        \
+        else { using I = Impl<double, 3, 2>; return EXPR; }                        \
+      }                                                                            \
+    } else {                                                                       \
+      if ((h)->dim == 2) {                                                         \
+        if ((h)->order == 1) { using I = Impl<float, 2, 1>; return EXPR; }         \
+        else { using I = Impl<float, 2, 2>; return EXPR; }                         \
+      } else {                                                                     \
+        if ((h)->order == 1) { using I = Impl<float, 3, 1>; return EXPR; }         \
+        else { using I = Impl<float, 3, 2>; return EXPR; }                         \
+      }                                                                            \
+    }                                                                              \
+  } while (0)
+
+// ---------------------------------------------------------------------------
+// C ABI
+// ---------------------------------------------------------------------------
+extern "C" int bfpic_query_sizes(const bfpic_config* cfg, int64_t cap, bfpic_sizes* out) {
+  std::string why;
+  if (!out || cap < 1 || !check_cfg(cfg, why)) return BFPIC_ERR_ARG;
+  if (cfg->deterministic) return BFPIC_ERR_UNSUPPORTED;
+  bfpic_ctx tmp;
+  derive(&tmp, cfg);
+  plan(&tmp, cap, nullptr, out);
+  return BFPIC_OK;
+}
+
+extern "C" int bfpic_create(const bfpic_config* cfg, int64_t cap, void* workspace,
+                            int64_t workspace_bytes, void* stream, bfpic_ctx** out) {
+  if (!out) return BFPIC_ERR_ARG;
+  *out = nullptr;
+  std::string why;
+  if (cap < 1 || cap > 0x7fffffffLL || !check_cfg(cfg, why) || !workspace)
+    return BFPIC_ERR_ARG;
+  if (cfg->deterministic) return BFPIC_ERR_UNSUPPORTED;
+  bfpic_ctx* h = new bfpic_ctx();
+  derive(h, cfg);
+  h->cap = cap;
+  bfpic_sizes sz;
+  plan(h, cap, nullptr, &sz);
+  if (workspace_bytes < sz.workspace_bytes || ((uintptr_t)workspace & 255)) {
+    delete h;
+    return BFPIC_ERR_ARG;
+  }
+  h->ws = (uint8_t*)workspace;
+  h->ws_bytes = workspace_bytes;
+  plan(h, cap, h, nullptr);
+  h->stream = (hipStream_t)stream;
+  int dev = 0, lds = 65536;
+  if (hipGetDevice(&dev) == hipSuccess &&
+      hipDeviceGetAttribute(&lds, hipDeviceAttributeMaxSharedMemoryPerBlock, dev) == hipSuccess)
+    h->lds_limit = (size_t)lds;
+  if (h->lds_tiled > h->lds_limit) h->tiled = false;
+  // the filter kernels may need more than 64 KB of LDS (3D, FP64, many passes)
+  {
+    int lim = (int)h->lds_limit;
+    hipFuncSetAttribute((const void*)k_fold_filter<float, 2, kF2Z, kF2X, 1>,
+                        hipFuncAttributeMaxDynamicSharedMemorySize, lim);
+    hipFuncSetAttribute((const void*)k_fold_filter<double, 2, kF2Z, kF2X, 1>,
+                        hipFuncAttributeMaxDynamicSharedMemorySize, lim);
+    hipFuncSetAttribute((const void*)k_fold_filter<float, 3, kF3, kF3, kF3>,
+                        hipFuncAttributeMaxDynamicSharedMemorySize, lim);
+    hipFuncSetAttribute((const void*)k_fold_filter<double, 3, kF3, kF3, kF3>,
+                        hipFuncAttributeMaxDynamicSharedMemorySize, lim);
+    hipFuncSetAttribute((const void*)k_filter_grid<2, kF2Z, kF2X, 1>,
+                        hipFuncAttributeMaxDynamicSharedMemorySize, lim);
+    hipFuncSetAttribute((const void*)k_filter_grid<3, kF3, kF3, kF3>,
+                        hipFuncAttributeMaxDynamicSharedMemorySize, lim);
+    FiltK fk;
+    fk.passes = cfg->filter_passes;
+    fk.comp = cfg->filter_compensate;
+    int H = fk.passes + (fk.comp && fk.passes > 0 ? 1 : 0);
+    size_t need = h->dim == 2 ? 2 * 8 * (size_t)(kF2Z + 2 * H) * (kF2X + 2 * H)
+                              : 2 * 8 * (size_t)(kF3 + 2 * H) * (kF3 + 2 * H) * (kF3 + 2 * H);
+    if (need > h->lds_limit) {
+      delete h;
+      return BFPIC_ERR_UNSUPPORTED;
+    }
+  }
+  if (h->tiled && h->lds_tiled > 65536) {
+    // opt in to large dynamic LDS for the tiled kernels
+    if (h->fp64) {
+      if (h->dim == 3 && h->order == 2)
+        hipFuncSetAttribute((const void*)k_gpd_tiled<double, 3, 2, kT3, kT3, kT3, kExc>,
+                            hipFuncAttributeMaxDynamicSharedMemorySize, (int)h->lds_tiled);
+      if (h->dim == 3 && h->order == 1)
+        hipFuncSetAttribute((const void*)k_gpd_tiled<double, 3, 1, kT3, kT3, kT3, kExc>,
+                            hipFuncAttributeMaxDynamicSharedMemorySize, (int)h->lds_tiled);
+    } else {
+      if (h->dim == 3 && h->order == 2)
+        hipFuncSetAttribute((const void*)k_gpd_tiled<float, 3, 2, kT3, kT3, kT3, kExc>,
+                            hipFuncAttributeMaxDynamicSharedMemorySize, (int)h->lds_tiled);
+      if (h->dim == 3 && h->order == 1)
+        hipFuncSetAttribute((const void*)k_gpd_tiled<float, 3, 1, kT3, kT3, kT3, kExc>,
+                            hipFuncAttributeMaxDynamicSharedMemorySize, (int)h->lds_tiled);
+    }
+  }
+  *out = h;
+  return BFPIC_OK;
+}
+
+extern "C" void bfpic_destroy(bfpic_ctx* h) {
+  if (!h) return;
+  for (int c = 0; c < kNumTimers; c++)
+    for (auto& pr : h->ev[c]) {
+      hipEventDestroy(pr.first);
+      hipEventDestroy(pr.second);
+    }
+  for (auto e : h->pool) hipEventDestroy(e);
+  delete h;
+}
+
+extern "C" const char* bfpic_last_error(const bfpic_ctx* h) { return h ? h->err.c_str() : "null"; }
+
+extern "C" int init_boosted_plasma(bfpic_ctx* h, double gamma_boost, const bfpic_density* n_e,
+                                   const bfpic_laser* laser) {
+  if (!h) return BFPIC_ERR_ARG;
+  if (!(gamma_boost >= 1.0)) return fail(h, BFPIC_ERR_ARG, "gamma_boost must be >= 1");
+  if (n_e && n_e->nknots == 1) return fail(h, BFPIC_ERR_ARG, "nknots must be 0 or >= 2");
+  BFPIC_DISPATCH(h, I::init(h, gamma_boost, n_e, laser));
+}
+
+extern "C" int pic_step(bfpic_ctx* h, int32_t nsteps) {
+  if (!h) return BFPIC_ERR_ARG;
+  if (!h->inited) return fail(h, BFPIC_ERR_STATE, "pic_step before init_boosted_plasma");
+  if (nsteps < 0) return fail(h, BFPIC_ERR_ARG, "nsteps < 0");
+  BFPIC_DISPATCH(h, I::steps(h, nsteps));
+}
+
+extern "C" int moving_window_shift(bfpic_ctx* h, int32_t n) {
+  if (!h) return BFPIC_ERR_ARG;
+  if (!h->inited) return fail(h, BFPIC_ERR_STATE, "window shift before init");
+  if (h->g.periodic_z && n != 0) return fail(h, BFPIC_ERR_ARG, "periodic z has no window");
+  BFPIC_DISPATCH(h, I::shift(h, n));
+}
+
+extern "C" int bfpic_window_due(bfpic_ctx* h, int32_t* n) {
+  if (!h || !n) return BFPIC_ERR_ARG;
+  double t = (double)h->step * h->dt;
+  *n = (int32_t)(std::floor((h->cfg.beta_window * t) / h->dz) - (double)h->window_cells);
+  return BFPIC_OK;
+}
+
+extern "C" int diagnostics(bfpic_ctx* h, uint32_t mask, bfpic_diag* out, double* lineout) {
+  (void)mask;
+  if (!h || !out) return BFPIC_ERR_ARG;
+  if (!h->inited) return fail(h, BFPIC_ERR_STATE, "diagnostics before init");
+  BFPIC_DISPATCH(h, I::diag(h, out, lineout));
+}
+
+extern "C" int bfpic_get_field(bfpic_ctx* h, int32_t comp, double* out) {
+  if (!h || !out || comp < 0 || comp > 8) return BFPIC_ERR_ARG;
+  BFPIC_DISPATCH(h, I::get_field(h, comp, out));
+}
+
+extern "C" int bfpic_set_field(bfpic_ctx* h, int32_t comp, const double* in) {
+  if (!h || !in || comp < 0 || comp > 5) return BFPIC_ERR_ARG;
+  BFPIC_DISPATCH(h, I::set_field(h, comp, in));
+}
+
+extern "C" int bfpic_num_slots(bfpic_ctx* h, int64_t* n) {
+  if (!h || !n) return BFPIC_ERR_ARG;
+  int c = 0;
+  HIPCHK(h, hipMemcpyAsync(&c, h->counts, 4, hipMemcpyDeviceToHost, h->stream));
+  HIPCHK(h, hipStreamSynchronize(h->stream));
+  *n = c;
+  return BFPIC_OK;
+}
+
+extern "C" int bfpic_get_particles(bfpic_ctx* h, double* z, double* x, double* y, double* ux,
+                                   double* uy, double* uz, double* w, int32_t* id) {
+  if (!h || !z || !x || !y || !ux || !uy || !uz || !w || !id) return BFPIC_ERR_ARG;
+  BFPIC_DISPATCH(h, I::export_particles(h, z, x, y, ux, uy, uz, w, id));
+}
+
+extern "C" int bfpic_sort(bfpic_ctx* h) {
+  if (!h) return BFPIC_ERR_ARG;
+  if (!h->inited) return fail(h, BFPIC_ERR_STATE, "sort before init");
+  BFPIC_DISPATCH(h, I::sort(h));
+}
+
+extern "C" int bfpic_last_sort(bfpic_ctx* h, int32_t* key_dev, int32_t* id_dev, int32_t* perm_dev,
+                               int64_t* n, int64_t* n_live, int64_t* tz_min, int32_t* ntz) {
+  if (!h || !key_dev || !id_dev || !perm_dev || !n || !n_live || !tz_min || !ntz)
+    return BFPIC_ERR_ARG;
+  if (!h->have_sort) return fail(h, BFPIC_ERR_STATE, "no sort yet");
+  int c[3];
+  HIPCHK(h, hipMemcpyAsync(c, h->counts, sizeof(c), hipMemcpyDeviceToHost, h->stream));
+  HIPCHK(h, hipStreamSynchronize(h->stream));
+  int nsrc = c[2];
+  HIPCHK(h, hipMemcpyAsync(key_dev, h->key, (size_t)nsrc * 4, hipMemcpyDeviceToDevice, h->stream));
+  HIPCHK(h, hipMemcpyAsync(id_dev, h->pid[1 - h->cur], (size_t)nsrc * 4, hipMemcpyDeviceToDevice,
+                           h->stream));
+  int nl = 0;
+  HIPCHK(h, hipMemcpyAsync(&nl, h->off + h->last_sort_nkeys, 4, hipMemcpyDeviceToHost, h->stream));
+  HIPCHK(h, hipStreamSynchronize(h->stream));
+  HIPCHK(h, hipMemcpyAsync(perm_dev, h->perm, (size_t)nl * 4, hipMemcpyDeviceToDevice, h->stream));
+  HIPCHK(h, hipStreamSynchronize(h->stream));
+  *n = nsrc;
+  *n_live = nl;
+  *tz_min = h->last_sort_tzmin;
+  *ntz = h->last_sort_ntz;
+  return BFPIC_OK;
+}
+
+extern "C" int bfpic_tile_shape(const bfpic_ctx* h, int32_t* tz, int32_t* tx, int32_t* ty) {
+  if (!h || !tz || !tx || !ty) return BFPIC_ERR_ARG;
+  *tz = h->TZ;
+  *tx = h->TX;
+  *ty = h->TY;
+  return BFPIC_OK;
+}
+
+extern "C" int bfpic_kernel_timing(bfpic_ctx* h, int32_t enable) {
+  if (!h) return BFPIC_ERR_ARG;
+  HIPCHK(h, hipStreamSynchronize(h->stream));
+  for (int c = 0; c < kNumTimers; c++) {
+    for (auto& pr : h->ev[c]) {
+      h->pool.push_back(pr.first);
+      h->pool.push_back(pr.second);
+    }
+    h->ev[c].clear();
+  }
+  h->timing = enable != 0;
+  return BFPIC_OK;
+}
+
+extern "C" int bfpic_kernel_time(bfpic_ctx* h, int32_t cls, double* total_ms, int64_t* launches) {
+  if (!h || cls < 0 || cls >= kNumTimers || !total_ms || !launches) return BFPIC_ERR_ARG;
+  HIPCHK(h, hipStreamSynchronize(h->stream));
+  double tot = 0.0;
+  for (auto& pr : h->ev[cls]) {
+    float ms = 0.f;
+    HIPCHK(h, hipEventElapsedTime(&ms, pr.first, pr.second));
+    tot += ms;
+  }
+  *total_ms = tot;
+  *launches = (int64_t)h->ev[cls].size();
+  return BFPIC_OK;
+}

@@ -1,0 +1,253 @@
+// device_common.hpp -- shared device-side definitions of the boosted-frame PIC
+// library: grid geometry and indexing, the counter-based generator, particle
+// position reconstruction, shape factors and the split-form Boris push.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace bfpic {
+
+constexpr int kGuard = 6;  // stored rows beyond each z end of the domain
+
+// Grid geometry.  Component arrays are [row][j][k] with row = i + kGuard,
+// i in [-kGuard, nz + kGuard]; k (y) fastest; ny = 1 in 2D.
+struct Geo {
+  int nz, nx, ny;
+  int periodic_z;
+  int64_t plane;  // nx * ny
+  int64_t rows;   // nz + 2 kGuard + 1
+};
+
+__device__ __forceinline__ int wrapi(int i, int n) {
+  int r = i % n;
+  return r < 0 ? r + n : r;
+}
+
+// Storage index of node (i, j, k) or -1 outside storage (open z only).
+__device__ __forceinline__ int64_t gidx(const Geo& g, int i, int j, int k) {
+  if (g.periodic_z) i = wrapi(i, g.nz);
+  else if (i < -kGuard || i > g.nz + kGuard) return -1;
+  j = wrapi(j, g.nx);
+  k = g.ny > 1 ? wrapi(k, g.ny) : 0;
+  return ((int64_t)(i + kGuard) * g.nx + j) * g.ny + k;
+}
+
+// Domain rows of a component: integer-z components own rows [0, nz] (both
+// boundary planes), half-z components [0, nz - 1]; periodic: [0, nz - 1].
+__device__ __forceinline__ int row_hi(const Geo& g, int half_z) {
+  return (g.periodic_z || half_z) ? g.nz - 1 : g.nz;
+}
+__device__ __forceinline__ bool in_domain(const Geo& g, int half_z, int i) {
+  return i >= 0 && i <= row_hi(g, half_z);
+}
+
+// ---------------------------------------------------------------------------
+// SplitMix64 (Steele, Lea, Flood 2014): output n of the generator started at
+// state `seed`.  In-cell offsets take its top 24 bits times 2^-24, exact in
+// both float and double.
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ uint64_t splitmix64(uint64_t seed, uint64_t n) {
+  uint64_t z = seed + n * 0x9E3779B97F4A7C15ULL;
+  z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ULL;
+  z = (z ^ (z >> 27)) * 0x94D049BB133111EBULL;
+  return z ^ (z >> 31);
+}
+
+// Particle identity: id = ((k * nyy + l) * nx + j) * ppc + s for lattice
+// column k, transverse cells (j, l) and slot s.  The generator counter of
+// axis a (0 z, 1 x, 2 y) is 4 id + a + 1.
+struct Birth {
+  int k, j, l;
+};
+
+struct LatticeP {
+  uint64_t seed;
+  int ppc, nx, nyy;
+  int load;  // 0 random, 1 centred
+};
+
+__device__ __forceinline__ Birth decode_id(const LatticeP& L, int id) {
+  Birth b;
+  int q = id / L.ppc;
+  b.j = q % L.nx;
+  q /= L.nx;
+  b.l = q % L.nyy;
+  b.k = q / L.nyy;
+  return b;
+}
+
+template <typename R>
+__device__ __forceinline__ R birth_offset(const LatticeP& L, int id, int axis) {
+  if (L.load) return (R)0.5;
+  uint64_t r = splitmix64(L.seed, 4ULL * (uint64_t)id + (uint64_t)axis + 1ULL);
+  return (R)(uint32_t)(r >> 40) * (R)(1.0 / 16777216.0);
+}
+
+// A particle position as an integer cell plus an offset in [0, 1).
+template <typename R>
+struct Pos {
+  int c[3];
+  R o[3];
+};
+
+// Renormalise cell + off (off may leave [0,1)).  If the offset rounds to 1
+// after the subtraction, move to the next cell with offset 0.
+template <typename R>
+__device__ __forceinline__ void renorm(int& c, R& o) {
+  R f = floor(o);
+  c += (int)f;
+  o -= f;
+  if (o >= (R)1) {
+    c += 1;
+    o = (R)0;
+  }
+}
+
+// Drift of the rigid ion lattice at a step: D = Dint + Dfrac, Dfrac in [0,1),
+// in cells along z (plasma drift n beta_b dt / dz plus window displacement).
+template <typename R>
+struct Drift {
+  int Dint;
+  R Dfrac;
+};
+
+// Ion partner position: its birth spot minus the drift (x, y never move).
+template <typename R, int DIM>
+__device__ __forceinline__ Pos<R> ion_pos(const LatticeP& L, int id, const Birth& b,
+                                          const Drift<R>& D) {
+  Pos<R> p;
+  p.c[0] = b.k - D.Dint;
+  p.o[0] = birth_offset<R>(L, id, 0) - D.Dfrac;  // exact: both multiples of 2^-24
+  if (p.o[0] < (R)0) {
+    p.o[0] += (R)1;
+    p.c[0] -= 1;
+  }
+  p.c[1] = b.j;
+  p.o[1] = birth_offset<R>(L, id, 1);
+  if (DIM == 3) {
+    p.c[2] = b.l;
+    p.o[2] = birth_offset<R>(L, id, 2);
+  } else {
+    p.c[2] = 0;
+    p.o[2] = (R)0;
+  }
+  return p;
+}
+
+// Electron position = ion partner + peculiar displacement xi (cells).
+template <typename R, int DIM>
+__device__ __forceinline__ Pos<R> add_xi(Pos<R> p, const R xi[3]) {
+#pragma unroll
+  for (int a = 0; a < DIM; a++) {
+    p.o[a] += xi[a];
+    renorm(p.c[a], p.o[a]);
+  }
+  return p;
+}
+
+// ---------------------------------------------------------------------------
+// Shape factors of order 1 (linear) and 2 (quadratic B-spline).  For a
+// position cell c + offset o, on the integer lattice (half = 0) or the
+// half-integer lattice (half = 1, node index m sits at m + 1/2), return the
+// first node b and weights w[0..ORDER] of nodes b..b+ORDER.
+// ---------------------------------------------------------------------------
+template <typename R, int ORDER>
+__device__ __forceinline__ int shape(int c, R o, int half, R w[ORDER + 1]) {
+  if (ORDER == 1) {
+    int b = c;
+    R f = o;
+    if (half) {
+      if (o >= (R)0.5) f = o - (R)0.5;
+      else {
+        b = c - 1;
+        f = o + (R)0.5;
+      }
+    }
+    w[0] = (R)1 - f;
+    w[1] = f;
+    return b;
+  } else {
+    int m;
+    R d;
+    if (half) {
+      m = c;
+      d = o - (R)0.5;
+    } else if (o >= (R)0.5) {
+      m = c + 1;
+      d = o - (R)1;
+    } else {
+      m = c;
+      d = o;
+    }
+    R a = (R)0.5 - d, e = (R)0.5 + d;
+    w[0] = (R)0.5 * a * a;
+    w[1] = (R)0.75 - d * d;
+    w[ORDER] = (R)0.5 * e * e;
+    return m - 1;
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Relativistic Boris push (Boris 1970) on the peculiar momentum du = u - ub z,
+// written so that no step subtracts two numbers of size gamma_b:
+//   gamma^2 = gb^2 + c,  c = 2 ub du_z + |du|^2,  gamma - gb = c / (gb + gamma)
+//   rotation terms (ub + du_z) t split into ub t + du_z t
+//   v_z - v_b = ((2 + gb (gamma - gb)) du_z - ub |du|^2) / ((gamma + gb) gamma gb)
+// ub, gb: drift momentum and its gamma (gb^2 = 1 + ub^2 in FP64, rounded once).
+// ---------------------------------------------------------------------------
+template <typename R>
+struct PushC {
+  R ub, gb, gb2;  // drift
+  R qdt2;         // q dt / 2 (q = -1)
+};
+
+template <typename R>
+__device__ __forceinline__ R gamma_minus_gb(const PushC<R>& P, R dux, R duy, R duz) {
+  R c = (R)2 * P.ub * duz + (dux * dux + duy * duy + duz * duz);
+  return c / (P.gb + sqrt(P.gb2 + c));
+}
+
+template <typename R>
+__device__ __forceinline__ void boris_split(const PushC<R>& P, const R E[3], const R B[3],
+                                            R du[3], R dv[3], R& gam) {
+  // vectors in (x, y, z) order
+  R mx = du[0] + P.qdt2 * E[0];
+  R my = du[1] + P.qdt2 * E[1];
+  R mz = du[2] + P.qdt2 * E[2];
+  R g = P.gb + gamma_minus_gb(P, mx, my, mz);
+  R f = P.qdt2 / g;
+  R tx = f * B[0], ty = f * B[1], tz = f * B[2];
+  R sfac = (R)2 / ((R)1 + (tx * tx + ty * ty + tz * tz));
+  // u' = u- + u- x t, with u-_z = ub + mz
+  R px = mx + (my * tz - (P.ub * ty + mz * ty));
+  R py = my + ((P.ub * tx + mz * tx) - mx * tz);
+  R pz = mz + (mx * ty - my * tx);
+  R sx = sfac * tx, sy = sfac * ty, sz = sfac * tz;
+  // u+ = u- + u' x s, with u'_z = ub + pz
+  R qx = mx + (py * sz - (P.ub * sy + pz * sy));
+  R qy = my + ((P.ub * sx + pz * sx) - px * sz);
+  R qz = mz + (px * sy - py * sx);
+  du[0] = qx + P.qdt2 * E[0];
+  du[1] = qy + P.qdt2 * E[1];
+  du[2] = qz + P.qdt2 * E[2];
+  R dg = gamma_minus_gb(P, du[0], du[1], du[2]);
+  gam = P.gb + dg;
+  R ig = (R)1 / gam;
+  dv[0] = du[0] * ig;
+  dv[1] = du[1] * ig;
+  R u2 = du[0] * du[0] + du[1] * du[1] + du[2] * du[2];
+  dv[2] = (((R)2 + P.gb * dg) * du[2] - P.ub * u2) / ((gam + P.gb) * gam * P.gb);
+}
+
+// XCD-aware block -> work item map: consecutive work items land on the same
+// XCD (blocks are dealt round-robin over the 8 XCDs), so neighbouring tiles
+// share that XCD's L2.
+__device__ __forceinline__ int xcd_remap(int b, int n) {
+  const int X = 8;
+  int per = n / X, rem = n % X;
+  int x = b % X, idx = b / X;
+  return x < rem ? x * (per + 1) + idx : rem * (per + 1) + (x - rem) * per + idx;
+}
+
+}  // namespace bfpic

@@ -1,0 +1,711 @@
+// kernels_particles.hpp -- gather, Boris push, move and Esirkepov deposit of
+// every electron and its drifting ion partner; plasma creation and export.
+//
+// Particle state (structure of arrays, one slot per electron):
+//   id          lattice identity; the ion partner's birth spot is derived from it
+//   xi[3]       electron displacement from its partner, in cells (z, x, y)
+//   du[3]       peculiar momentum u - u_b z, (x, y, z) order
+//   w           weight (real particles per macro-particle)
+// The partner never stores a position: it sits at its birth spot minus the
+// rigid drift D of the lab-rest plasma (plus the window displacement).
+#pragma once
+
+#include "device_common.hpp"
+
+namespace bfpic {
+
+template <typename R>
+struct PSoA {
+  int* id;
+  R* xi[3];
+  R* du[3];
+  R* w;
+};
+
+template <typename R>
+struct Fields {
+  R* F[6];  // Ex Ey Ez Bx By Bz
+};
+
+// Per-step constants of the particle kernels.
+template <typename R>
+struct StepK {
+  Geo g;
+  LatticeP L;
+  PushC<R> push;
+  Drift<R> D0, D1;   // drift at the start and end of the step
+  R dtd[3];          // dt / d along z, x, y: cells moved per unit velocity
+  R kj[3];           // prefix scale per unit q w: Jz 1/(dx[dy] dt), Jx 1/(dz[dy] dt), Jy 1/(dz dx dt)
+  R ky2d;            // 2D out-of-plane: 1/(dz dx)
+  int ion_moves;     // the partner drifts (boosted frame)
+  int remove;        // open z: drop pairs beyond `lim` cells outside [0, nz]
+  int lim;
+};
+
+// Overflow sink for particles outside their tile's LDS region.
+template <typename R>
+struct Ovf {
+  R* J[3];           // Jx Jy Jz on the grid (zero between steps)
+  int* rows;         // [0] min row touched, [1] max row touched
+};
+
+// --------------------------------------------------------------------------
+// Field fetchers and current sinks.  Coordinates are node indices in the
+// fetcher's own frame: LDS-relative for the tiled path, absolute (unwrapped)
+// grid indices for the global path.
+// --------------------------------------------------------------------------
+template <typename R, int LX, int LY>
+struct LdsFetch {
+  const R* s;   // [6][LZ*LX*LY]
+  int lv;
+  __device__ __forceinline__ R operator()(int comp, int i, int j, int k) const {
+    return s[comp * lv + (i * LX + j) * LY + k];
+  }
+};
+
+template <typename R>
+struct GlobalFetch {
+  const R* const* F;
+  Geo g;
+  __device__ __forceinline__ R operator()(int comp, int i, int j, int k) const {
+    int64_t n = gidx(g, i, j, k);
+    return n < 0 ? (R)0 : F[comp][n];
+  }
+};
+
+template <typename R, int LX, int LY>
+struct LdsSink {
+  R* s;  // [3][LZ*LX*LY]: Jx Jy Jz
+  int lv;
+  __device__ __forceinline__ void add(int comp, int i, int j, int k, R v) const {
+    if (v != (R)0) atomicAdd(&s[comp * lv + (i * LX + j) * LY + k], v);
+  }
+};
+
+template <typename R>
+struct GlobalSink {
+  Ovf<R> o;
+  Geo g;
+  __device__ __forceinline__ void add(int comp, int i, int j, int k, R v) const {
+    if (v == (R)0) return;
+    int64_t n = gidx(g, i, j, k);
+    if (n >= 0) atomicAdd(&o.J[comp][n], v);
+  }
+};
+
+// --------------------------------------------------------------------------
+// Gather: each component interpolated from its own staggered lattice with the
+// deposit's shape (momentum-conserving gather).  bc = the particle's cell in
+// the fetcher's frame, p its absolute position.
+// --------------------------------------------------------------------------
+template <typename R, int DIM, int ORDER, class F>
+__device__ __forceinline__ R interp(const F& f, int comp, int bz, const R* wz, int bx, const R* wx,
+                                    int by, const R* wy) {
+  R acc = (R)0;
+#pragma unroll
+  for (int a = 0; a <= ORDER; a++) {
+    R rowz = (R)0;
+#pragma unroll
+    for (int b = 0; b <= ORDER; b++) {
+      if (DIM == 3) {
+        R cy = (R)0;
+#pragma unroll
+        for (int c = 0; c <= ORDER; c++) cy += f(comp, bz + a, bx + b, by + c) * wy[c];
+        rowz += cy * wx[b];
+      } else {
+        rowz += f(comp, bz + a, bx + b, 0) * wx[b];
+      }
+    }
+    acc += rowz * wz[a];
+  }
+  return acc;
+}
+
+template <typename R, int DIM, int ORDER, class F>
+__device__ __forceinline__ void gather(const F& f, const int bc[3], const Pos<R>& p, R E[3],
+                                       R B[3]) {
+  R wz0[ORDER + 1], wz1[ORDER + 1], wx0[ORDER + 1], wx1[ORDER + 1];
+  R wy0[ORDER + 1], wy1[ORDER + 1];
+  int z0 = shape<R, ORDER>(p.c[0], p.o[0], 0, wz0) - p.c[0] + bc[0];
+  int z1 = shape<R, ORDER>(p.c[0], p.o[0], 1, wz1) - p.c[0] + bc[0];
+  int x0 = shape<R, ORDER>(p.c[1], p.o[1], 0, wx0) - p.c[1] + bc[1];
+  int x1 = shape<R, ORDER>(p.c[1], p.o[1], 1, wx1) - p.c[1] + bc[1];
+  int y0 = 0, y1 = 0;
+  if (DIM == 3) {
+    y0 = shape<R, ORDER>(p.c[2], p.o[2], 0, wy0) - p.c[2] + bc[2];
+    y1 = shape<R, ORDER>(p.c[2], p.o[2], 1, wy1) - p.c[2] + bc[2];
+  }
+  // staggering (z, x, y): Ex (0,h,0) Ey (0,0,h) Ez (h,0,0) Bx (h,0,h) By (h,h,0) Bz (0,h,h)
+  E[0] = interp<R, DIM, ORDER>(f, 0, z0, wz0, x1, wx1, y0, wy0);
+  E[1] = interp<R, DIM, ORDER>(f, 1, z0, wz0, x0, wx0, y1, wy1);
+  E[2] = interp<R, DIM, ORDER>(f, 2, z1, wz1, x0, wx0, y0, wy0);
+  B[0] = interp<R, DIM, ORDER>(f, 3, z1, wz1, x0, wx0, y1, wy1);
+  B[1] = interp<R, DIM, ORDER>(f, 4, z1, wz1, x1, wx1, y0, wy0);
+  B[2] = interp<R, DIM, ORDER>(f, 5, z0, wz0, x1, wx1, y1, wy1);
+}
+
+// --------------------------------------------------------------------------
+// Esirkepov stencil along one axis: old and new shape factors of the charge
+// lattice placed on NS = ORDER + 2 nodes starting at bs.
+// --------------------------------------------------------------------------
+template <typename R, int ORDER>
+__device__ __forceinline__ void place(bool shifted, const R* w, R* S) {
+  constexpr int NS = ORDER + 2;
+#pragma unroll
+  for (int m = 0; m < NS; m++) {
+    R lo = m <= ORDER ? w[m < ORDER + 1 ? m : 0] : (R)0;
+    R hi = m >= 1 ? w[m >= 1 ? m - 1 : 0] : (R)0;
+    S[m] = shifted ? hi : lo;
+  }
+}
+
+template <typename R, int ORDER>
+__device__ __forceinline__ int esk_axis(int c0, R o0, int c1, R o1, R* S0, R* dS) {
+  constexpr int NS = ORDER + 2;
+  R w0[ORDER + 1], w1[ORDER + 1], S1[NS];
+  int b0 = shape<R, ORDER>(c0, o0, 0, w0);
+  int b1 = shape<R, ORDER>(c1, o1, 0, w1);
+  int bs = b0 < b1 ? b0 : b1;
+  place<R, ORDER>(b0 != bs, w0, S0);
+  place<R, ORDER>(b1 != bs, w1, S1);
+#pragma unroll
+  for (int m = 0; m < NS; m++) dS[m] = S1[m] - S0[m];
+  return bs;
+}
+
+// --------------------------------------------------------------------------
+// Deposit of one electron (charge -w) moving e0 -> e1 and of its partner
+// (charge +w) moving i0 -> i1 along z.  When the partner's stencil lies
+// inside the electron's, both W patterns are combined before the prefix sums,
+// so an unperturbed pair deposits exactly zero.
+// --------------------------------------------------------------------------
+template <typename R, int ORDER, class Snk>
+__device__ __forceinline__ void deposit2d(const StepK<R>& P, const Snk& snk, const int bc[3],
+                                          const Pos<R>& e0, const Pos<R>& e1, const Pos<R>& i0,
+                                          const Pos<R>& i1, R w, R vy) {
+  constexpr int NS = ORDER + 2;
+  R S0z[NS], dSz[NS], S0x[NS], dSx[NS];
+  int bz = esk_axis<R, ORDER>(e0.c[0], e0.o[0], e1.c[0], e1.o[0], S0z, dSz);
+  int bx = esk_axis<R, ORDER>(e0.c[1], e0.o[1], e1.c[1], e1.o[1], S0x, dSx);
+  const int rz = bc[0] + (bz - e0.c[0]), rx = bc[1] + (bx - e0.c[1]);
+  // partner: moves along z only
+  R I0z[NS], dIz[NS], Ix[NS];
+  bool ion = P.ion_moves;
+  bool comb = false;
+  int ibz = 0, ibx = 0;
+  if (ion) {
+    ibz = esk_axis<R, ORDER>(i0.c[0], i0.o[0], i1.c[0], i1.o[0], I0z, dIz);
+    R wx[ORDER + 1];
+    ibx = shape<R, ORDER>(i0.c[1], i0.o[1], 0, wx);
+    int ox = ibx - bx;
+    comb = (ibz == bz) && (ox == 0 || ox == 1);
+    place<R, ORDER>(ox == 1, wx, Ix);
+  }
+  // Jz: prefix along z of kz w (We - Wi), We = dSz (S0x + dSx/2), Wi = dIz Ix
+  const R kz = P.kj[0] * w;
+#pragma unroll
+  for (int b = 0; b < NS; b++) {
+    R fx = S0x[b] + (R)0.5 * dSx[b];
+    R acc = (R)0;
+#pragma unroll
+    for (int a = 0; a < NS - 1; a++) {
+      R We = dSz[a] * fx;
+      R Wi = comb ? dIz[a] * Ix[b] : (R)0;
+      acc += kz * (We - Wi);
+      snk.add(2, rz + a, rx + b, 0, acc);
+    }
+  }
+  if (ion && !comb) {
+    const int irz = bc[0] + (ibz - e0.c[0]), irx = bc[1] + (ibx - e0.c[1]);
+    R wx[ORDER + 1];
+    shape<R, ORDER>(i0.c[1], i0.o[1], 0, wx);
+#pragma unroll
+    for (int b = 0; b <= ORDER; b++) {
+      R acc = (R)0;
+#pragma unroll
+      for (int a = 0; a < NS - 1; a++) {
+        acc -= kz * dIz[a] * wx[b];
+        snk.add(2, irz + a, irx + b, 0, acc);
+      }
+    }
+  }
+  // Jx: prefix along x of kx w We, We = dSx (S0z + dSz/2)
+  const R kx = P.kj[1] * w;
+#pragma unroll
+  for (int a = 0; a < NS; a++) {
+    R fz = S0z[a] + (R)0.5 * dSz[a];
+    R acc = (R)0;
+#pragma unroll
+    for (int b = 0; b < NS - 1; b++) {
+      acc += kx * dSx[b] * fz;
+      snk.add(0, rz + a, rx + b, 0, acc);
+    }
+  }
+  // Jy (out of plane): q w vy Wy / (dz dx), Wy the time-averaged shape product
+  if (vy != (R)0) {
+    const R ky = -P.ky2d * w * vy;
+#pragma unroll
+    for (int a = 0; a < NS; a++)
+#pragma unroll
+      for (int b = 0; b < NS; b++) {
+        R wy = S0z[a] * S0x[b] + (R)0.5 * (dSz[a] * S0x[b] + S0z[a] * dSx[b]) +
+               dSz[a] * dSx[b] * (R)(1.0 / 3.0);
+        snk.add(1, rz + a, rx + b, 0, ky * wy);
+      }
+  }
+}
+
+// --------------------------------------------------------------------------
+// Pair deposit, linear shape, 2D: the electron's shape factors written as its
+// partner's plus a difference dS computed from the displacement xi itself.
+// With S(d) = Rc(d + 1) - Rc(d), Rc = clamp(., 0, 1):
+//   S(d + xi) - S(d) = dRc(d + 1) - dRc(d),
+//   dRc(t) = clamp(xi, -t, 1 - t) - clamp(0, -t, 1 - t),
+// whose bounds are (integer - offset) of the partner, so no step subtracts
+// two nearly equal positions.  Electron minus partner then reads
+//   We - Wi = dSi eta + eps fxi + eps eta   (Jz),
+// eps = dS(new) - dS(old) along z, eta = (dS_x(old) + dS_x(new)) / 2,
+// and the electron's own Jx, Jy use Si + dS.  Window: 4 nodes per axis from
+// the lowest cell among partner and electron, old and new.
+// --------------------------------------------------------------------------
+template <typename R>
+__device__ __forceinline__ R dclamp(R xi, R lo, R hi) {
+  return fmin(fmax(xi, lo), hi) - fmin(fmax((R)0, lo), hi);
+}
+
+// partner weight S(o - k) and electron-minus-partner dS at node c + k
+template <typename R>
+__device__ __forceinline__ void pair_node(R o, R xi, int k, R& Si, R& dS) {
+  R d = o - (R)k;
+  R ad = fabs(d);
+  Si = ad < (R)1 ? (R)1 - ad : (R)0;
+  R qm = (R)(k - 1) - o, q0 = (R)k - o, qp = (R)(k + 1) - o;
+  dS = dclamp(xi, qm, q0) - dclamp(xi, q0, qp);
+}
+
+template <typename R, class Snk>
+__device__ __forceinline__ bool deposit2d_pair(const StepK<R>& P, const Snk& snk, const int bc[3],
+                                               const Pos<R>& e0, const Pos<R>& e1,
+                                               const Pos<R>& i0, const Pos<R>& i1,
+                                               const R xi0[3], const R xi1[3], R w, R vy) {
+  int mz = min(min(i0.c[0], i1.c[0]), min(e0.c[0], e1.c[0]));
+  int Mz = max(max(i0.c[0], i1.c[0]), max(e0.c[0], e1.c[0]));
+  int mx = min(i0.c[1], min(e0.c[1], e1.c[1]));
+  int Mx = max(i0.c[1], max(e0.c[1], e1.c[1]));
+  if (Mz - mz > 2 || Mx - mx > 2) return false;
+  R Si0[4], Si1[4], dS0[4], dS1[4], Sx[4], dX0[4], dX1[4];
+#pragma unroll
+  for (int j = 0; j < 4; j++) {
+    pair_node(i0.o[0], xi0[0], mz + j - i0.c[0], Si0[j], dS0[j]);
+    pair_node(i1.o[0], xi1[0], mz + j - i1.c[0], Si1[j], dS1[j]);
+    R s_unused;
+    pair_node(i0.o[1], xi0[1], mx + j - i0.c[1], Sx[j], dX0[j]);
+    pair_node(i0.o[1], xi1[1], mx + j - i0.c[1], s_unused, dX1[j]);
+  }
+  const int rz = bc[0] + (mz - e0.c[0]), rx = bc[1] + (mx - e0.c[1]);
+  const R kz = P.kj[0] * w, kx = P.kj[1] * w;
+  const bool ion = P.ion_moves;
+  // Jz: prefix along z of kz (We - Wi)
+#pragma unroll
+  for (int b = 0; b < 4; b++) {
+    R eta = (R)0.5 * (dX0[b] + dX1[b]);
+    R acc = (R)0;
+#pragma unroll
+    for (int a = 0; a < 3; a++) {
+      R dSi = ion ? Si1[a] - Si0[a] : (R)0;
+      R eps = dS1[a] - dS0[a];
+      acc += kz * (dSi * eta + eps * Sx[b] + eps * eta);
+      snk.add(2, rz + a, rx + b, 0, acc);
+    }
+  }
+  // electron shape factors along z: old Si0 + dS0, change dSi + eps
+  R S0e[4], dSe[4];
+#pragma unroll
+  for (int a = 0; a < 4; a++) {
+    S0e[a] = Si0[a] + dS0[a];
+    dSe[a] = (ion ? Si1[a] - Si0[a] : (R)0) + (dS1[a] - dS0[a]);
+  }
+  // Jx: prefix along x of kx dSx_e (S0z_e + dSz_e / 2), dSx_e = dX1 - dX0
+#pragma unroll
+  for (int a = 0; a < 4; a++) {
+    R fz = S0e[a] + (R)0.5 * dSe[a];
+    R acc = (R)0;
+#pragma unroll
+    for (int b = 0; b < 3; b++) {
+      acc += kx * (dX1[b] - dX0[b]) * fz;
+      snk.add(0, rz + a, rx + b, 0, acc);
+    }
+  }
+  if (vy != (R)0) {
+    const R ky = -P.ky2d * w * vy;
+#pragma unroll
+    for (int a = 0; a < 4; a++)
+#pragma unroll
+      for (int b = 0; b < 4; b++) {
+        R s0x = Sx[b] + dX0[b], dsx = dX1[b] - dX0[b];
+        R wy = S0e[a] * s0x + (R)0.5 * (dSe[a] * s0x + S0e[a] * dsx) +
+               dSe[a] * dsx * (R)(1.0 / 3.0);
+        snk.add(1, rz + a, rx + b, 0, ky * wy);
+      }
+  }
+  return true;
+}
+
+template <typename R>
+__device__ __forceinline__ R wmix(R s0a, R dsa, R s0b, R dsb) {
+  return s0a * s0b + (R)0.5 * (dsa * s0b + s0a * dsb) + dsa * dsb * (R)(1.0 / 3.0);
+}
+
+template <typename R, int ORDER, class Snk>
+__device__ __forceinline__ void deposit3d(const StepK<R>& P, const Snk& snk, const int bc[3],
+                                          const Pos<R>& e0, const Pos<R>& e1, const Pos<R>& i0,
+                                          const Pos<R>& i1, R w) {
+  constexpr int NS = ORDER + 2;
+  R S0z[NS], dSz[NS], S0x[NS], dSx[NS], S0y[NS], dSy[NS];
+  int bz = esk_axis<R, ORDER>(e0.c[0], e0.o[0], e1.c[0], e1.o[0], S0z, dSz);
+  int bx = esk_axis<R, ORDER>(e0.c[1], e0.o[1], e1.c[1], e1.o[1], S0x, dSx);
+  int by = esk_axis<R, ORDER>(e0.c[2], e0.o[2], e1.c[2], e1.o[2], S0y, dSy);
+  const int rz = bc[0] + (bz - e0.c[0]), rx = bc[1] + (bx - e0.c[1]),
+            ry = bc[2] + (by - e0.c[2]);
+  R I0z[NS], dIz[NS], Ix[NS], Iy[NS];
+  bool ion = P.ion_moves, comb = false;
+  int ibz = 0, ibx = 0, iby = 0;
+  R wxi[ORDER + 1], wyi[ORDER + 1];
+  if (ion) {
+    ibz = esk_axis<R, ORDER>(i0.c[0], i0.o[0], i1.c[0], i1.o[0], I0z, dIz);
+    ibx = shape<R, ORDER>(i0.c[1], i0.o[1], 0, wxi);
+    iby = shape<R, ORDER>(i0.c[2], i0.o[2], 0, wyi);
+    int ox = ibx - bx, oy = iby - by;
+    comb = (ibz == bz) && (ox == 0 || ox == 1) && (oy == 0 || oy == 1);
+    place<R, ORDER>(ox == 1, wxi, Ix);
+    place<R, ORDER>(oy == 1, wyi, Iy);
+  }
+  const R kz = P.kj[0] * w, kx = P.kj[1] * w, ky = P.kj[2] * w;
+#pragma unroll
+  for (int b = 0; b < NS; b++)
+#pragma unroll
+    for (int c = 0; c < NS; c++) {
+      R f = wmix(S0x[b], dSx[b], S0y[c], dSy[c]);
+      R acc = (R)0;
+#pragma unroll
+      for (int a = 0; a < NS - 1; a++) {
+        R Wi = comb ? dIz[a] * Ix[b] * Iy[c] : (R)0;
+        acc += kz * (dSz[a] * f - Wi);
+        snk.add(2, rz + a, rx + b, ry + c, acc);
+      }
+    }
+  if (ion && !comb) {
+    const int irz = bc[0] + (ibz - e0.c[0]), irx = bc[1] + (ibx - e0.c[1]),
+              iry = bc[2] + (iby - e0.c[2]);
+#pragma unroll
+    for (int b = 0; b <= ORDER; b++)
+#pragma unroll
+      for (int c = 0; c <= ORDER; c++) {
+        R acc = (R)0;
+#pragma unroll
+        for (int a = 0; a < NS - 1; a++) {
+          acc -= kz * dIz[a] * wxi[b] * wyi[c];
+          snk.add(2, irz + a, irx + b, iry + c, acc);
+        }
+      }
+  }
+#pragma unroll
+  for (int a = 0; a < NS; a++)
+#pragma unroll
+    for (int c = 0; c < NS; c++) {
+      R f = wmix(S0z[a], dSz[a], S0y[c], dSy[c]);
+      R acc = (R)0;
+#pragma unroll
+      for (int b = 0; b < NS - 1; b++) {
+        acc += kx * dSx[b] * f;
+        snk.add(0, rz + a, rx + b, ry + c, acc);
+      }
+    }
+#pragma unroll
+  for (int a = 0; a < NS; a++)
+#pragma unroll
+    for (int b = 0; b < NS; b++) {
+      R f = wmix(S0z[a], dSz[a], S0x[b], dSx[b]);
+      R acc = (R)0;
+#pragma unroll
+      for (int c = 0; c < NS - 1; c++) {
+        acc += ky * dSy[c] * f;
+        snk.add(1, rz + a, rx + b, ry + c, acc);
+      }
+    }
+}
+
+// --------------------------------------------------------------------------
+// One particle step after its positions are known: gather at e0, push, move,
+// deposit, decide removal.  Returns the new displacement through xi.
+// --------------------------------------------------------------------------
+template <typename R, int DIM, int ORDER, class F, class Snk>
+__device__ __forceinline__ bool particle_step(const StepK<R>& P, const F& fetch, const Snk& snk,
+                                              const int bc[3], const Pos<R>& e0,
+                                              const Pos<R>& i0, const Pos<R>& i1, R xi[3],
+                                              R du[3], R w) {
+  R E[3], B[3], dv[3], gam;
+  gather<R, DIM, ORDER>(fetch, bc, e0, E, B);
+  boris_split(P.push, E, B, du, dv, gam);
+  const R xi_old[3] = {xi[0], xi[1], xi[2]};
+  // position axes (z, x, y) <- velocity components (z, x, y) = dv[2], dv[0], dv[1]
+  xi[0] += dv[2] * P.dtd[0];
+  xi[1] += dv[0] * P.dtd[1];
+  if (DIM == 3) xi[2] += dv[1] * P.dtd[2];
+  Pos<R> e1 = add_xi<R, DIM>(i1, xi);
+  if (DIM == 2) {
+    bool done = false;
+    if constexpr (ORDER == 1)
+      done = deposit2d_pair<R>(P, snk, bc, e0, e1, i0, i1, xi_old, xi, w, dv[1]);
+    if (!done) deposit2d<R, ORDER>(P, snk, bc, e0, e1, i0, i1, w, dv[1]);
+  } else {
+    deposit3d<R, ORDER>(P, snk, bc, e0, e1, i0, i1, w);
+  }
+  if (!P.remove) return false;
+  // outside [-lim, nz + lim] along z, for both members of the pair
+  const int lo = -P.lim - 1, hi = P.g.nz + P.lim;
+  bool eo = e1.c[0] <= lo || e1.c[0] > hi || (e1.c[0] == hi && e1.o[0] > (R)0);
+  bool io = i1.c[0] <= lo || i1.c[0] > hi || (i1.c[0] == hi && i1.o[0] > (R)0);
+  return eo && io;
+}
+
+template <typename R>
+__device__ __forceinline__ void load_state(const PSoA<R>& S, int p, R xi[3], R du[3], R& w) {
+  xi[0] = S.xi[0][p];
+  xi[1] = S.xi[1][p];
+  xi[2] = S.xi[2] ? S.xi[2][p] : (R)0;
+  du[0] = S.du[0][p];
+  du[1] = S.du[1][p];
+  du[2] = S.du[2][p];
+  w = S.w[p];
+}
+
+template <typename R, int DIM>
+__device__ __forceinline__ void store_state(const PSoA<R>& S, int p, const R xi[3], const R du[3],
+                                            bool dead) {
+  S.xi[0][p] = xi[0];
+  S.xi[1][p] = xi[1];
+  if (DIM == 3) S.xi[2][p] = xi[2];
+  S.du[0][p] = du[0];
+  S.du[1][p] = du[1];
+  S.du[2][p] = du[2];
+  if (dead) S.id[p] = -1;
+}
+
+// Row range of a particle's stencils (for the overflow fold).
+template <typename R, int ORDER>
+__device__ __forceinline__ void note_rows(const Ovf<R>& o, const Geo& g, int ce, int ci) {
+  if (g.periodic_z) {
+    atomicMin(&o.rows[0], 0);
+    atomicMax(&o.rows[1], g.nz);
+    return;
+  }
+  int lo = (ce < ci ? ce : ci) - ORDER - 1;
+  int hi = (ce > ci ? ce : ci) + ORDER + 2;
+  atomicMin(&o.rows[0], lo);
+  atomicMax(&o.rows[1], hi);
+}
+
+// --------------------------------------------------------------------------
+// Global path: every slot in [first, *n_slots) (the unsorted tail, or all
+// particles when the grid is too small to tile).
+// --------------------------------------------------------------------------
+template <typename R, int DIM, int ORDER>
+__global__ __launch_bounds__(256) void k_gpd_global(StepK<R> P, Fields<R> F, PSoA<R> S, Ovf<R> O,
+                                                    const int* counts, int from_sorted) {
+  const int n = counts[0];
+  const int first = from_sorted ? counts[1] : 0;
+  int p = first + blockIdx.x * blockDim.x + threadIdx.x;
+  if (p >= n) return;
+  int id = S.id[p];
+  if (id < 0) return;
+  R xi[3], du[3], w;
+  load_state(S, p, xi, du, w);
+  Birth b = decode_id(P.L, id);
+  Pos<R> i0 = ion_pos<R, DIM>(P.L, id, b, P.D0);
+  Pos<R> i1 = ion_pos<R, DIM>(P.L, id, b, P.D1);
+  Pos<R> e0 = add_xi<R, DIM>(i0, xi);
+  GlobalFetch<R> f{(const R* const*)F.F, P.g};
+  GlobalSink<R> s{O, P.g};
+  int bc[3] = {e0.c[0], e0.c[1], e0.c[2]};
+  note_rows<R, ORDER>(O, P.g, e0.c[0], i0.c[0]);
+  bool dead = particle_step<R, DIM, ORDER>(P, f, s, bc, e0, i0, i1, xi, du, w);
+  store_state<R, DIM>(S, p, xi, du, dead);
+}
+
+// --------------------------------------------------------------------------
+// Tiled path.  One workgroup per co-moving tile of TZ x TX [x TY] cells.  The
+// tile's E, B and a zeroed J accumulator are staged in LDS over the tile plus
+// a margin of E_ cells of peculiar excursion and the stencil reach; each
+// particle of the tile gathers from LDS and deposits with LDS atomics; the J
+// region is then stored whole to the tile's scratch slot, to be folded into
+// the grid by the filter kernel.  Particles whose stencil leaves the region
+// take the global path.
+// --------------------------------------------------------------------------
+struct TileK {
+  const int* start;  // particle range of tile t: [start[t], start[t+1])
+  int ntiles, ntx, nty;
+  int zc0;           // first co-moving z cell of tile row 0
+};
+
+// Region of a tile: its cells, the excursion margin EXC on each side, one row
+// of plasma drift along z, and the stencil reach HLO below / HHI above a cell
+// (HHI includes the spare node of the 4-node pair window).
+template <int DIM, int ORDER, int TZ, int TX, int TY, int EXC>
+struct TileGeom {
+  static constexpr int HLO = ORDER;
+  static constexpr int HHI = ORDER + 2;
+  static constexpr int LZ = TZ + 2 * EXC + 1 + HLO + HHI;
+  static constexpr int LX = TX + 2 * EXC + HLO + HHI;
+  static constexpr int LY = DIM == 3 ? TY + 2 * EXC + HLO + HHI : 1;
+  static constexpr int LV = LZ * LX * LY;
+};
+
+template <typename R, int DIM, int ORDER, int TZ, int TX, int TY, int EXC>
+__global__ __launch_bounds__(256) void k_gpd_tiled(StepK<R> P, Fields<R> F, PSoA<R> S, Ovf<R> O,
+                                                   TileK T, R* scratch) {
+  using TG = TileGeom<DIM, ORDER, TZ, TX, TY, EXC>;
+  constexpr int LZ = TG::LZ, LX = TG::LX, LY = TG::LY, LV = TG::LV;
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  R* sF = reinterpret_cast<R*>(smem_raw);
+  R* sJ = sF + 6 * LV;
+  const int t = xcd_remap(blockIdx.x, T.ntiles);
+  const int ty = DIM == 3 ? t % T.nty : 0;
+  const int tx = (t / T.nty) % T.ntx;
+  const int tz = t / (T.nty * T.ntx);
+  const int gz0 = T.zc0 + tz * TZ - P.D0.Dint - 1 - EXC - TG::HLO;
+  const int gx0 = tx * TX - EXC - TG::HLO;
+  const int gy0 = DIM == 3 ? ty * TY - EXC - TG::HLO : 0;
+  const Geo& g = P.g;
+  for (int v = threadIdx.x; v < 6 * LV; v += blockDim.x) {
+    int comp = v / LV, r = v - comp * LV;
+    int rz = r / (LX * LY), rem = r - rz * (LX * LY);
+    int rx = rem / LY, ry = rem - rx * LY;
+    int64_t n = gidx(g, gz0 + rz, gx0 + rx, gy0 + ry);
+    sF[v] = n < 0 ? (R)0 : F.F[comp][n];
+  }
+  for (int v = threadIdx.x; v < 3 * LV; v += blockDim.x) sJ[v] = (R)0;
+  __syncthreads();
+  LdsFetch<R, LX, LY> lf{sF, LV};
+  LdsSink<R, LX, LY> ls{sJ, LV};
+  GlobalFetch<R> gf{(const R* const*)F.F, g};
+  GlobalSink<R> gs{O, g};
+  const int p0 = T.start[t], p1 = T.start[t + 1];
+  for (int p = p0 + threadIdx.x; p < p1; p += blockDim.x) {
+    int id = S.id[p];
+    if (id < 0) continue;
+    R xi[3], du[3], w;
+    load_state(S, p, xi, du, w);
+    Birth b = decode_id(P.L, id);
+    Pos<R> i0 = ion_pos<R, DIM>(P.L, id, b, P.D0);
+    Pos<R> i1 = ion_pos<R, DIM>(P.L, id, b, P.D1);
+    Pos<R> e0 = add_xi<R, DIM>(i0, xi);
+    // cells relative to the LDS region (wrapped where the axis is periodic)
+    int rz = e0.c[0] - gz0, riz = i0.c[0] - gz0;
+    if (g.periodic_z) {
+      rz = wrapi(rz, g.nz);
+      riz = wrapi(riz, g.nz);
+    }
+    int rx = wrapi(e0.c[1] - gx0, g.nx), rix = wrapi(i0.c[1] - gx0, g.nx);
+    int ry = 0, riy = 0;
+    bool inside = rz >= TG::HLO && rz < LZ - TG::HHI && riz >= TG::HLO && riz < LZ - TG::HHI &&
+                  rx >= TG::HLO && rx < LX - TG::HHI && rix >= TG::HLO && rix < LX - TG::HHI;
+    if (DIM == 3) {
+      ry = wrapi(e0.c[2] - gy0, g.ny);
+      riy = wrapi(i0.c[2] - gy0, g.ny);
+      inside = inside && ry >= TG::HLO && ry < LY - TG::HHI && riy >= TG::HLO &&
+               riy < LY - TG::HHI;
+    }
+    bool dead;
+    if (inside) {
+      int bc[3] = {rz, rx, ry};
+      dead = particle_step<R, DIM, ORDER>(P, lf, ls, bc, e0, i0, i1, xi, du, w);
+    } else {
+      int bc[3] = {e0.c[0], e0.c[1], e0.c[2]};
+      note_rows<R, ORDER>(O, g, e0.c[0], i0.c[0]);
+      dead = particle_step<R, DIM, ORDER>(P, gf, gs, bc, e0, i0, i1, xi, du, w);
+    }
+    store_state<R, DIM>(S, p, xi, du, dead);
+  }
+  __syncthreads();
+  R* dst = scratch + (int64_t)t * 3 * LV;
+  for (int v = threadIdx.x; v < 3 * LV; v += blockDim.x) dst[v] = sJ[v];
+}
+
+// --------------------------------------------------------------------------
+// Plasma creation: lattice columns [k0, k0 + ncols) -> slots starting at
+// counts[0] (the current slot count); each slot gets id, xi = 0, du = du0
+// and the weight gamma_b n_lab(z_lab) dV / ppc at z_lab = gamma_b (k + r_z) dz.
+// --------------------------------------------------------------------------
+struct DensityK {
+  double n_uniform;
+  int nknots;
+  double kz[32], kn[32];
+  double gamma_b, dz, dV_over_ppc;
+  double du0[3];
+};
+
+__device__ __forceinline__ double lab_density(const DensityK& d, double zl) {
+  if (d.nknots < 2) return d.n_uniform;
+  if (zl < d.kz[0] || zl > d.kz[d.nknots - 1]) return 0.0;
+  for (int m = 0; m + 1 < d.nknots; m++) {
+    if (zl <= d.kz[m + 1]) {
+      double f = (zl - d.kz[m]) / (d.kz[m + 1] - d.kz[m]);
+      return d.kn[m] + f * (d.kn[m + 1] - d.kn[m]);
+    }
+  }
+  return d.kn[d.nknots - 1];
+}
+
+template <typename R>
+__global__ __launch_bounds__(256) void k_create(PSoA<R> S, LatticeP L, DensityK d, int k0,
+                                                int64_t count, const int* counts) {
+  int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (q >= count) return;
+  const int base = counts[0];
+  int id = (int)((int64_t)k0 * L.nyy * L.nx * L.ppc + q);
+  int p = base + (int)q;
+  Birth b = decode_id(L, id);
+  double rz = (double)birth_offset<double>(L, id, 0);
+  double zl = d.gamma_b * ((double)b.k + rz) * d.dz;
+  double w = d.gamma_b * lab_density(d, zl) * d.dV_over_ppc;
+  S.id[p] = id;
+  S.xi[0][p] = (R)0;
+  S.xi[1][p] = (R)0;
+  if (S.xi[2]) S.xi[2][p] = (R)0;
+  S.du[0][p] = (R)d.du0[0];
+  S.du[1][p] = (R)d.du0[1];
+  S.du[2][p] = (R)d.du0[2];
+  S.w[p] = (R)w;
+}
+
+__global__ void k_bump_slots(int* counts, int add) {
+  if (threadIdx.x == 0 && blockIdx.x == 0) counts[0] += add;
+}
+
+// Export of every slot as absolute FP64 state (electron position in grid
+// cells relative to the window; momentum u = du + u_b z).
+template <typename R, int DIM>
+__global__ __launch_bounds__(256) void k_export(PSoA<R> S, LatticeP L, Drift<R> D, double ub,
+                                                const int* counts, double* z, double* x,
+                                                double* y, double* ux, double* uy, double* uz,
+                                                double* w, int* ido) {
+  int p = blockIdx.x * blockDim.x + threadIdx.x;
+  if (p >= counts[0]) return;
+  int id = S.id[p];
+  ido[p] = id;
+  if (id < 0) return;
+  R xi[3], du[3], ww;
+  load_state(S, p, xi, du, ww);
+  Birth b = decode_id(L, id);
+  Pos<R> e = add_xi<R, DIM>(ion_pos<R, DIM>(L, id, b, D), xi);
+  z[p] = (double)e.c[0] + (double)e.o[0];
+  x[p] = (double)e.c[1] + (double)e.o[1];
+  y[p] = DIM == 3 ? (double)e.c[2] + (double)e.o[2] : 0.0;
+  ux[p] = (double)du[0];
+  uy[p] = (double)du[1];
+  uz[p] = ub + (double)du[2];
+  w[p] = (double)ww;
+}
+
+}  // namespace bfpic

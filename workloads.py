@@ -1,0 +1,132 @@
+"""Seeded synthetic workloads shared by the tests, the smoke check and the benchmark.
+
+Plain numbers only: each workload states its grid, frame, plasma, laser and
+numerics in the paper's terms (cells per boosted laser wavelength, lengths in
+vacuum laser wavelengths lambda0, lab densities in n_crit).  Turning them into
+cell sizes, time steps, window speeds and lab-frame laser positions is done by
+``resolve_gpu`` with the HIP library's own boost helper and by
+``resolve_oracle`` with the oracle's own helper; the two never share a helper.
+
+The paper measures on physical stages (densities 1e19..1e15 cm^-3, the caption
+of Fig. 4) whose parameters are in companion papers; these synthetic
+configurations stand in for them.  Random numbers are drawn by each side from
+the same counter-based generator (SplitMix64) keyed by ``seed``.
+"""
+import math
+
+LAMBDA0 = 2.0 * math.pi  # vacuum laser wavelength in units of c / omega0
+
+# --------------------------------------------------------------------------
+# lab_2d:       plain lab-frame 2D3V run (FP64), periodic box, 200 steps
+# boost13_2d:   gamma_boost = 13, 2048 x 256, moving window, FP32 split
+# boost130_2d:  gamma_boost = 130, 8192 x 512, FP32 split (throughput headline)
+# boost100_3d:  gamma_boost = 100, 3D3V quadratic, 512 x 128 x 128, FP32 split
+# The *_small variants keep the physics of their parent (frame, resolution rule,
+# density, laser, numerics) on a grid the oracle finishes in seconds.
+# --------------------------------------------------------------------------
+WORKLOADS = {
+    "lab_2d": dict(
+        dim=2, nz=128, nx=64, ny=1, gamma_b=1.0, dz_lambda0=1 / 16, dx_lambda0=1 / 16,
+        cfl=0.95, n_lab=0.01, ppc=4, order=1, filter_passes=1, filter_compensate=0,
+        zbc="periodic", precision="fp64", steps=200, seed=1012, window=None,
+        laser=dict(a0=1.0, w0_lambda0=8.0, L_lambda0=4.0, place="box_center", collimated=1,
+                   images_z=3, images_x=12)),
+    "boost13_2d": dict(
+        dim=2, nz=2048, nx=256, ny=1, gamma_b=13.0, dz_cells_per_wavelength=16, dx_lambda0=0.25,
+        cfl=0.95, n_lab=1e-3, ppc=8, order=1, filter_passes=4, filter_compensate=1, zbc="mur",
+        precision="fp32", steps=2000, seed=1013, window="group",
+        laser=dict(a0=1.0, w0_lambda0=8.0, L_lambda0=4.0, place="front", front_gap=4.5,
+                   collimated=1)),
+    "boost130_2d": dict(
+        dim=2, nz=8192, nx=512, ny=1, gamma_b=130.0, dz_cells_per_wavelength=16,
+        dx_lambda0=0.5, cfl=0.95, n_lab=1e-4, ppc=8, order=1, filter_passes=4,
+        filter_compensate=1, zbc="mur", precision="fp32", steps=5000, seed=1014, window=None,
+        laser=dict(a0=1.0, w0_lambda0=8.0, L_lambda0=4.0, place="front", front_gap=4.5,
+                   collimated=1)),
+    "boost100_3d": dict(
+        dim=3, nz=512, nx=128, ny=128, gamma_b=100.0, dz_cells_per_wavelength=16,
+        dx_lambda0=0.5, dy_lambda0=0.5, cfl=0.95, n_lab=3e-4, ppc=2, order=2, filter_passes=4,
+        filter_compensate=1, zbc="mur", precision="fp32", steps=1000, seed=1015, window="group",
+        laser=dict(a0=2.0, w0_lambda0=10.0, L_lambda0=4.0, place="front", front_gap=4.5,
+                   collimated=1)),
+}
+
+
+def small(name, **over):
+    """A smaller box with the physics of `name`; the pulse sits at the box centre."""
+    w = dict(WORKLOADS[name])
+    w["laser"] = dict(w["laser"], place="box_center")
+    w.update(over)
+    return w
+
+
+WORKLOADS["boost13_2d_small"] = small("boost13_2d", nz=256, nx=64, ppc=4, steps=100)
+WORKLOADS["boost130_2d_small"] = small("boost130_2d", nz=256, nx=64, ppc=4, steps=100)
+WORKLOADS["boost100_3d_small"] = small("boost100_3d", nz=48, nx=16, ny=16, steps=30)
+WORKLOADS["lab_2d_fp32"] = small("lab_2d", precision="fp32")
+SMOKE = small("boost13_2d", nz=96, nx=64, ppc=2, steps=20, precision="fp64")
+
+
+def _resolve(W, beta, boosted_dz, yee_dt, group_beta):
+    g = W["gamma_b"]
+    if "dz_cells_per_wavelength" in W:
+        dz = boosted_dz(g, LAMBDA0, W["dz_cells_per_wavelength"])
+    else:
+        dz = W["dz_lambda0"] * LAMBDA0
+    dx = W["dx_lambda0"] * LAMBDA0
+    dy = W.get("dy_lambda0", 1.0 / LAMBDA0) * LAMBDA0
+    dt = yee_dt(W["dim"], dz, dx, dy, W["cfl"])
+    bw = group_beta(g, W["n_lab"]) if W.get("window") == "group" else 0.0
+    las = W["laser"]
+    b = beta(g)
+    doppler = 1.0 / (g * (1.0 + b))  # gamma (1 - beta): lab -> frame wavenumber factor
+    L = las["L_lambda0"] * LAMBDA0
+    if las["place"] == "box_center":
+        zc_frame = 0.5 * W["nz"] * dz
+    else:  # centre front_gap envelope lengths behind the front edge of the box
+        zc_frame = W["nz"] * dz - las["front_gap"] * L / doppler
+    laser = dict(a0=las["a0"], w0=las["w0_lambda0"] * LAMBDA0, L=L,
+                 z_center=doppler * zc_frame, z_focus=g * zc_frame, phase=0.0,
+                 collimated=las.get("collimated", 0), images_z=las.get("images_z", 0),
+                 images_x=las.get("images_x", 0), images_y=las.get("images_y", 0))
+    return dict(dz=dz, dx=dx, dy=dy, dt=dt, beta_window=bw, laser=laser)
+
+
+def resolve_gpu(W, precision=None, sort_interval=20, capacity=None):
+    """HIP library config, init arguments and step count of a workload."""
+    import paper_1011_0917_amd as P
+    r = _resolve(W, P.beta, P.boosted_dz, P.yee_dt, P.boosted_group_beta)
+    prec = precision or W["precision"]
+    cfg = P.make_config(
+        dim=W["dim"], nz=W["nz"], nx=W["nx"], ny=W.get("ny", 1), dz=r["dz"], dx=r["dx"],
+        dy=r["dy"], cfl=W["cfl"], shape_order=W["order"], filter_passes=W["filter_passes"],
+        filter_compensate=W["filter_compensate"],
+        precision=P.FP64 if prec == "fp64" else P.FP32_SPLIT,
+        z_boundary=P.BC_PERIODIC if W["zbc"] == "periodic" else P.BC_MUR, ppc=W["ppc"],
+        load=W.get("load", 0), sort_interval=sort_interval, seed=W["seed"],
+        beta_window=r["beta_window"], auto_window=1 if W.get("window") else 0)
+    cells = W["nz"] * W["nx"] * W.get("ny", 1)
+    if capacity is None:
+        # initial plasma + injected columns over the run + margin
+        capacity = int(cells * W["ppc"] * 1.15) + 64 * W["nx"] * W.get("ny", 1) * W["ppc"]
+    init = dict(gamma_b=W["gamma_b"], n_lab=W["n_lab"], laser=P.make_laser(**r["laser"]),
+                capacity=capacity)
+    return cfg, init, W["steps"]
+
+
+def resolve_oracle(W):
+    """Oracle Sim keyword arguments and init arguments of a workload."""
+    import oracle as O
+
+    def group_beta(g, n):
+        return O.boosted_group_beta(g, n)
+
+    r = _resolve(W, O.beta_of_gamma, O.boosted_dz, O.yee_dt, group_beta)
+    kw = dict(dim=W["dim"], nz=W["nz"], nx=W["nx"], ny=W.get("ny", 1), dz=r["dz"], dx=r["dx"],
+              dy=r["dy"], dt=r["dt"], order=W["order"], filter_passes=W["filter_passes"],
+              filter_compensate=W["filter_compensate"],
+              zbc=0 if W["zbc"] == "periodic" else 1, ppc=W["ppc"], seed=W["seed"],
+              gamma_b=W["gamma_b"], beta_window=r["beta_window"],
+              auto_window=1 if W.get("window") else 0, ions=1, load=W.get("load", 0))
+    init = dict(n_lab=W["n_lab"], laser=O.make_laser(**r["laser"]))
+    return kw, init
