@@ -170,14 +170,18 @@ class Simulation:
                                   C.c_void_p(self.workspace.data_ptr()), sz.workspace_bytes,
                                   C.c_void_p(self.stream.cuda_stream), C.byref(h)))
         self.h = h
+        # held here so that close() still works while the interpreter shuts
+        # down and module globals are already cleared
+        self._destroy = lib().bfpic_destroy
         ny = cfg.ny if cfg.dim == 3 else 1
         self.field_shape = (cfg.nz + 1, cfg.nx, ny)
         self.dt = yee_dt(cfg.dim, cfg.dz, cfg.dx, cfg.dy, cfg.cfl)
 
     def close(self):
-        if getattr(self, "h", None):
-            lib().bfpic_destroy(self.h)
+        h = getattr(self, "h", None)
+        if h:
             self.h = None
+            self._destroy(h)
 
     def __del__(self):
         self.close()

@@ -52,11 +52,13 @@ constexpr int kExc = 1;
 constexpr int kT2Z = 16, kT2X = 32;
 constexpr int kT3 = 8;
 constexpr int kF2Z = 16, kF2X = 64;  // filter output tiles
+constexpr int kColsRows = 16;        // output rows per wave of the 2D register filter
 constexpr int kF3 = 8;
 constexpr int kNumTimers = 7;
 
 static inline int64_t align256(int64_t b) { return (b + 255) & ~int64_t(255); }
 static inline int64_t cdiv(int64_t a, int64_t b) { return (a + b - 1) / b; }
+static inline int floor_div(int a, int b) { return a >= 0 ? a / b : -((b - 1 - a) / b); }
 
 struct bfpic_ctx {
   bfpic_config cfg;
@@ -90,7 +92,9 @@ struct bfpic_ctx {
   void* pdu[2][3] = {};
   void* pw[2] = {};
   int cur = 0;
-  int* counts = nullptr;   // [0] slots in use, [1] sorted prefix, [2] slots at last sort
+  int* counts = nullptr;   // [0] slots in use, [1] sorted prefix, [2] slots at last sort,
+                           // [4] stragglers listed this step
+  int* strag = nullptr;
   int* ovf_rows = nullptr;
   int* tile_start = nullptr;
   void* scratch = nullptr;
@@ -181,6 +185,13 @@ static int check_cfg(const bfpic_config* c, std::string& why) {
   return 1;
 }
 
+template <class TG>
+static void set_region(bfpic_ctx* h) {
+  h->LZ = TG::LZ;
+  h->LX = TG::LX;
+  h->LY = TG::LY;
+}
+
 static void derive(bfpic_ctx* h, const bfpic_config* c) {
   h->cfg = *c;
   h->dim = c->dim;
@@ -202,18 +213,16 @@ static void derive(bfpic_ctx* h, const bfpic_config* c) {
   g.rows = h->nz + 2 * kGuard + 1;
   // tiles
   const int o = h->order;
-  // must agree with TileGeom: LZ = T + 2 E + 1 + o + (o + 2), LX = T + 2 E + o + (o + 2)
   if (h->dim == 2) {
     h->TZ = kT2Z;
     h->TX = kT2X;
     h->TY = 1;
-    h->LZ = kT2Z + 2 * kExc + 2 * o + 3;
-    h->LX = kT2X + 2 * kExc + 2 * o + 2;
-    h->LY = 1;
+    if (o == 1) set_region<TileGeom<2, 1, kT2Z, kT2X, 1, kExc>>(h);
+    else set_region<TileGeom<2, 2, kT2Z, kT2X, 1, kExc>>(h);
   } else {
     h->TZ = h->TX = h->TY = kT3;
-    h->LZ = kT3 + 2 * kExc + 2 * o + 3;
-    h->LX = h->LY = kT3 + 2 * kExc + 2 * o + 2;
+    if (o == 1) set_region<TileGeom<3, 1, kT3, kT3, kT3, kExc>>(h);
+    else set_region<TileGeom<3, 2, kT3, kT3, kT3, kExc>>(h);
   }
   h->LV = h->LZ * h->LX * h->LY;
   bool fit_x = h->nx % h->TX == 0 && h->LX <= h->nx && h->LX <= 2 * h->TX;
@@ -290,8 +299,12 @@ static int64_t plan(bfpic_ctx* h, int64_t cap, bfpic_ctx* fill, bfpic_sizes* sz)
   if (fill) fill->ovf_rows = (int*)p;
   p = P((h->maxtiles + 1) * 4);
   if (fill) fill->tile_start = (int*)p;
-  p = P(h->tiled ? h->maxtiles * 3 * (int64_t)h->LV * rs : 0);
+  // tile regions, then one row of tiles that stays zero (read for tile rows
+  // outside the co-moving range)
+  p = P(h->tiled ? (h->maxtiles + (int64_t)h->ntx * h->nty) * 3 * (int64_t)h->LV * rs : 0);
   if (fill) fill->scratch = p;
+  p = P(cap * 4);
+  if (fill) fill->strag = (int*)p;
   p = P(cap * 4);
   if (fill) fill->key = (int*)p;
   p = P(cap * 4);
@@ -351,6 +364,22 @@ struct Impl {
     for (int c = 0; c < 6; c++) f.F[c] = (R*)h->F[c];
     return f;
   }
+  // Granlund-Montgomery magic for division by d (see FastDiv).
+  static FastDiv fastdiv(int d) {
+    FastDiv f;
+    f.d = d;
+    if (d <= 1) {
+      f.m = 0;
+      f.l = 0;
+      return f;
+    }
+    int l = 0;
+    while ((1LL << l) < d) l++;
+    unsigned __int128 num = ((unsigned __int128)1 << 32) * (((unsigned __int128)1 << l) - d);
+    f.m = (uint32_t)(num / (unsigned)d + 1);
+    f.l = l;
+    return f;
+  }
   static LatticeP lattice(bfpic_ctx* h) {
     LatticeP L;
     L.seed = h->cfg.seed;
@@ -358,6 +387,9 @@ struct Impl {
     L.nx = h->nx;
     L.nyy = h->ny;
     L.load = h->cfg.load;
+    L.dppc = fastdiv(h->cfg.ppc);
+    L.dnx = fastdiv(h->nx);
+    L.dnyy = fastdiv(h->ny);
     return L;
   }
   static Ovf<R> ovf(bfpic_ctx* h) {
@@ -534,9 +566,11 @@ struct Impl {
     K.ntx = h->ntx;
     K.nty = h->nty;
     K.ntiles = h->tiled ? h->ntz * h->ntx * h->nty : 0;
-    K.gz0 = h->zc0 - P.D0.Dint - 1 - kExc - ORDER;
-    K.gx0 = -kExc - ORDER;
-    K.gy0 = DIM == 3 ? -kExc - ORDER : 0;
+    // region origin of tile (0,0,0): the same expression as in k_gpd_tiled
+    using TG = TileGeom<DIM, ORDER, TZc, TXc, TYc, kExc>;
+    K.gz0 = h->zc0 - P.D0.Dint - 1 - kExc - TG::HLO;
+    K.gx0 = -kExc - TG::HLO;
+    K.gy0 = DIM == 3 ? -kExc - TG::HLO : 0;
     K.TZ = h->TZ;
     K.TX = h->TX;
     K.TY = h->TY;
@@ -557,6 +591,38 @@ struct Impl {
     f.a_c = (float)(-0.25 * N);
     f.b_c = (float)(1.0 + 0.5 * N);
     return f;
+  }
+
+  // 2D fold + filter on register columns for up to 6 passes per axis; false
+  // when the configuration needs the LDS tile kernel instead.
+  template <int NP>
+  static void cols(bfpic_ctx* h, const FoldK<R>& K, const FiltK& fk, const Fields<R>& Jf) {
+    using TG = TileGeom<2, ORDER, kT2Z, kT2X, 1, kExc>;
+    constexpr int FX = 64 - 2 * NP;
+    // windows are rows of tiles: tile row t holds output rows gz0 + t TZ ...
+    const int tz_lo = floor_div(-K.gz0, kT2Z), tz_hi = floor_div(h->nz - K.gz0, kT2Z);
+    const int nseg = tz_hi - tz_lo + 1, nbx = (int)cdiv(h->nx, FX);
+    const int64_t nw = (int64_t)nseg * nbx;
+    k_fold_filter_cols<R, NP, kT2Z, kT2X, TG::LZ, TG::LX><<<(unsigned)cdiv(nw, 4), 256, 0, h->stream>>>(
+        h->g, K, fk, Jf, tz_lo, nseg, nbx, h->ntz_max);
+  }
+  static bool fold_filter_cols(bfpic_ctx* h, const FoldK<R>& K, const FiltK& fk,
+                               const Fields<R>& Jf) {
+    if constexpr (DIM != 2) {
+      return false;
+    } else {
+      if (!h->tiled) return false;
+      switch (fk.H) {
+        case 0: cols<0>(h, K, fk, Jf); return true;
+        case 1: cols<1>(h, K, fk, Jf); return true;
+        case 2: cols<2>(h, K, fk, Jf); return true;
+        case 3: cols<3>(h, K, fk, Jf); return true;
+        case 4: cols<4>(h, K, fk, Jf); return true;
+        case 5: cols<5>(h, K, fk, Jf); return true;
+        case 6: cols<6>(h, K, fk, Jf); return true;
+        default: return false;
+      }
+    }
   }
 
   static int one_step(bfpic_ctx* h) {
@@ -581,20 +647,29 @@ struct Impl {
       T.ntx = h->ntx;
       T.nty = h->nty;
       T.zc0 = h->zc0;
+      T.strag = h->strag;
+      T.nstrag = h->counts + 4;
       if (DIM == 2)
         k_gpd_tiled<R, 2, ORDER, kT2Z, kT2X, 1, kExc>
-            <<<T.ntiles, 256, h->lds_tiled, h->stream>>>(P, F, S, O, T, (R*)h->scratch);
+            <<<T.ntiles, 256, h->lds_tiled, h->stream>>>(P, F, S, T, (R*)h->scratch);
       else
         k_gpd_tiled<R, 3, ORDER, kT3, kT3, kT3, kExc>
-            <<<T.ntiles, 256, h->lds_tiled, h->stream>>>(P, F, S, O, T, (R*)h->scratch);
+            <<<T.ntiles, 256, h->lds_tiled, h->stream>>>(P, F, S, T, (R*)h->scratch);
       HIPCHK(h, hipGetLastError());
     }
-    int64_t nglob = h->tiled && h->ntz > 0 ? h->tail_bound : h->slots_bound;
-    if (nglob > 0) {
-      Timer t(h, 1);
-      k_gpd_global<R, DIM, ORDER><<<(unsigned)cdiv(nglob, 256), 256, 0, h->stream>>>(
-          P, F, S, O, h->counts, h->tiled && h->ntz > 0 ? 1 : 0);
-      HIPCHK(h, hipGetLastError());
+    {
+      // unsorted tail and stragglers (or every slot when not tiled); the
+      // straggler count is only known on the device, so the grid strides
+      const bool tl = h->tiled && h->ntz > 0;
+      int64_t nglob = tl ? h->tail_bound : h->slots_bound;
+      unsigned nb = (unsigned)std::min<int64_t>(std::max<int64_t>(cdiv(nglob, 256), tl ? 256 : 1),
+                                                 4096);
+      if (tl || nglob > 0) {
+        Timer t(h, 1);
+        k_gpd_global<R, DIM, ORDER><<<nb, 256, 0, h->stream>>>(
+            P, F, S, O, h->counts, tl ? 1 : 0, tl ? h->strag : nullptr, h->counts + 4);
+        HIPCHK(h, hipGetLastError());
+      }
     }
     {
       Timer t(h, 2);
@@ -603,20 +678,21 @@ struct Impl {
       Fields<R> Jf;
       for (int c = 0; c < 3; c++) Jf.F[c] = (R*)h->Jf[c];
       for (int c = 3; c < 6; c++) Jf.F[c] = nullptr;
-      if (DIM == 2) {
+      if (DIM == 2 && fold_filter_cols(h, K, fk, Jf)) {
+      } else if (DIM == 2) {
         int nbz = (int)cdiv(h->nz + 1, kF2Z), nbx = (int)cdiv(h->nx, kF2X);
         size_t lds = 2 * sizeof(R) * (kF2Z + 2 * fk.H) * (kF2X + 2 * fk.H);
-        k_fold_filter<R, 2, kF2Z, kF2X, 1><<<nbz * nbx, 256, lds, h->stream>>>(g, K, fk, Jf, nbz,
+        k_fold_filter<R, 2, kF2Z, kF2X, 1, kT2Z, kT2X, 1><<<nbz * nbx, 256, lds, h->stream>>>(g, K, fk, Jf, nbz,
                                                                              nbx, 1);
       } else {
         int nbz = (int)cdiv(h->nz + 1, kF3), nbx = (int)cdiv(h->nx, kF3),
             nby = (int)cdiv(h->ny, kF3);
         size_t lds = 2 * sizeof(R) * (size_t)(kF3 + 2 * fk.H) * (kF3 + 2 * fk.H) * (kF3 + 2 * fk.H);
-        k_fold_filter<R, 3, kF3, kF3, kF3><<<nbz * nbx * nby, 256, lds, h->stream>>>(
+        k_fold_filter<R, 3, kF3, kF3, kF3, kT3, kT3, kT3><<<nbz * nbx * nby, 256, lds, h->stream>>>(
             g, K, fk, Jf, nbz, nbx, nby);
       }
       k_ovf_clear<R><<<1024, 256, 0, h->stream>>>(g, O);
-      k_ovf_reset<<<1, 1, 0, h->stream>>>(h->ovf_rows);
+      k_ovf_reset<<<1, 1, 0, h->stream>>>(h->ovf_rows, h->counts + 4);
       HIPCHK(h, hipGetLastError());
     }
     {
@@ -699,7 +775,12 @@ struct Impl {
       HIPCHK(h, hipMemsetAsync(h->Jo[c], 0, grid * rs, h->stream));
     }
     HIPCHK(h, hipMemsetAsync(h->counts, 0, 16 * 4, h->stream));
-    k_ovf_reset<<<1, 1, 0, h->stream>>>(h->ovf_rows);
+    if (h->tiled) {
+      const int64_t tile_bytes = 3 * (int64_t)h->LV * rs;
+      HIPCHK(h, hipMemsetAsync((char*)h->scratch + h->maxtiles * tile_bytes, 0,
+                               (int64_t)h->ntx * h->nty * tile_bytes, h->stream));
+    }
+    k_ovf_reset<<<1, 1, 0, h->stream>>>(h->ovf_rows, h->counts + 4);
     if (laser) {
       LaserK K;
       K.a0 = laser->a0;
@@ -932,13 +1013,13 @@ extern "C" int bfpic_create(const bfpic_config* cfg, int64_t cap, void* workspac
   // the filter kernels may need more than 64 KB of LDS (3D, FP64, many passes)
   {
     int lim = (int)h->lds_limit;
-    hipFuncSetAttribute((const void*)k_fold_filter<float, 2, kF2Z, kF2X, 1>,
+    hipFuncSetAttribute((const void*)k_fold_filter<float, 2, kF2Z, kF2X, 1, kT2Z, kT2X, 1>,
                         hipFuncAttributeMaxDynamicSharedMemorySize, lim);
-    hipFuncSetAttribute((const void*)k_fold_filter<double, 2, kF2Z, kF2X, 1>,
+    hipFuncSetAttribute((const void*)k_fold_filter<double, 2, kF2Z, kF2X, 1, kT2Z, kT2X, 1>,
                         hipFuncAttributeMaxDynamicSharedMemorySize, lim);
-    hipFuncSetAttribute((const void*)k_fold_filter<float, 3, kF3, kF3, kF3>,
+    hipFuncSetAttribute((const void*)k_fold_filter<float, 3, kF3, kF3, kF3, kT3, kT3, kT3>,
                         hipFuncAttributeMaxDynamicSharedMemorySize, lim);
-    hipFuncSetAttribute((const void*)k_fold_filter<double, 3, kF3, kF3, kF3>,
+    hipFuncSetAttribute((const void*)k_fold_filter<double, 3, kF3, kF3, kF3, kT3, kT3, kT3>,
                         hipFuncAttributeMaxDynamicSharedMemorySize, lim);
     hipFuncSetAttribute((const void*)k_filter_grid<2, kF2Z, kF2X, 1>,
                         hipFuncAttributeMaxDynamicSharedMemorySize, lim);

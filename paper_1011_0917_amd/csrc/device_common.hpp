@@ -54,6 +54,20 @@ __device__ __forceinline__ uint64_t splitmix64(uint64_t seed, uint64_t n) {
   return z ^ (z >> 31);
 }
 
+// Division by a runtime-invariant divisor d >= 1 for 0 <= n < 2^31
+// (Granlund & Montgomery 1994): l = ceil(log2 d), m = 2^32 (2^l - d) / d + 1,
+// n / d = (umulhi(m, n) + n) >> l.  The host fills (m, l); d = 1 has m = l = 0.
+struct FastDiv {
+  uint32_t m;
+  int l;
+  int d;
+};
+
+__device__ __forceinline__ int fdiv(const FastDiv& f, int n) {
+  uint32_t t = __umulhi(f.m, (uint32_t)n);
+  return (int)((t + (uint32_t)n) >> f.l);
+}
+
 // Particle identity: id = ((k * nyy + l) * nx + j) * ppc + s for lattice
 // column k, transverse cells (j, l) and slot s.  The generator counter of
 // axis a (0 z, 1 x, 2 y) is 4 id + a + 1.
@@ -65,16 +79,26 @@ struct LatticeP {
   uint64_t seed;
   int ppc, nx, nyy;
   int load;  // 0 random, 1 centred
+  FastDiv dppc, dnx, dnyy;
 };
 
 __device__ __forceinline__ Birth decode_id(const LatticeP& L, int id) {
   Birth b;
-  int q = id / L.ppc;
-  b.j = q % L.nx;
-  q /= L.nx;
-  b.l = q % L.nyy;
-  b.k = q / L.nyy;
+  int q = fdiv(L.dppc, id);
+  int r = fdiv(L.dnx, q);
+  b.j = q - r * L.nx;
+  int t = fdiv(L.dnyy, r);
+  b.l = r - t * L.nyy;
+  b.k = t;
   return b;
+}
+
+// Wrap into [0, n) for x in (-n, 2n); other values take the full modulo.
+__device__ __forceinline__ int wrap_small(int x, int n) {
+  if (x < 0) x += n;
+  else if (x >= n) x -= n;
+  if ((unsigned)x >= (unsigned)n) x = wrapi(x, n);
+  return x;
 }
 
 template <typename R>
@@ -112,27 +136,37 @@ struct Drift {
   R Dfrac;
 };
 
-// Ion partner position: its birth spot minus the drift (x, y never move).
+// Ion partner position from its birth cell and in-cell offsets r: the birth
+// spot minus the drift (x, y never move).
 template <typename R, int DIM>
-__device__ __forceinline__ Pos<R> ion_pos(const LatticeP& L, int id, const Birth& b,
-                                          const Drift<R>& D) {
+__device__ __forceinline__ Pos<R> ion_at(const Birth& b, const R r[3], const Drift<R>& D) {
   Pos<R> p;
   p.c[0] = b.k - D.Dint;
-  p.o[0] = birth_offset<R>(L, id, 0) - D.Dfrac;  // exact: both multiples of 2^-24
+  p.o[0] = r[0] - D.Dfrac;  // exact in FP32: both are multiples of 2^-24
   if (p.o[0] < (R)0) {
     p.o[0] += (R)1;
     p.c[0] -= 1;
   }
   p.c[1] = b.j;
-  p.o[1] = birth_offset<R>(L, id, 1);
-  if (DIM == 3) {
-    p.c[2] = b.l;
-    p.o[2] = birth_offset<R>(L, id, 2);
-  } else {
-    p.c[2] = 0;
-    p.o[2] = (R)0;
-  }
+  p.o[1] = r[1];
+  p.c[2] = DIM == 3 ? b.l : 0;
+  p.o[2] = DIM == 3 ? r[2] : (R)0;
   return p;
+}
+
+template <typename R, int DIM>
+__device__ __forceinline__ void birth_offsets(const LatticeP& L, int id, R r[3]) {
+  r[0] = birth_offset<R>(L, id, 0);
+  r[1] = birth_offset<R>(L, id, 1);
+  r[2] = DIM == 3 ? birth_offset<R>(L, id, 2) : (R)0;
+}
+
+template <typename R, int DIM>
+__device__ __forceinline__ Pos<R> ion_pos(const LatticeP& L, int id, const Birth& b,
+                                          const Drift<R>& D) {
+  R r[3];
+  birth_offsets<R, DIM>(L, id, r);
+  return ion_at<R, DIM>(b, r, D);
 }
 
 // Electron position = ion partner + peculiar displacement xi (cells).
@@ -202,10 +236,14 @@ struct PushC {
   R qdt2;         // q dt / 2 (q = -1)
 };
 
+// Reciprocal: the hardware estimate (1 ulp) in FP32, exact division in FP64.
+__device__ __forceinline__ float rcp(float x) { return __builtin_amdgcn_rcpf(x); }
+__device__ __forceinline__ double rcp(double x) { return 1.0 / x; }
+
 template <typename R>
 __device__ __forceinline__ R gamma_minus_gb(const PushC<R>& P, R dux, R duy, R duz) {
   R c = (R)2 * P.ub * duz + (dux * dux + duy * duy + duz * duz);
-  return c / (P.gb + sqrt(P.gb2 + c));
+  return c * rcp(P.gb + sqrt(P.gb2 + c));
 }
 
 template <typename R>
@@ -216,9 +254,9 @@ __device__ __forceinline__ void boris_split(const PushC<R>& P, const R E[3], con
   R my = du[1] + P.qdt2 * E[1];
   R mz = du[2] + P.qdt2 * E[2];
   R g = P.gb + gamma_minus_gb(P, mx, my, mz);
-  R f = P.qdt2 / g;
+  R f = P.qdt2 * rcp(g);
   R tx = f * B[0], ty = f * B[1], tz = f * B[2];
-  R sfac = (R)2 / ((R)1 + (tx * tx + ty * ty + tz * tz));
+  R sfac = (R)2 * rcp((R)1 + (tx * tx + ty * ty + tz * tz));
   // u' = u- + u- x t, with u-_z = ub + mz
   R px = mx + (my * tz - (P.ub * ty + mz * ty));
   R py = my + ((P.ub * tx + mz * tx) - mx * tz);
@@ -233,11 +271,11 @@ __device__ __forceinline__ void boris_split(const PushC<R>& P, const R E[3], con
   du[2] = qz + P.qdt2 * E[2];
   R dg = gamma_minus_gb(P, du[0], du[1], du[2]);
   gam = P.gb + dg;
-  R ig = (R)1 / gam;
+  R ig = rcp(gam);
   dv[0] = du[0] * ig;
   dv[1] = du[1] * ig;
   R u2 = du[0] * du[0] + du[1] * du[1] + du[2] * du[2];
-  dv[2] = (((R)2 + P.gb * dg) * du[2] - P.ub * u2) / ((gam + P.gb) * gam * P.gb);
+  dv[2] = (((R)2 + P.gb * dg) * du[2] - P.ub * u2) * (ig * rcp((gam + P.gb) * P.gb));
 }
 
 // XCD-aware block -> work item map: consecutive work items land on the same

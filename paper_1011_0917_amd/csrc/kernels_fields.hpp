@@ -25,39 +25,38 @@ struct FoldK {
   Ovf<R> o;
 };
 
-template <typename R, int DIM>
+// Candidate tiles of a node along one axis: the regions are spaced T apart
+// and are L <= 2 T long, so node offset q (from the region origin of tile 0)
+// lies in tile h = q / T at local q - h T, and also in tile h - 1 at local
+// q - h T + T when that is below L.
+template <typename R, int DIM, int TZ, int TX, int TY>
 __device__ __forceinline__ R fold_at(const FoldK<R>& K, const Geo& g, int comp, int i, int j,
                                      int k) {
   R acc = (R)0;
-  if (g.periodic_z) i = wrapi(i, g.nz);  // halo rows of the filter may lie beyond the seam
+  if (g.periodic_z) i = wrap_small(i, g.nz);  // halo rows of the filter may lie beyond the seam
   if (K.ntiles > 0) {
     int qz = i - K.gz0;
-    if (g.periodic_z) qz = wrapi(qz, g.nz);
-    int qx = wrapi(j - K.gx0, g.nx);
-    int qy = DIM == 3 ? wrapi(k - K.gy0, g.ny) : 0;
-    int hz = qz >= 0 ? qz / K.TZ : -((-qz + K.TZ - 1) / K.TZ);
-    int hx = qx / K.TX, hy = DIM == 3 ? qy / K.TY : 0;
-    const int dzmax = (K.LZ - 1) / K.TZ, dxmax = (K.LX - 1) / K.TX;
-    const int dymax = DIM == 3 ? (K.LY - 1) / K.TY : 0;
-    for (int dz_ = 0; dz_ <= dzmax; dz_++) {
-      int tz = hz - dz_;
-      int rz = qz - tz * K.TZ;
-      if (g.periodic_z) {
-        tz = wrapi(tz, K.ntz);
-        rz = wrapi(i - (K.gz0 + tz * K.TZ), g.nz);
-      }
-      if (tz < 0 || tz >= K.ntz || rz < 0 || rz >= K.LZ) continue;
-      for (int dx_ = 0; dx_ <= dxmax; dx_++) {
-        int tx = wrapi(hx - dx_, K.ntx);
-        int rx = wrapi(j - (K.gx0 + tx * K.TX), g.nx);
+    if (g.periodic_z) qz = wrap_small(qz, g.nz);
+    const int qx = wrap_small(j - K.gx0, g.nx);
+    const int qy = DIM == 3 ? wrap_small(k - K.gy0, g.ny) : 0;
+    const int hz = qz >= 0 ? qz / TZ : -((TZ - 1 - qz) / TZ);
+    const int hx = qx / TX, hy = DIM == 3 ? qy / TY : 0;
+    const int lz = qz - hz * TZ, lx = qx - hx * TX, ly = qy - hy * TY;
+#pragma unroll
+    for (int a = 0; a < 2; a++) {
+      int tz = hz - a, rz = lz + a * TZ;
+      if (g.periodic_z && tz < 0) tz += K.ntz;
+      if (tz < 0 || tz >= K.ntz || rz >= K.LZ) continue;
+#pragma unroll
+      for (int b = 0; b < 2; b++) {
+        int tx = hx - b, rx = lx + b * TX;
+        if (tx < 0) tx += K.ntx;
         if (rx >= K.LX) continue;
-        for (int dy_ = 0; dy_ <= dymax; dy_++) {
-          int ty = 0, ry = 0;
-          if (DIM == 3) {
-            ty = wrapi(hy - dy_, K.nty);
-            ry = wrapi(k - (K.gy0 + ty * K.TY), g.ny);
-            if (ry >= K.LY) continue;
-          }
+#pragma unroll
+        for (int c = 0; c < (DIM == 3 ? 2 : 1); c++) {
+          int ty = hy - c, ry = ly + c * TY;
+          if (ty < 0) ty += K.nty;
+          if (DIM == 3 && ry >= K.LY) continue;
           int t = (tz * K.ntx + tx) * K.nty + ty;
           acc += K.scratch[((int64_t)t * 3 + comp) * K.LV + (rz * K.LX + rx) * K.LY + ry];
         }
@@ -75,7 +74,8 @@ __device__ __forceinline__ R fold_at(const FoldK<R>& K, const Geo& g, int comp, 
 // Filter: per axis N passes of (1/4, 1/2, 1/4) then (-N/4, 1 + N/2, -N/4)
 // when compensating; outside an open z domain the current counts as zero.
 // One workgroup filters an FZ x FX [x FY] output tile of one component with
-// a halo of H = N (+1) nodes, all passes in LDS.
+// a halo of H = N (+1) nodes, all passes in LDS.  Work is laid out as rows
+// (one wave each) by lanes along the contiguous axis (x in 2D, y in 3D).
 struct FiltK {
   int passes, comp;  // N and the compensation flag
   int H;
@@ -87,34 +87,44 @@ __device__ void filter_tile(const Geo& g, const FiltK& fk, int half_z, int i0, i
                             const Src& src, R* out, R* lds) {
   const int H = fk.H;
   const int NZ = FZ + 2 * H, NX = FX + 2 * H, NY = DIM == 3 ? FY + 2 * H : 1;
-  const int NV = NZ * NX * NY;
+  const int LN = DIM == 3 ? NY : NX;       // lane axis length
+  const int NR = DIM == 3 ? NZ * NX : NZ;  // rows
+  const int NV = NR * LN;
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6, nw = blockDim.x >> 6;
   R* A = lds;
   R* Bq = lds + NV;
-  for (int v = threadIdx.x; v < NV; v += blockDim.x) {
-    int r = v / (NX * NY), rem = v - r * (NX * NY);
-    int s = rem / NY, u = rem - s * NY;
-    int i = i0 - H + r, j = j0 - H + s, k = DIM == 3 ? k0 - H + u : 0;
-    bool ok = g.periodic_z || in_domain(g, half_z, i);
-    A[v] = ok ? src(i, j, k) : (R)0;
+  for (int row = wv; row < NR; row += nw) {
+    const int rz = DIM == 3 ? row / NX : row;
+    const int rx = DIM == 3 ? row - rz * NX : 0;
+    const int i = i0 - H + rz;
+    const bool ok = g.periodic_z || in_domain(g, half_z, i);
+    for (int c = lane; c < LN; c += 64) {
+      const int j = DIM == 3 ? j0 - H + rx : j0 - H + c;
+      const int k = DIM == 3 ? k0 - H + c : 0;
+      A[row * LN + c] = ok ? src(i, j, k) : (R)0;
+    }
   }
   __syncthreads();
   const int naxes = DIM == 3 ? 3 : 2;
+  const int npass = fk.passes + (fk.comp && fk.passes > 0 ? 1 : 0);
   for (int axis = 0; axis < naxes; axis++) {
-    const int npass = fk.passes + (fk.comp && fk.passes > 0 ? 1 : 0);
-    const int stride = axis == 0 ? NX * NY : (axis == 1 ? NY : 1);
+    // neighbour stride in A and the length of the axis
+    const int stride = axis == 0 ? (DIM == 3 ? NX * NY : NX) : (axis == 1 && DIM == 3 ? NY : 1);
+    const int len = axis == 0 ? NZ : (axis == 1 ? NX : NY);
     for (int p = 0; p < npass; p++) {
-      R a = p < fk.passes ? (R)0.25 : (R)fk.a_c;
-      R b = p < fk.passes ? (R)0.5 : (R)fk.b_c;
-      for (int v = threadIdx.x; v < NV; v += blockDim.x) {
-        int r = v / (NX * NY), rem = v - r * (NX * NY);
-        int s = rem / NY, u = rem - s * NY;
-        int pos = axis == 0 ? r : (axis == 1 ? s : u);
-        int len = axis == 0 ? NZ : (axis == 1 ? NX : NY);
-        R val;
-        if (pos == 0 || pos == len - 1) val = A[v];
-        else val = a * A[v - stride] + b * A[v] + a * A[v + stride];
-        if (axis == 0 && !g.periodic_z && !in_domain(g, half_z, i0 - H + r)) val = (R)0;
-        Bq[v] = val;
+      const R a = p < fk.passes ? (R)0.25 : (R)fk.a_c;
+      const R b = p < fk.passes ? (R)0.5 : (R)fk.b_c;
+      for (int row = wv; row < NR; row += nw) {
+        const int rz = DIM == 3 ? row / NX : row;
+        const int rx = DIM == 3 ? row - rz * NX : 0;
+        const bool zero_row = axis == 0 && !g.periodic_z && !in_domain(g, half_z, i0 - H + rz);
+        for (int c = lane; c < LN; c += 64) {
+          const int v = row * LN + c;
+          const int pos = axis == 0 ? rz : (axis == 1 ? (DIM == 3 ? rx : c) : c);
+          R val = (pos == 0 || pos == len - 1) ? A[v]
+                                               : a * A[v - stride] + b * A[v] + a * A[v + stride];
+          Bq[v] = zero_row ? (R)0 : val;
+        }
       }
       __syncthreads();
       R* t = A;
@@ -122,28 +132,36 @@ __device__ void filter_tile(const Geo& g, const FiltK& fk, int half_z, int i0, i
       Bq = t;
     }
   }
-  for (int v = threadIdx.x; v < FZ * FX * (DIM == 3 ? FY : 1); v += blockDim.x) {
-    int fy = DIM == 3 ? FY : 1;
-    int r = v / (FX * fy), rem = v - r * (FX * fy);
-    int s = rem / fy, u = rem - s * fy;
-    int i = i0 + r, j = j0 + s, k = DIM == 3 ? k0 + u : 0;
-    if (!in_domain(g, half_z, i) || j >= g.nx || (DIM == 3 && k >= g.ny)) continue;
-    out[gidx(g, i, j, k)] = A[((r + H) * NX + (s + H)) * NY + (DIM == 3 ? u + H : 0)];
+  const int fy = DIM == 3 ? FY : 1;
+  const int ORW = DIM == 3 ? FZ * FX : FZ;  // output rows
+  const int OLN = DIM == 3 ? fy : FX;
+  for (int row = wv; row < ORW; row += nw) {
+    const int r = DIM == 3 ? row / FX : row;
+    const int s = DIM == 3 ? row - r * FX : 0;
+    const int i = i0 + r;
+    if (!in_domain(g, half_z, i)) continue;
+    for (int c = lane; c < OLN; c += 64) {
+      const int j = DIM == 3 ? j0 + s : j0 + c;
+      const int k = DIM == 3 ? k0 + c : 0;
+      if (j >= g.nx || (DIM == 3 && k >= g.ny)) continue;
+      const int v = DIM == 3 ? ((r + H) * NX + (s + H)) * NY + (c + H) : (r + H) * NX + (c + H);
+      out[gidx(g, i, j, k)] = A[v];
+    }
   }
   __syncthreads();
 }
 
-template <typename R, int DIM>
+template <typename R, int DIM, int TZ, int TX, int TY>
 struct FoldSrc {
   const FoldK<R>* K;
   Geo g;
   int comp;
   __device__ __forceinline__ R operator()(int i, int j, int k) const {
-    return fold_at<R, DIM>(*K, g, comp, i, j, k);
+    return fold_at<R, DIM, TZ, TX, TY>(*K, g, comp, i, j, k);
   }
 };
 
-template <typename R, int DIM, int FZ, int FX, int FY>
+template <typename R, int DIM, int FZ, int FX, int FY, int TZ, int TX, int TY>
 __global__ __launch_bounds__(256) void k_fold_filter(Geo g, FoldK<R> K, FiltK fk, Fields<R> Jf,
                                                      int nbz, int nbx, int nby) {
   extern __shared__ __align__(16) unsigned char smem_raw[];
@@ -153,8 +171,140 @@ __global__ __launch_bounds__(256) void k_fold_filter(Geo g, FoldK<R> K, FiltK fk
   int by = b % nby, bx = (b / nby) % nbx, bz = b / (nby * nbx);
   int i0 = bz * FZ, j0 = bx * FX, k0 = by * FY;
   for (int comp = 0; comp < 3; comp++) {
-    FoldSrc<R, DIM> src{&K, g, comp};
+    FoldSrc<R, DIM, TZ, TX, TY> src{&K, g, comp};
     filter_tile<R, DIM, FZ, FX, FY>(g, fk, half_z_j(comp), i0, j0, k0, src, Jf.F[comp], lds);
+  }
+}
+
+// 2D fold + filter on register columns.  A wave owns a window of TZ output
+// rows (the z extent of one row of co-moving tiles, so that every row's
+// candidate tiles and local row are fixed at compile time) by 64 - 2 NP
+// output columns.  Lane c holds column j0 - NP + c over the TZ + 2 NP rows
+// the filter needs; the z passes run in registers, the x passes exchange
+// neighbours across lanes.  After NP passes along an axis the values NP or
+// more nodes inside the window are exact; those are stored.  Tile rows
+// outside the co-moving range read a row of zero tiles kept past the last
+// tile, so every load is unconditional.  No LDS and no barriers.
+//
+// The fold sums, per node, the tile whose core holds it, then the tile
+// before it in z, each with the two x candidates, then the overflow grid:
+// the order of fold_at.
+template <typename R, int NP, int TZ, int TX, int LZ, int LX>
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(1, 4))) void k_fold_filter_cols(Geo g, FoldK<R> K, FiltK fk,
+                                                          Fields<R> Jf, int tz_lo, int nseg,
+                                                          int nbx, int zero_row) {
+  constexpr int H = NP, L = TZ + 2 * H;
+  constexpr int FX = 64 - 2 * H;
+  static_assert(H <= TZ && LZ <= 2 * TZ, "window geometry");
+  const int lane = threadIdx.x & 63;
+  // the window index is the same for the whole wave: keep it (and the row
+  // arithmetic derived from it) in scalar registers
+  const int w = __builtin_amdgcn_readfirstlane(xcd_remap(blockIdx.x, gridDim.x) * 4 +
+                                               (int)(threadIdx.x >> 6));
+  if (w >= nseg * nbx) return;  // the whole wave leaves together
+  const int sw = w / nbx, bx = w - sw * nbx;
+  const int tzw = tz_lo + sw;
+  const int iw0 = K.gz0 + tzw * TZ;  // first output row of the window
+  const int j0 = bx * FX;
+  const int j = j0 - H + lane;
+  const bool out_lane = lane >= H && lane < 64 - H && j < g.nx;
+  const int jl = lane == 0 ? 63 : lane - 1, jr = lane == 63 ? 0 : lane + 1;
+  // x candidates of this lane's column: tile hx at lx, tile hx - 1 at lx + TX
+  constexpr int LV = LZ * LX;  // one component of a tile region (2D)
+  const int qx = wrap_small(j - K.gx0, g.nx);
+  const int hx = qx / TX, lx = qx - hx * TX;
+  const int txb = hx > 0 ? hx - 1 : K.ntx - 1;
+  const bool vb = lx + TX < LX;
+  const int xa = hx * 3 * LV + lx;
+  const int xb = vb ? txb * 3 * LV + lx + TX : xa;
+  const int jw = wrap_small(j, g.nx);
+  // tile rows tzw - 2 .. tzw + 1
+  int64_t trow[4];
+#pragma unroll
+  for (int d = 0; d < 4; d++) {
+    int t = tzw + d - 2;
+    if (g.periodic_z) t = wrap_small(t, K.ntz);
+    else if (t < 0 || t >= K.ntz) t = zero_row;
+    if (K.ntiles == 0) t = zero_row;
+    trow[d] = (int64_t)t * K.ntx * 3 * LV;
+  }
+  const int r0 = K.o.rows[0], r1 = K.o.rows[1];
+  const int ilo = iw0 - H, ihi = iw0 - H + L - 1;  // rows of the window (unwrapped)
+  const bool any_ovf = g.periodic_z ? r1 >= r0 : (ihi >= r0 && ilo <= r1);
+#pragma unroll 1
+  for (int comp = 0; comp < 3; comp++) {
+    const int hz = half_z_j(comp);
+    const bool interior = g.periodic_z || (ilo >= 0 && ihi <= row_hi(g, hz));
+    // per-lane pointers to row 0 of each candidate tile; rows are then
+    // compile-time offsets
+    const R* pA[4];
+    const R* pB[4];
+#pragma unroll
+    for (int d = 0; d < 4; d++) {
+      pA[d] = K.scratch + trow[d] + comp * LV + xa;
+      pB[d] = K.scratch + trow[d] + comp * LV + xb;
+    }
+    R v[L];
+#pragma unroll
+    for (int r = 0; r < L; r++) {
+      const int q = r - H;
+      const int dt = q >= 0 ? q / TZ : -((TZ - 1 - q) / TZ);
+      const int lz = q - dt * TZ;
+      R acc = pA[dt + 2][lz * LX];
+      const R a1 = pB[dt + 2][lz * LX];
+      acc += vb ? a1 : (R)0;
+      if (lz + TZ < LZ) {
+        const R b0 = pA[dt + 1][(lz + TZ) * LX], b1 = pB[dt + 1][(lz + TZ) * LX];
+        acc += b0;
+        acc += vb ? b1 : (R)0;
+      }
+      v[r] = acc;
+    }
+    if (any_ovf) {
+#pragma unroll
+      for (int r = 0; r < L; r++) {
+        int i = iw0 - H + r;
+        if (g.periodic_z) i = wrap_small(i, g.nz);
+        if (i >= r0 && i <= r1 && i >= -kGuard && i <= g.nz + kGuard)
+          v[r] += K.o.J[comp][(int64_t)(i + kGuard) * g.plane + jw];
+      }
+    }
+    if (!interior) {
+#pragma unroll
+      for (int r = 0; r < L; r++)
+        if (!in_domain(g, hz, iw0 - H + r)) v[r] = (R)0;
+    }
+#pragma unroll
+    for (int p = 0; p < NP; p++) {
+      const R a = p < fk.passes ? (R)0.25 : (R)fk.a_c;
+      const R b = p < fk.passes ? (R)0.5 : (R)fk.b_c;
+      R prev = v[0];
+#pragma unroll
+      for (int r = 1; r < L - 1; r++) {
+        const R cur = v[r];
+        v[r] = a * prev + b * cur + a * v[r + 1];
+        prev = cur;
+      }
+      if (!interior) {
+#pragma unroll
+        for (int r = 0; r < L; r++)
+          if (!in_domain(g, hz, iw0 - H + r)) v[r] = (R)0;
+      }
+    }
+    R* out = Jf.F[comp];
+#pragma unroll
+    for (int r = H; r < H + TZ; r++) {
+      R x = v[r];
+#pragma unroll
+      for (int p = 0; p < NP; p++) {
+        const R a = p < fk.passes ? (R)0.25 : (R)fk.a_c;
+        const R b = p < fk.passes ? (R)0.5 : (R)fk.b_c;
+        const R l = __shfl(x, jl), rr = __shfl(x, jr);
+        x = a * l + b * x + a * rr;
+      }
+      const int i = iw0 + r - H;
+      if (out_lane && in_domain(g, hz, i)) out[(int64_t)(i + kGuard) * g.plane + j] = x;
+    }
   }
 }
 
@@ -175,10 +325,11 @@ __global__ __launch_bounds__(256) void k_ovf_clear(Geo g, Ovf<R> o) {
   }
 }
 
-__global__ void k_ovf_reset(int* rows) {
+__global__ void k_ovf_reset(int* rows, int* nstrag) {
   if (threadIdx.x == 0 && blockIdx.x == 0) {
     rows[0] = 0x7fffffff;
     rows[1] = -0x7fffffff;
+    *nstrag = 0;
   }
 }
 

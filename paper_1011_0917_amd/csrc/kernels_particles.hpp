@@ -78,7 +78,10 @@ struct LdsSink {
   R* s;  // [3][LZ*LX*LY]: Jx Jy Jz
   int lv;
   __device__ __forceinline__ void add(int comp, int i, int j, int k, R v) const {
-    if (v != (R)0) atomicAdd(&s[comp * lv + (i * LX + j) * LY + k], v);
+#ifndef BFPIC_LDS_ADD_ALL
+    if (v != (R)0)
+#endif
+      atomicAdd(&s[comp * lv + (i * LX + j) * LY + k], v);
   }
 };
 
@@ -256,31 +259,40 @@ __device__ __forceinline__ void deposit2d(const StepK<R>& P, const Snk& snk, con
 }
 
 // --------------------------------------------------------------------------
-// Pair deposit, linear shape, 2D: the electron's shape factors written as its
-// partner's plus a difference dS computed from the displacement xi itself.
-// With S(d) = Rc(d + 1) - Rc(d), Rc = clamp(., 0, 1):
-//   S(d + xi) - S(d) = dRc(d + 1) - dRc(d),
-//   dRc(t) = clamp(xi, -t, 1 - t) - clamp(0, -t, 1 - t),
-// whose bounds are (integer - offset) of the partner, so no step subtracts
-// two nearly equal positions.  Electron minus partner then reads
-//   We - Wi = dSi eta + eps fxi + eps eta   (Jz),
-// eps = dS(new) - dS(old) along z, eta = (dS_x(old) + dS_x(new)) / 2,
-// and the electron's own Jx, Jy use Si + dS.  Window: 4 nodes per axis from
-// the lowest cell among partner and electron, old and new.
+// Pair deposit, linear shape, 2D.  The electron sits at its partner's position
+// plus xi; with u = o + xi (o the partner's offset in its cell) the linear
+// shape factors of nodes k = -1..2 of the partner's cell differ from the
+// partner's by
+//   u < 0:      dS = (-u, 2 o + xi, -o, 0)
+//   0 <= u < 1: dS = (0, -xi, xi, 0)
+//   1 <= u < 2: dS = (0, o - 1, 2 (1 - o) - xi, (o - 1) + xi)
+// (partner weights (0, 1 - o, o, 0)), so electron minus partner is formed
+// from xi and exact offset distances only, never from two nearly equal
+// positions.  Only Jz carries the pair difference (the partner moves along z
+// only); Jx and Jy are the electron's own and use its plain stencil.
 // --------------------------------------------------------------------------
 template <typename R>
-__device__ __forceinline__ R dclamp(R xi, R lo, R hi) {
-  return fmin(fmax(xi, lo), hi) - fmin(fmax((R)0, lo), hi);
+__device__ __forceinline__ bool lin_pair(R o, R xi, R Si[4], R dS[4]) {
+  R u = o + xi;
+  bool lo = u < (R)0, hi = u >= (R)1;
+  R om1 = o - (R)1;
+  Si[0] = (R)0;
+  Si[1] = (R)1 - o;
+  Si[2] = o;
+  Si[3] = (R)0;
+  dS[0] = lo ? -u : (R)0;
+  dS[1] = lo ? (o + o) + xi : (hi ? om1 : -xi);
+  dS[2] = lo ? -o : (hi ? (R)-2 * om1 - xi : xi);
+  dS[3] = hi ? om1 + xi : (R)0;
+  return u >= (R)-1 && u < (R)2;
 }
 
-// partner weight S(o - k) and electron-minus-partner dS at node c + k
+// shift a 4-node array by s in {0, 1} into a 4-node window (entry 3 drops)
 template <typename R>
-__device__ __forceinline__ void pair_node(R o, R xi, int k, R& Si, R& dS) {
-  R d = o - (R)k;
-  R ad = fabs(d);
-  Si = ad < (R)1 ? (R)1 - ad : (R)0;
-  R qm = (R)(k - 1) - o, q0 = (R)k - o, qp = (R)(k + 1) - o;
-  dS = dclamp(xi, qm, q0) - dclamp(xi, q0, qp);
+__device__ __forceinline__ R at4(const R a[4], int s, int m) {
+  R v0 = m < 4 ? a[m < 4 ? m : 0] : (R)0;
+  R v1 = m >= 1 ? a[m >= 1 ? m - 1 : 0] : (R)0;
+  return s ? v1 : v0;
 }
 
 template <typename R, class Snk>
@@ -288,65 +300,73 @@ __device__ __forceinline__ bool deposit2d_pair(const StepK<R>& P, const Snk& snk
                                                const Pos<R>& e0, const Pos<R>& e1,
                                                const Pos<R>& i0, const Pos<R>& i1,
                                                const R xi0[3], const R xi1[3], R w, R vy) {
-  int mz = min(min(i0.c[0], i1.c[0]), min(e0.c[0], e1.c[0]));
-  int Mz = max(max(i0.c[0], i1.c[0]), max(e0.c[0], e1.c[0]));
-  int mx = min(i0.c[1], min(e0.c[1], e1.c[1]));
-  int Mx = max(i0.c[1], max(e0.c[1], e1.c[1]));
-  if (Mz - mz > 2 || Mx - mx > 2) return false;
-  R Si0[4], Si1[4], dS0[4], dS1[4], Sx[4], dX0[4], dX1[4];
+  // z: partner old / new, electron = partner + xi
+  R Sa[4], da[4], Sb[4], db[4], Sx[4], dx0[4], dx1[4];
+  bool ok = lin_pair(i0.o[0], xi0[0], Sa, da);
+  ok &= lin_pair(i1.o[0], xi1[0], Sb, db);
+  ok &= lin_pair(i0.o[1], xi0[1], Sx, dx0);
+  R unused[4];
+  ok &= lin_pair(i0.o[1], xi1[1], unused, dx1);
+  const int W = min(i0.c[0], i1.c[0]) - 1;
+  const int s0 = i0.c[0] - 1 - W, s1 = i1.c[0] - 1 - W;  // each 0 or 1
+  // a shifted array loses its top node, which must then be empty
+  ok &= !(s0 && da[3] != (R)0) && !(s1 && db[3] != (R)0);
+  ok &= (unsigned)s0 <= 1u && (unsigned)s1 <= 1u;
+  if (!ok) return false;
+  R dSi[4], eps[4];
 #pragma unroll
-  for (int j = 0; j < 4; j++) {
-    pair_node(i0.o[0], xi0[0], mz + j - i0.c[0], Si0[j], dS0[j]);
-    pair_node(i1.o[0], xi1[0], mz + j - i1.c[0], Si1[j], dS1[j]);
-    R s_unused;
-    pair_node(i0.o[1], xi0[1], mx + j - i0.c[1], Sx[j], dX0[j]);
-    pair_node(i0.o[1], xi1[1], mx + j - i0.c[1], s_unused, dX1[j]);
+  for (int m = 0; m < 4; m++) {
+    dSi[m] = P.ion_moves ? at4(Sb, s1, m) - at4(Sa, s0, m) : (R)0;
+    eps[m] = at4(db, s1, m) - at4(da, s0, m);
   }
-  const int rz = bc[0] + (mz - e0.c[0]), rx = bc[1] + (mx - e0.c[1]);
-  const R kz = P.kj[0] * w, kx = P.kj[1] * w;
-  const bool ion = P.ion_moves;
-  // Jz: prefix along z of kz (We - Wi)
+  const int rz = bc[0] + (W - e0.c[0]), rx = bc[1] + (i0.c[1] - 1 - e0.c[1]);
+  const R kz = P.kj[0] * w;
+  // Jz(a + 1/2, b) = kz sum_{a' <= a} (dSi eta + eps fx_e) = kz (CSi[a] eta[b] + Ceps[a] fxe[b])
+  R CSi[3], Ce[3];
+  CSi[0] = kz * dSi[0];
+  Ce[0] = kz * eps[0];
+#pragma unroll
+  for (int a2 = 1; a2 < 3; a2++) {
+    CSi[a2] = CSi[a2 - 1] + kz * dSi[a2];
+    Ce[a2] = Ce[a2 - 1] + kz * eps[a2];
+  }
 #pragma unroll
   for (int b = 0; b < 4; b++) {
-    R eta = (R)0.5 * (dX0[b] + dX1[b]);
-    R acc = (R)0;
+    const R eta = (R)0.5 * (dx0[b] + dx1[b]);
+    const R fxe = Sx[b] + eta;
 #pragma unroll
-    for (int a = 0; a < 3; a++) {
-      R dSi = ion ? Si1[a] - Si0[a] : (R)0;
-      R eps = dS1[a] - dS0[a];
-      acc += kz * (dSi * eta + eps * Sx[b] + eps * eta);
-      snk.add(2, rz + a, rx + b, 0, acc);
-    }
+    for (int a2 = 0; a2 < 3; a2++) snk.add(2, rz + a2, rx + b, 0, CSi[a2] * eta + Ce[a2] * fxe);
   }
-  // electron shape factors along z: old Si0 + dS0, change dSi + eps
-  R S0e[4], dSe[4];
+  // Jx, Jy: the electron alone, on its own 3-node stencil.
+  //   Jx(a, b + 1/2) = fz[a] * kx sum_{b' <= b} dSx[b'],  fz = S0z + dSz / 2
+  //   Wy = S0z S0x + (dSz S0x + S0z dSx) / 2 + dSz dSx / 3 = fz fx + dSz dSx / 12
+  constexpr int NS = 3;
+  R S0z[NS], dSz[NS], S0x[NS], dSx[NS];
+  int bz = esk_axis<R, 1>(e0.c[0], e0.o[0], e1.c[0], e1.o[0], S0z, dSz);
+  int bx = esk_axis<R, 1>(e0.c[1], e0.o[1], e1.c[1], e1.o[1], S0x, dSx);
+  const int ez = bc[0] + (bz - e0.c[0]), ex = bc[1] + (bx - e0.c[1]);
+  const R kx = P.kj[1] * w;
+  R fz[NS], fx[NS];
 #pragma unroll
-  for (int a = 0; a < 4; a++) {
-    S0e[a] = Si0[a] + dS0[a];
-    dSe[a] = (ion ? Si1[a] - Si0[a] : (R)0) + (dS1[a] - dS0[a]);
+  for (int m = 0; m < NS; m++) {
+    fz[m] = S0z[m] + (R)0.5 * dSz[m];
+    fx[m] = S0x[m] + (R)0.5 * dSx[m];
   }
-  // Jx: prefix along x of kx dSx_e (S0z_e + dSz_e / 2), dSx_e = dX1 - dX0
+  const R cx0 = kx * dSx[0], cx1 = cx0 + kx * dSx[1];
 #pragma unroll
-  for (int a = 0; a < 4; a++) {
-    R fz = S0e[a] + (R)0.5 * dSe[a];
-    R acc = (R)0;
-#pragma unroll
-    for (int b = 0; b < 3; b++) {
-      acc += kx * (dX1[b] - dX0[b]) * fz;
-      snk.add(0, rz + a, rx + b, 0, acc);
-    }
+  for (int a2 = 0; a2 < NS; a2++) {
+    snk.add(0, ez + a2, ex + 0, 0, fz[a2] * cx0);
+    snk.add(0, ez + a2, ex + 1, 0, fz[a2] * cx1);
   }
   if (vy != (R)0) {
     const R ky = -P.ky2d * w * vy;
+    const R ky12 = ky * (R)(1.0 / 12.0);
 #pragma unroll
-    for (int a = 0; a < 4; a++)
+    for (int a2 = 0; a2 < NS; a2++) {
+      const R za = ky * fz[a2], zb = ky12 * dSz[a2];
 #pragma unroll
-      for (int b = 0; b < 4; b++) {
-        R s0x = Sx[b] + dX0[b], dsx = dX1[b] - dX0[b];
-        R wy = S0e[a] * s0x + (R)0.5 * (dSe[a] * s0x + S0e[a] * dsx) +
-               dSe[a] * dsx * (R)(1.0 / 3.0);
-        snk.add(1, rz + a, rx + b, 0, ky * wy);
-      }
+      for (int b = 0; b < NS; b++) snk.add(1, ez + a2, ex + b, 0, za * fx[b] + zb * dSx[b]);
+    }
   }
   return true;
 }
@@ -507,53 +527,64 @@ __device__ __forceinline__ void note_rows(const Ovf<R>& o, const Geo& g, int ce,
 }
 
 // --------------------------------------------------------------------------
-// Global path: every slot in [first, *n_slots) (the unsorted tail, or all
-// particles when the grid is too small to tile).
+// Global path: the unsorted tail [first, counts[0]) plus the stragglers the
+// tiled kernel listed (particles whose stencil left their tile's region), or
+// every slot when the grid is too small to tile.  Fields are read and the
+// current is accumulated in global memory (the overflow sink).
 // --------------------------------------------------------------------------
 template <typename R, int DIM, int ORDER>
 __global__ __launch_bounds__(256) void k_gpd_global(StepK<R> P, Fields<R> F, PSoA<R> S, Ovf<R> O,
-                                                    const int* counts, int from_sorted) {
-  const int n = counts[0];
+                                                    const int* counts, int from_sorted,
+                                                    const int* strag, const int* nstrag) {
   const int first = from_sorted ? counts[1] : 0;
-  int p = first + blockIdx.x * blockDim.x + threadIdx.x;
-  if (p >= n) return;
-  int id = S.id[p];
-  if (id < 0) return;
-  R xi[3], du[3], w;
-  load_state(S, p, xi, du, w);
-  Birth b = decode_id(P.L, id);
-  Pos<R> i0 = ion_pos<R, DIM>(P.L, id, b, P.D0);
-  Pos<R> i1 = ion_pos<R, DIM>(P.L, id, b, P.D1);
-  Pos<R> e0 = add_xi<R, DIM>(i0, xi);
+  const int ntail = counts[0] - first;
+  const int total = ntail + (strag ? *nstrag : 0);
   GlobalFetch<R> f{(const R* const*)F.F, P.g};
-  GlobalSink<R> s{O, P.g};
-  int bc[3] = {e0.c[0], e0.c[1], e0.c[2]};
-  note_rows<R, ORDER>(O, P.g, e0.c[0], i0.c[0]);
-  bool dead = particle_step<R, DIM, ORDER>(P, f, s, bc, e0, i0, i1, xi, du, w);
-  store_state<R, DIM>(S, p, xi, du, dead);
+  GlobalSink<R> sk{O, P.g};
+  for (int q = blockIdx.x * blockDim.x + threadIdx.x; q < total; q += gridDim.x * blockDim.x) {
+    const int p = q < ntail ? first + q : strag[q - ntail];
+    const int id = S.id[p];
+    if (id < 0) continue;
+    R xi[3], du[3], w;
+    load_state(S, p, xi, du, w);
+    Birth b = decode_id(P.L, id);
+    R r[3];
+    birth_offsets<R, DIM>(P.L, id, r);
+    Pos<R> i0 = ion_at<R, DIM>(b, r, P.D0);
+    Pos<R> i1 = ion_at<R, DIM>(b, r, P.D1);
+    Pos<R> e0 = add_xi<R, DIM>(i0, xi);
+    int bc[3] = {e0.c[0], e0.c[1], e0.c[2]};
+    note_rows<R, ORDER>(O, P.g, e0.c[0], i0.c[0]);
+    bool dead = particle_step<R, DIM, ORDER>(P, f, sk, bc, e0, i0, i1, xi, du, w);
+    store_state<R, DIM>(S, p, xi, du, dead);
+  }
 }
 
 // --------------------------------------------------------------------------
 // Tiled path.  One workgroup per co-moving tile of TZ x TX [x TY] cells.  The
 // tile's E, B and a zeroed J accumulator are staged in LDS over the tile plus
-// a margin of E_ cells of peculiar excursion and the stencil reach; each
-// particle of the tile gathers from LDS and deposits with LDS atomics; the J
-// region is then stored whole to the tile's scratch slot, to be folded into
-// the grid by the filter kernel.  Particles whose stencil leaves the region
-// take the global path.
+// a margin of EXC cells of peculiar excursion, one row of drift and the
+// stencil reach; each particle of the tile gathers from LDS and deposits with
+// LDS atomics; the J region is then stored whole to the tile's scratch slot,
+// to be folded into the grid by the filter kernel.  A particle whose stencil
+// would leave the region is appended to the straggler list instead and is
+// advanced by the global path in the same step.
 // --------------------------------------------------------------------------
 struct TileK {
   const int* start;  // particle range of tile t: [start[t], start[t+1])
   int ntiles, ntx, nty;
   int zc0;           // first co-moving z cell of tile row 0
+  int* strag;        // straggler slots
+  int* nstrag;       // their count
 };
 
 // Region of a tile: its cells, the excursion margin EXC on each side, one row
 // of plasma drift along z, and the stencil reach HLO below / HHI above a cell
-// (HHI includes the spare node of the 4-node pair window).
+// (the 4-node pair window reaches two nodes below the partner's cell when the
+// partner crosses a cell, and one spare node above).
 template <int DIM, int ORDER, int TZ, int TX, int TY, int EXC>
 struct TileGeom {
-  static constexpr int HLO = ORDER;
+  static constexpr int HLO = ORDER + 1;
   static constexpr int HHI = ORDER + 2;
   static constexpr int LZ = TZ + 2 * EXC + 1 + HLO + HHI;
   static constexpr int LX = TX + 2 * EXC + HLO + HHI;
@@ -562,8 +593,8 @@ struct TileGeom {
 };
 
 template <typename R, int DIM, int ORDER, int TZ, int TX, int TY, int EXC>
-__global__ __launch_bounds__(256) void k_gpd_tiled(StepK<R> P, Fields<R> F, PSoA<R> S, Ovf<R> O,
-                                                   TileK T, R* scratch) {
+__global__ __launch_bounds__(256) void k_gpd_tiled(StepK<R> P, Fields<R> F, PSoA<R> S, TileK T,
+                                                   R* scratch) {
   using TG = TileGeom<DIM, ORDER, TZ, TX, TY, EXC>;
   constexpr int LZ = TG::LZ, LX = TG::LX, LY = TG::LY, LV = TG::LV;
   extern __shared__ __align__(16) unsigned char smem_raw[];
@@ -577,54 +608,81 @@ __global__ __launch_bounds__(256) void k_gpd_tiled(StepK<R> P, Fields<R> F, PSoA
   const int gx0 = tx * TX - EXC - TG::HLO;
   const int gy0 = DIM == 3 ? ty * TY - EXC - TG::HLO : 0;
   const Geo& g = P.g;
-  for (int v = threadIdx.x; v < 6 * LV; v += blockDim.x) {
-    int comp = v / LV, r = v - comp * LV;
-    int rz = r / (LX * LY), rem = r - rz * (LX * LY);
-    int rx = rem / LY, ry = rem - rx * LY;
-    int64_t n = gidx(g, gz0 + rz, gx0 + rx, gy0 + ry);
-    sF[v] = n < 0 ? (R)0 : F.F[comp][n];
+  // stage E, B: one wave per (component, row), lanes along the contiguous axis
+  {
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6, nw = blockDim.x >> 6;
+    constexpr int NIN = DIM == 3 ? LY : LX;        // lane axis
+    constexpr int NOUT = DIM == 3 ? LZ * LX : LZ;  // rows per component
+    for (int q = wv; q < 6 * NOUT; q += nw) {
+      const int comp = q / NOUT, r = q - comp * NOUT;
+      const int rz = DIM == 3 ? r / LX : r;
+      const int rx = DIM == 3 ? r - rz * LX : 0;
+      int i = gz0 + rz;
+      bool valid = true;
+      if (g.periodic_z) i = wrap_small(i, g.nz);
+      else valid = i >= -kGuard && i <= g.nz + kGuard;
+      const int64_t rowbase = (int64_t)(i + kGuard) * g.plane;
+      for (int v = lane; v < NIN; v += 64) {
+        R val = (R)0;
+        if (valid) {
+          if (DIM == 3) {
+            int j = wrap_small(gx0 + rx, g.nx), k = wrap_small(gy0 + v, g.ny);
+            val = F.F[comp][rowbase + (int64_t)j * g.ny + k];
+          } else {
+            int j = wrap_small(gx0 + v, g.nx);
+            val = F.F[comp][rowbase + j];
+          }
+        }
+        if (DIM == 3) sF[comp * LV + (rz * LX + rx) * LY + v] = val;
+        else sF[comp * LV + rz * LX + v] = val;
+      }
+    }
   }
   for (int v = threadIdx.x; v < 3 * LV; v += blockDim.x) sJ[v] = (R)0;
   __syncthreads();
   LdsFetch<R, LX, LY> lf{sF, LV};
   LdsSink<R, LX, LY> ls{sJ, LV};
-  GlobalFetch<R> gf{(const R* const*)F.F, g};
-  GlobalSink<R> gs{O, g};
   const int p0 = T.start[t], p1 = T.start[t + 1];
   for (int p = p0 + threadIdx.x; p < p1; p += blockDim.x) {
-    int id = S.id[p];
+    const int id = S.id[p];
     if (id < 0) continue;
-    R xi[3], du[3], w;
-    load_state(S, p, xi, du, w);
+    R xi[3];
+    xi[0] = S.xi[0][p];
+    xi[1] = S.xi[1][p];
+    xi[2] = DIM == 3 ? S.xi[2][p] : (R)0;
     Birth b = decode_id(P.L, id);
-    Pos<R> i0 = ion_pos<R, DIM>(P.L, id, b, P.D0);
-    Pos<R> i1 = ion_pos<R, DIM>(P.L, id, b, P.D1);
+    R r[3];
+    birth_offsets<R, DIM>(P.L, id, r);
+    Pos<R> i0 = ion_at<R, DIM>(b, r, P.D0);
     Pos<R> e0 = add_xi<R, DIM>(i0, xi);
     // cells relative to the LDS region (wrapped where the axis is periodic)
     int rz = e0.c[0] - gz0, riz = i0.c[0] - gz0;
     if (g.periodic_z) {
-      rz = wrapi(rz, g.nz);
-      riz = wrapi(riz, g.nz);
+      rz = wrap_small(rz, g.nz);
+      riz = wrap_small(riz, g.nz);
     }
-    int rx = wrapi(e0.c[1] - gx0, g.nx), rix = wrapi(i0.c[1] - gx0, g.nx);
-    int ry = 0, riy = 0;
+    const int rx = wrap_small(e0.c[1] - gx0, g.nx), rix = wrap_small(i0.c[1] - gx0, g.nx);
     bool inside = rz >= TG::HLO && rz < LZ - TG::HHI && riz >= TG::HLO && riz < LZ - TG::HHI &&
                   rx >= TG::HLO && rx < LX - TG::HHI && rix >= TG::HLO && rix < LX - TG::HHI;
+    int ry = 0;
     if (DIM == 3) {
-      ry = wrapi(e0.c[2] - gy0, g.ny);
-      riy = wrapi(i0.c[2] - gy0, g.ny);
+      ry = wrap_small(e0.c[2] - gy0, g.ny);
+      const int riy = wrap_small(i0.c[2] - gy0, g.ny);
       inside = inside && ry >= TG::HLO && ry < LY - TG::HHI && riy >= TG::HLO &&
                riy < LY - TG::HHI;
     }
-    bool dead;
-    if (inside) {
-      int bc[3] = {rz, rx, ry};
-      dead = particle_step<R, DIM, ORDER>(P, lf, ls, bc, e0, i0, i1, xi, du, w);
-    } else {
-      int bc[3] = {e0.c[0], e0.c[1], e0.c[2]};
-      note_rows<R, ORDER>(O, g, e0.c[0], i0.c[0]);
-      dead = particle_step<R, DIM, ORDER>(P, gf, gs, bc, e0, i0, i1, xi, du, w);
+    if (!inside) {
+      T.strag[atomicAdd(T.nstrag, 1)] = p;
+      continue;
     }
+    R du[3];
+    du[0] = S.du[0][p];
+    du[1] = S.du[1][p];
+    du[2] = S.du[2][p];
+    const R w = S.w[p];
+    Pos<R> i1 = ion_at<R, DIM>(b, r, P.D1);
+    int bc[3] = {rz, rx, ry};
+    bool dead = particle_step<R, DIM, ORDER>(P, lf, ls, bc, e0, i0, i1, xi, du, w);
     store_state<R, DIM>(S, p, xi, du, dead);
   }
   __syncthreads();
