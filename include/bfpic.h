@@ -211,11 +211,15 @@ int bfpic_num_slots(bfpic_ctx* h, int64_t* n);
 int bfpic_get_particles(bfpic_ctx* h, double* z, double* x, double* y, double* ux,
                         double* uy, double* uz, double* w, int32_t* id);
 
-/* Forces a particle sort now (co-moving tile-major keys, ties by id). */
+/* Forces a particle sort now: co-moving tile-major cell keys, ties by id;
+ * then, inside each tile of at most 512 cells, particles are ordered by their
+ * rank within their cell and then by cell, so that consecutive particles lie
+ * in distinct cells. */
 int bfpic_sort(bfpic_ctx* h);
 
 /* The last sort: the key and id of every source slot, and perm[d] = source
- * slot of destination d (live particles only).  Device arrays of at least
+ * slot of destination d (live particles only, in the order bfpic_sort
+ * describes).  Device arrays of at least
  * bfpic_num_slots entries before that sort.  *n (host) receives the number of
  * source slots and *n_live the number of sorted live particles; *tz_min,
  * *ntz (host) the co-moving tile rows used for the keys.  Synchronises. */

@@ -52,7 +52,16 @@ constexpr int kExc = 1;
 constexpr int kT2Z = 16, kT2X = 32;
 constexpr int kT3 = 8;
 constexpr int kF2Z = 16, kF2X = 64;  // filter output tiles
-constexpr int kColsRows = 16;        // output rows per wave of the 2D register filter
+// Threads per tile of the gather-push-deposit kernel (measured: FP32 runs
+// best with 512, FP64, whose LDS footprint is larger, with 256).
+#ifndef BFPIC_GPD_THREADS32
+#define BFPIC_GPD_THREADS32 512
+#endif
+#ifndef BFPIC_GPD_THREADS64
+#define BFPIC_GPD_THREADS64 256
+#endif
+template <typename R>
+constexpr int kGpdThreads = sizeof(R) == 4 ? BFPIC_GPD_THREADS32 : BFPIC_GPD_THREADS64;
 constexpr int kF3 = 8;
 constexpr int kNumTimers = 7;
 
@@ -112,6 +121,7 @@ struct bfpic_ctx {
   void* mur_save = nullptr;
   int64_t last_sort_nkeys = 0;
   int last_sort_tzmin = 0, last_sort_ntz = 0;
+  const int* final_perm = nullptr;  // destination -> source slot of the last sort
   bool have_sort = false;
   // timing
   bool timing = false;
@@ -240,7 +250,8 @@ static void derive(bfpic_ctx* h, const bfpic_config* c) {
   h->maxtiles = (int64_t)h->ntz_max * h->ntx * h->nty;
   h->maxkeys = h->maxtiles * h->TZ * h->TX * h->TY;
   size_t rs = h->fp64 ? 8 : 4;
-  h->lds_tiled = (size_t)9 * h->LV * rs;
+  // staged E, B in the working precision; currents in FP64 in 2D
+  h->lds_tiled = (size_t)6 * h->LV * rs + (size_t)3 * h->LV * (h->dim == 2 ? 8 : rs);
 }
 
 struct Layout {
@@ -514,7 +525,16 @@ struct Impl {
                                                         h->perm);
     k_sort_cells<<<(unsigned)cdiv(nkeys, 256), 256, 0, h->stream>>>(h->off, src.id, h->perm,
                                                                     (int)nkeys);
-    k_permute<R><<<(unsigned)nb, 256, 0, h->stream>>>(src, dst, h->perm, h->off + nkeys);
+    // tiles with at most kInterleaveCells cells are interleaved by rank within
+    // cell; the result goes to `rank` (free once the scatter has run)
+    const int* fin = h->perm;
+    if (cpt <= kInterleaveCells) {
+      k_sort_interleave<<<(unsigned)(ntz * h->ntx * h->nty), 256, 0, h->stream>>>(
+          h->off, h->perm, h->rank, (int)cpt);
+      fin = h->rank;
+    }
+    h->final_perm = fin;
+    k_permute<R><<<(unsigned)nb, 256, 0, h->stream>>>(src, dst, fin, h->off + nkeys);
     int ntiles = ntz * h->ntx * h->nty;
     k_tile_starts<<<(unsigned)cdiv(ntiles + 1, 256), 256, 0, h->stream>>>(
         h->off, h->tile_start, ntiles, (int)cpt, h->counts, (int)nkeys);
@@ -650,11 +670,11 @@ struct Impl {
       T.strag = h->strag;
       T.nstrag = h->counts + 4;
       if (DIM == 2)
-        k_gpd_tiled<R, 2, ORDER, kT2Z, kT2X, 1, kExc>
-            <<<T.ntiles, 256, h->lds_tiled, h->stream>>>(P, F, S, T, (R*)h->scratch);
+        k_gpd_tiled<R, 2, ORDER, kT2Z, kT2X, 1, kExc, kGpdThreads<R>>
+            <<<T.ntiles, kGpdThreads<R>, h->lds_tiled, h->stream>>>(P, F, S, T, (R*)h->scratch);
       else
-        k_gpd_tiled<R, 3, ORDER, kT3, kT3, kT3, kExc>
-            <<<T.ntiles, 256, h->lds_tiled, h->stream>>>(P, F, S, T, (R*)h->scratch);
+        k_gpd_tiled<R, 3, ORDER, kT3, kT3, kT3, kExc, kGpdThreads<R>>
+            <<<T.ntiles, kGpdThreads<R>, h->lds_tiled, h->stream>>>(P, F, S, T, (R*)h->scratch);
       HIPCHK(h, hipGetLastError());
     }
     {
@@ -1037,23 +1057,26 @@ extern "C" int bfpic_create(const bfpic_config* cfg, int64_t cap, void* workspac
     }
   }
   if (h->tiled && h->lds_tiled > 65536) {
-    // opt in to large dynamic LDS for the tiled kernels
-    if (h->fp64) {
-      if (h->dim == 3 && h->order == 2)
-        hipFuncSetAttribute((const void*)k_gpd_tiled<double, 3, 2, kT3, kT3, kT3, kExc>,
-                            hipFuncAttributeMaxDynamicSharedMemorySize, (int)h->lds_tiled);
-      if (h->dim == 3 && h->order == 1)
-        hipFuncSetAttribute((const void*)k_gpd_tiled<double, 3, 1, kT3, kT3, kT3, kExc>,
-                            hipFuncAttributeMaxDynamicSharedMemorySize, (int)h->lds_tiled);
-    } else {
-      if (h->dim == 3 && h->order == 2)
-        hipFuncSetAttribute((const void*)k_gpd_tiled<float, 3, 2, kT3, kT3, kT3, kExc>,
-                            hipFuncAttributeMaxDynamicSharedMemorySize, (int)h->lds_tiled);
-      if (h->dim == 3 && h->order == 1)
-        hipFuncSetAttribute((const void*)k_gpd_tiled<float, 3, 1, kT3, kT3, kT3, kExc>,
-                            hipFuncAttributeMaxDynamicSharedMemorySize, (int)h->lds_tiled);
-    }
+    // opt in to large dynamic LDS for the tiled kernel of this configuration
+    const void* fn = nullptr;
+    const bool f64 = h->fp64;
+    if (h->dim == 2 && h->order == 1)
+      fn = f64 ? (const void*)k_gpd_tiled<double, 2, 1, kT2Z, kT2X, 1, kExc, kGpdThreads<double>>
+               : (const void*)k_gpd_tiled<float, 2, 1, kT2Z, kT2X, 1, kExc, kGpdThreads<float>>;
+    else if (h->dim == 2)
+      fn = f64 ? (const void*)k_gpd_tiled<double, 2, 2, kT2Z, kT2X, 1, kExc, kGpdThreads<double>>
+               : (const void*)k_gpd_tiled<float, 2, 2, kT2Z, kT2X, 1, kExc, kGpdThreads<float>>;
+    else if (h->order == 1)
+      fn = f64 ? (const void*)k_gpd_tiled<double, 3, 1, kT3, kT3, kT3, kExc, kGpdThreads<double>>
+               : (const void*)k_gpd_tiled<float, 3, 1, kT3, kT3, kT3, kExc, kGpdThreads<float>>;
+    else
+      fn = f64 ? (const void*)k_gpd_tiled<double, 3, 2, kT3, kT3, kT3, kExc, kGpdThreads<double>>
+               : (const void*)k_gpd_tiled<float, 3, 2, kT3, kT3, kT3, kExc, kGpdThreads<float>>;
+    if (hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)h->lds_tiled) !=
+        hipSuccess)
+      h->tiled = false;
   }
+
   *out = h;
   return BFPIC_OK;
 }
@@ -1153,7 +1176,8 @@ extern "C" int bfpic_last_sort(bfpic_ctx* h, int32_t* key_dev, int32_t* id_dev, 
   int nl = 0;
   HIPCHK(h, hipMemcpyAsync(&nl, h->off + h->last_sort_nkeys, 4, hipMemcpyDeviceToHost, h->stream));
   HIPCHK(h, hipStreamSynchronize(h->stream));
-  HIPCHK(h, hipMemcpyAsync(perm_dev, h->perm, (size_t)nl * 4, hipMemcpyDeviceToDevice, h->stream));
+  HIPCHK(h, hipMemcpyAsync(perm_dev, h->final_perm, (size_t)nl * 4, hipMemcpyDeviceToDevice,
+                           h->stream));
   HIPCHK(h, hipStreamSynchronize(h->stream));
   *n = nsrc;
   *n_live = nl;

@@ -10,6 +10,8 @@
 // rigid drift D of the lab-rest plasma (plus the window displacement).
 #pragma once
 
+#include <type_traits>
+
 #include "device_common.hpp"
 
 namespace bfpic {
@@ -73,17 +75,28 @@ struct GlobalFetch {
   }
 };
 
-template <typename R, int LX, int LY>
+// LDS current accumulator of element type A.  FP32 atomic adds on LDS are
+// serialised lane by lane on this hardware, FP64 ones are not, so where the
+// LDS budget allows the currents accumulate in FP64 (one rounding to the
+// working precision at the flush) and every lane adds unconditionally; FP32
+// accumulation skips zero addends to keep the serialised lanes few.
+template <typename A, int LX, int LY>
 struct LdsSink {
-  R* s;  // [3][LZ*LX*LY]: Jx Jy Jz
+  A* s;  // [3][LZ*LX*LY]: Jx Jy Jz
   int lv;
+  template <typename R>
   __device__ __forceinline__ void add(int comp, int i, int j, int k, R v) const {
-#ifndef BFPIC_LDS_ADD_ALL
-    if (v != (R)0)
-#endif
-      atomicAdd(&s[comp * lv + (i * LX + j) * LY + k], v);
+    if constexpr (sizeof(A) == 4) {
+      if (v == (R)0) return;
+    }
+    atomicAdd(&s[comp * lv + (i * LX + j) * LY + k], (A)v);
   }
 };
+
+// Accumulator type of the tiled kernel's LDS currents (2D: FP64; 3D keeps
+// the working precision so that the staged fields and currents fit in LDS).
+template <typename R, int DIM>
+using LdsAcc = typename std::conditional<DIM == 2, double, R>::type;
 
 template <typename R>
 struct GlobalSink {
@@ -592,14 +605,15 @@ struct TileGeom {
   static constexpr int LV = LZ * LX * LY;
 };
 
-template <typename R, int DIM, int ORDER, int TZ, int TX, int TY, int EXC>
-__global__ __launch_bounds__(256) void k_gpd_tiled(StepK<R> P, Fields<R> F, PSoA<R> S, TileK T,
-                                                   R* scratch) {
+template <typename R, int DIM, int ORDER, int TZ, int TX, int TY, int EXC, int NT>
+__global__ __launch_bounds__(NT) void k_gpd_tiled(StepK<R> P, Fields<R> F, PSoA<R> S, TileK T,
+                                                  R* scratch) {
   using TG = TileGeom<DIM, ORDER, TZ, TX, TY, EXC>;
   constexpr int LZ = TG::LZ, LX = TG::LX, LY = TG::LY, LV = TG::LV;
+  using A = LdsAcc<R, DIM>;
   extern __shared__ __align__(16) unsigned char smem_raw[];
   R* sF = reinterpret_cast<R*>(smem_raw);
-  R* sJ = sF + 6 * LV;
+  A* sJ = reinterpret_cast<A*>(sF + 6 * LV);  // 6 LV sizeof(R) is a multiple of 8
   const int t = xcd_remap(blockIdx.x, T.ntiles);
   const int ty = DIM == 3 ? t % T.nty : 0;
   const int tx = (t / T.nty) % T.ntx;
@@ -608,48 +622,61 @@ __global__ __launch_bounds__(256) void k_gpd_tiled(StepK<R> P, Fields<R> F, PSoA
   const int gx0 = tx * TX - EXC - TG::HLO;
   const int gy0 = DIM == 3 ? ty * TY - EXC - TG::HLO : 0;
   const Geo& g = P.g;
-  // stage E, B: one wave per (component, row), lanes along the contiguous axis
+  // Stage E, B: flat over [comp][rz][rx][ry], PER loads in flight per thread
+  // (unconditional loads from a clamped row, zero where the row lies outside
+  // the stored grid).
   {
-    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6, nw = blockDim.x >> 6;
-    constexpr int NIN = DIM == 3 ? LY : LX;        // lane axis
-    constexpr int NOUT = DIM == 3 ? LZ * LX : LZ;  // rows per component
-    for (int q = wv; q < 6 * NOUT; q += nw) {
-      const int comp = q / NOUT, r = q - comp * NOUT;
-      const int rz = DIM == 3 ? r / LX : r;
-      const int rx = DIM == 3 ? r - rz * LX : 0;
-      int i = gz0 + rz;
-      bool valid = true;
-      if (g.periodic_z) i = wrap_small(i, g.nz);
-      else valid = i >= -kGuard && i <= g.nz + kGuard;
-      const int64_t rowbase = (int64_t)(i + kGuard) * g.plane;
-      for (int v = lane; v < NIN; v += 64) {
-        R val = (R)0;
-        if (valid) {
-          if (DIM == 3) {
-            int j = wrap_small(gx0 + rx, g.nx), k = wrap_small(gy0 + v, g.ny);
-            val = F.F[comp][rowbase + (int64_t)j * g.ny + k];
-          } else {
-            int j = wrap_small(gx0 + v, g.nx);
-            val = F.F[comp][rowbase + j];
-          }
+    constexpr int NST = 6 * LV, PER = 8;
+    for (int base = 0; base < NST; base += PER * NT) {
+      R val[PER];
+#pragma unroll
+      for (int m = 0; m < PER; m++) {
+        const int v = base + m * NT + (int)threadIdx.x;
+        const int vc = v < NST ? v : NST - 1;
+        const int comp = vc / LV, rem = vc - comp * LV;
+        const int rz = rem / (LX * LY), rxy = rem - rz * (LX * LY);
+        const int rx = DIM == 3 ? rxy / LY : rxy;
+        int i = gz0 + rz;
+        bool valid = true;
+        if (g.periodic_z) i = wrap_small(i, g.nz);
+        else {
+          valid = i >= -kGuard && i <= g.nz + kGuard;
+          i = valid ? i : 0;
         }
-        if (DIM == 3) sF[comp * LV + (rz * LX + rx) * LY + v] = val;
-        else sF[comp * LV + rz * LX + v] = val;
+        const int j = wrap_small(gx0 + rx, g.nx);
+        const int k = DIM == 3 ? wrap_small(gy0 + (rxy - rx * LY), g.ny) : 0;
+        const R x = F.F[comp][(int64_t)(i + kGuard) * g.plane + (int64_t)j * g.ny + k];
+        val[m] = valid ? x : (R)0;
+      }
+#pragma unroll
+      for (int m = 0; m < PER; m++) {
+        const int v = base + m * NT + (int)threadIdx.x;
+        if (v < NST) sF[v] = val[m];
       }
     }
   }
-  for (int v = threadIdx.x; v < 3 * LV; v += blockDim.x) sJ[v] = (R)0;
+  for (int v = threadIdx.x; v < 3 * LV; v += NT) sJ[v] = (A)0;
   __syncthreads();
   LdsFetch<R, LX, LY> lf{sF, LV};
-  LdsSink<R, LX, LY> ls{sJ, LV};
+  LdsSink<A, LX, LY> ls{sJ, LV};
   const int p0 = T.start[t], p1 = T.start[t + 1];
-  for (int p = p0 + threadIdx.x; p < p1; p += blockDim.x) {
-    const int id = S.id[p];
+  // the whole state of the next particle is loaded while this one is pushed
+  int p = p0 + (int)threadIdx.x;
+  int id_n = -1;
+  R xn[3] = {(R)0, (R)0, (R)0}, un[3] = {(R)0, (R)0, (R)0}, wn = (R)0;
+  if (p < p1) {
+    id_n = S.id[p];
+    load_state(S, p, xn, un, wn);
+  }
+  for (; p < p1; p += NT) {
+    const int id = id_n;
+    R xi[3] = {xn[0], xn[1], xn[2]}, du[3] = {un[0], un[1], un[2]};
+    const R w = wn;
+    if (p + NT < p1) {
+      id_n = S.id[p + NT];
+      load_state(S, p + NT, xn, un, wn);
+    }
     if (id < 0) continue;
-    R xi[3];
-    xi[0] = S.xi[0][p];
-    xi[1] = S.xi[1][p];
-    xi[2] = DIM == 3 ? S.xi[2][p] : (R)0;
     Birth b = decode_id(P.L, id);
     R r[3];
     birth_offsets<R, DIM>(P.L, id, r);
@@ -675,11 +702,6 @@ __global__ __launch_bounds__(256) void k_gpd_tiled(StepK<R> P, Fields<R> F, PSoA
       T.strag[atomicAdd(T.nstrag, 1)] = p;
       continue;
     }
-    R du[3];
-    du[0] = S.du[0][p];
-    du[1] = S.du[1][p];
-    du[2] = S.du[2][p];
-    const R w = S.w[p];
     Pos<R> i1 = ion_at<R, DIM>(b, r, P.D1);
     int bc[3] = {rz, rx, ry};
     bool dead = particle_step<R, DIM, ORDER>(P, lf, ls, bc, e0, i0, i1, xi, du, w);
@@ -687,7 +709,7 @@ __global__ __launch_bounds__(256) void k_gpd_tiled(StepK<R> P, Fields<R> F, PSoA
   }
   __syncthreads();
   R* dst = scratch + (int64_t)t * 3 * LV;
-  for (int v = threadIdx.x; v < 3 * LV; v += blockDim.x) dst[v] = sJ[v];
+  for (int v = threadIdx.x; v < 3 * LV; v += NT) dst[v] = (R)sJ[v];
 }
 
 // --------------------------------------------------------------------------

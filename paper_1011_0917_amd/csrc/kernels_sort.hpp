@@ -1,6 +1,7 @@
 // kernels_sort.hpp -- particle sort by co-moving tile-major cell key, ties by
 // id: count (atomic rank per key), exclusive scan, scatter, per-cell
-// insertion sort by id (makes the order unique), permute, tile starts.
+// insertion sort by id (makes the order unique), interleave of each tile by
+// rank within cell, permute, tile starts.
 #pragma once
 
 #include "device_common.hpp"
@@ -132,6 +133,63 @@ __global__ __launch_bounds__(256) void k_sort_cells(const int* off, const int* i
       y--;
     }
     perm[y + 1] = pv;
+  }
+}
+
+// Within each tile, reorder the (cell, id)-sorted particles by (rank within
+// their cell, cell): position of rank r of cell c is
+//   sum_{r' < r} #{cells with more than r' particles} + #{c' < c with more than r}.
+// Consecutive particles then sit in distinct cells, so the lanes of a wave
+// add their currents to distinct LDS addresses.  One workgroup per tile of
+// cpt <= kInterleaveCells cells.
+constexpr int kInterleaveCells = 512;
+
+__global__ __launch_bounds__(256) void k_sort_interleave(const int* off, const int* perm,
+                                                         int* out, int cpt) {
+  __shared__ int n[kInterleaveCells];
+  __shared__ int sc[256];
+  __shared__ int red;
+  const int t = threadIdx.x;
+  const int64_t k0 = (int64_t)blockIdx.x * cpt;
+  const int base = off[k0];
+  if (t == 0) red = 0;
+  __syncthreads();
+  int mx = 0;
+  for (int c = t; c < cpt; c += 256) {
+    n[c] = off[k0 + c + 1] - off[k0 + c];
+    mx = max(mx, n[c]);
+  }
+  atomicMax(&red, mx);
+  __syncthreads();
+  const int maxn = red;
+  // each thread owns cells [t * per, t * per + per)
+  const int per = (cpt + 255) / 256;
+  int S = 0;
+  for (int r = 0; r < maxn; r++) {
+    int cntv = 0;
+    for (int m = 0; m < per; m++) {
+      const int c = t * per + m;
+      cntv += (c < cpt && n[c] > r) ? 1 : 0;
+    }
+    sc[t] = cntv;
+    __syncthreads();
+    for (int o = 1; o < 256; o <<= 1) {
+      const int v = t >= o ? sc[t - o] : 0;
+      __syncthreads();
+      sc[t] += v;
+      __syncthreads();
+    }
+    int pos = S + sc[t] - cntv;  // exclusive prefix
+    const int Nr = sc[255];
+    for (int m = 0; m < per; m++) {
+      const int c = t * per + m;
+      if (c < cpt && n[c] > r) {
+        out[base + pos] = perm[off[k0 + c] + r];
+        pos++;
+      }
+    }
+    S += Nr;
+    __syncthreads();
   }
 }
 

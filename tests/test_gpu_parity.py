@@ -138,8 +138,20 @@ def test_boosted_3d_fp32_split_within_tolerance(P):
 
 
 # --------------------------------------------------------------------------
-# Sort: bit-exact against the oracle's stable sort by (key, id)
+# Sort: bit-exact against the oracle's stable sort by (key, id), interleaved
+# inside each tile by rank within cell
 # --------------------------------------------------------------------------
+def interleave_tiles(perm, key, cpt):
+    """Reorder a (key, id)-sorted permutation inside each tile of cpt cells by
+    (rank within cell, cell), the layout the tiled particle kernel reads."""
+    if cpt > 512:
+        return perm
+    k = key[perm]
+    first = np.searchsorted(k, k, side="left")
+    rank = np.arange(len(k)) - first
+    return perm[np.lexsort((k % cpt, rank, k // cpt))]
+
+
 @pytest.mark.parametrize("name,steps", [("boost13_2d_small", 0), ("boost13_2d_small", 37),
                                         ("lab_2d", 50), ("boost100_3d_small", 9)])
 def test_sort_bit_exact(P, name, steps):
@@ -153,8 +165,9 @@ def test_sort_bit_exact(P, name, steps):
         sim.sort()
     s = sim.last_sort()
     keep = s["id"] >= 0
-    perm = O.sort_perm(s["key"], s["id"])
-    assert np.array_equal(s["perm"], perm[: keep.sum()])
+    perm = O.sort_perm(s["key"], s["id"])[: keep.sum()]
+    tz, tx, ty = sim.tile_shape()
+    assert np.array_equal(s["perm"], interleave_tiles(perm, s["key"], tz * tx * ty))
     if steps == 0:
         # identical initial states: the oracle computes the same keys itself
         kw, oi = resolve_oracle(W)
