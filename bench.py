@@ -9,6 +9,8 @@ FP64, per-kernel HIP-event times of the dominant kernel against the HBM
 roofline, and the FP64 oracle timed on the host cores on a bounded sample.
 """
 import argparse
+import glob
+import hashlib
 import json
 import math
 import os
@@ -29,6 +31,51 @@ BYTES_PER_CELL_STEP = {"fp32": 72.0, "fp64": 144.0}  # whole step: E, B r+w, J w
 
 def log(*a):
     print(*a, file=sys.stderr, flush=True)
+
+
+def kernel_source_hash():
+    """sha256 over the HIP sources and the C header (sorted by name)."""
+    h = hashlib.sha256()
+    files = sorted(glob.glob(os.path.join(ROOT, "paper_1011_0917_amd", "csrc", "*")) +
+                   [os.path.join(ROOT, "include", "bfpic.h")])
+    for f in files:
+        with open(f, "rb") as fh:
+            h.update(os.path.basename(f).encode() + b"\0" + fh.read())
+    return h.hexdigest()
+
+
+def measured_traffic(kernel, workload, precision):
+    """HBM bytes per launch of `kernel` from the committed counter summary, or
+    None when the summary is missing or the sources changed since it was taken."""
+    path = os.path.join(ROOT, "profiles", f"{kernel}_{workload}_{precision}_traffic.txt")
+    if not os.path.exists(path):
+        return None
+    vals = {}
+    with open(path) as fh:
+        for line in fh:
+            if ":" in line and not line.startswith("#"):
+                k, v = line.split(":", 1)
+                vals[k.strip()] = v.strip()
+    if vals.get("source_sha256") != kernel_source_hash():
+        return None
+    try:
+        return float(vals["hbm_bytes_per_launch"])
+    except (KeyError, ValueError):
+        return None
+
+
+def copy_calibration(mib):
+    """A plain device copy of known size, for scaling the FETCH_SIZE and
+    WRITE_SIZE counters: reads and writes mib MiB three times."""
+    import torch
+    n = mib * (1 << 20) // 4
+    src = torch.ones(n, dtype=torch.float32, device="cuda")
+    dst = torch.empty_like(src)
+    torch.cuda.synchronize()
+    for _ in range(3):
+        dst.copy_(src)
+    torch.cuda.synchronize()
+    log(f"bench: copy calibration {mib} MiB x 3")
 
 
 def run_gpu(name, precision, steps, warmup, sort_interval, with_kernel_times=True):
@@ -67,7 +114,7 @@ def run_gpu(name, precision, steps, warmup, sort_interval, with_kernel_times=Tru
             "diag_end": d1, "W": W}
 
 
-def cpu_baseline(name, nz_sample=256, steps=6):
+def cpu_baseline(name, nz_sample=256, steps=20):
     """The FP64 oracle, single-threaded, on a slab of the same workload."""
     import oracle as O
     from workloads import WORKLOADS, resolve_oracle, small
@@ -94,6 +141,8 @@ def main():
     ap.add_argument("--sort-interval", type=int, default=50)
     ap.add_argument("--no-fp64", action="store_true")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
+                    help="after the run, copy MIB MiB three times (counter calibration)")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU: this build runs on a single MI355X "
@@ -127,7 +176,11 @@ def main():
         "cell_updates_per_s": cups,
         "step_roofline_frac": step_bytes / (ms_step * 1e-3) / 1e9 / HBM_PEAK_GBS,
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS,
-                     "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS, "traffic": None,
+                     "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
+                     "traffic": measured_traffic("k_gpd_tiled", args.workload, "fp32"),
+                     "traffic_unit": "HBM bytes per launch (FETCH_SIZE + WRITE_SIZE, "
+                                     "scaled by a plain copy)",
+                     "algorithmic_bytes": gpd_bytes,
                      "kernel": "k_gpd_tiled", "kernel_ms": gpd_ms},
         "kernel_ms_per_step": {k: v["ms"] / args.steps for k, v in r32["kernels"].items()},
     }
@@ -142,6 +195,8 @@ def main():
     if not args.no_cpu_baseline:
         log("bench: oracle cpu baseline")
         out["cpu_baseline"] = cpu_baseline(args.workload)
+    if args.copy_calibration > 0:
+        copy_calibration(args.copy_calibration)
     print(json.dumps(out), flush=True)
 
 
