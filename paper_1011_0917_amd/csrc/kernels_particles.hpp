@@ -622,10 +622,38 @@ __global__ __launch_bounds__(NT) void k_gpd_tiled(StepK<R> P, Fields<R> F, PSoA<
   const int gx0 = tx * TX - EXC - TG::HLO;
   const int gy0 = DIM == 3 ? ty * TY - EXC - TG::HLO : 0;
   const Geo& g = P.g;
-  // Stage E, B: flat over [comp][rz][rx][ry], PER loads in flight per thread
-  // (unconditional loads from a clamped row, zero where the row lies outside
-  // the stored grid).
-  {
+  // Stage E, B (unconditional loads from a clamped row, zero where the row
+  // lies outside the stored grid).  2D: one wave per (component, row), lanes
+  // along x, every row of a wave issued before any is stored; the x wrap of a
+  // lane and the row offsets are computed once.
+  if constexpr (DIM == 2) {
+    static_assert(LX <= 64, "one wave spans a staged row");
+    constexpr int NW = NT / 64, NPAIR = 6 * LZ, PERW = (NPAIR + NW - 1) / NW;
+    const int lane = threadIdx.x & 63;
+    const int wv = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
+    const int j = wrap_small(gx0 + (lane < LX ? lane : 0), g.nx);
+    R val[PERW];
+#pragma unroll
+    for (int m = 0; m < PERW; m++) {
+      const int q = wv + m * NW;  // (component, row) pair of this wave
+      const int qc = q < NPAIR ? q : NPAIR - 1;
+      const int comp = qc / LZ, rz = qc - comp * LZ;
+      int i = gz0 + rz;
+      bool valid = true;
+      if (g.periodic_z) i = wrap_small(i, g.nz);
+      else {
+        valid = i >= -kGuard && i <= g.nz + kGuard;
+        i = valid ? i : 0;
+      }
+      const R x = F.F[comp][(int64_t)(i + kGuard) * g.plane + j];
+      val[m] = valid ? x : (R)0;
+    }
+#pragma unroll
+    for (int m = 0; m < PERW; m++) {
+      const int q = wv + m * NW;
+      if (q < NPAIR && lane < LX) sF[q * LX + lane] = val[m];
+    }
+  } else {
     constexpr int NST = 6 * LV, PER = 8;
     for (int base = 0; base < NST; base += PER * NT) {
       R val[PER];
