@@ -78,12 +78,13 @@ def copy_calibration(mib):
     log(f"bench: copy calibration {mib} MiB x 3")
 
 
-def run_gpu(name, precision, steps, warmup, sort_interval, with_kernel_times=True):
+def run_gpu(name, precision, steps, warmup, sort_interval, with_kernel_times=True, det=0):
     import torch
     import paper_1011_0917_amd as P
     from workloads import WORKLOADS, resolve_gpu
     W = WORKLOADS[name]
     cfg, init, _ = resolve_gpu(W, precision=precision, sort_interval=sort_interval)
+    cfg.deterministic = det
     sim = P.Simulation(cfg, capacity=init["capacity"])
     sim.init_boosted_plasma(init["gamma_b"], n_uniform=init["n_lab"], laser=init["laser"])
     sim.pic_step(warmup)
@@ -141,6 +142,8 @@ def main():
     ap.add_argument("--sort-interval", type=int, default=50)
     ap.add_argument("--no-fp64", action="store_true")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-deterministic", action="store_true",
+                    help="skip timing the deterministic (fixed-point current) FP32 form")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="after the run, copy MIB MiB three times (counter calibration)")
     args = ap.parse_args()
@@ -192,6 +195,13 @@ def main():
         out["fp64"] = {"value": pps64, "unit": "particle-steps/s",
                        "ms_per_step": r64["ms"] / r64["steps"]}
         out["fp32_over_fp64"] = pps / pps64
+    if not args.no_deterministic:
+        log("bench: fp32 deterministic (int64 fixed-point currents)")
+        rd = run_gpu(args.workload, "fp32", max(args.steps // 2, 10), args.warmup,
+                     args.sort_interval, with_kernel_times=False, det=1)
+        out["deterministic"] = {
+            "value": rd["particles"] * rd["steps"] / (rd["ms"] * 1e-3),
+            "unit": "particle-steps/s", "ms_per_step": rd["ms"] / rd["steps"]}
     if not args.no_cpu_baseline:
         log("bench: oracle cpu baseline")
         out["cpu_baseline"] = cpu_baseline(args.workload)

@@ -70,7 +70,11 @@ typedef struct bfpic_config {
   int32_t filter_passes;     /* N binomial (1/4,1/2,1/4) passes per axis */
   int32_t filter_compensate; /* 1: one (-N/4, 1+N/2, -N/4) pass per axis */
   int32_t precision;         /* BFPIC_FP64 or BFPIC_FP32_SPLIT */
-  int32_t deterministic;     /* must be 0 (fixed-point deposit not built) */
+  int32_t deterministic;     /* 1: currents are summed as int64 fixed point
+                                (unit 2^-e of the current, e fixed at init
+                                from the largest particle weight), so results
+                                do not depend on the order of atomic adds and
+                                repeat bitwise from run to run */
   int32_t z_boundary;        /* BFPIC_BC_PERIODIC or BFPIC_BC_MUR */
   int32_t ppc;               /* macro-particles per lattice cell */
   int32_t load;              /* BFPIC_LOAD_RANDOM (SplitMix64) or _CENTERED */

@@ -89,6 +89,9 @@ struct bfpic_ctx {
   int LZ = 1, LX = 1, LY = 1, LV = 1;
   int64_t maxtiles = 0, maxkeys = 0;
   size_t lds_tiled = 0, lds_limit = 65536;
+  // deterministic mode: currents summed as int64 in units of 1 / fx_scale
+  bool det = false;
+  double fx_scale = 1.0, fx_inv = 1.0;
   // device buffers
   uint8_t* ws = nullptr;
   int64_t ws_bytes = 0;
@@ -202,8 +205,15 @@ static void set_region(bfpic_ctx* h) {
   h->LY = TG::LY;
 }
 
+// Bytes per element of the tiled kernel's LDS current accumulators, and of
+// the tile current scratch and the overflow grid (the working precision, or
+// int64 in the deterministic mode).
+static size_t acc_bytes(const bfpic_ctx* h) { return h->det || h->fp64 || h->dim == 2 ? 8 : 4; }
+static size_t ovf_bytes(const bfpic_ctx* h) { return h->det || h->fp64 ? 8 : 4; }
+
 static void derive(bfpic_ctx* h, const bfpic_config* c) {
   h->cfg = *c;
+  h->det = c->deterministic != 0;
   h->dim = c->dim;
   h->nz = c->nz;
   h->nx = c->nx;
@@ -251,7 +261,9 @@ static void derive(bfpic_ctx* h, const bfpic_config* c) {
   h->maxkeys = h->maxtiles * h->TZ * h->TX * h->TY;
   size_t rs = h->fp64 ? 8 : 4;
   // staged E, B in the working precision; currents in FP64 in 2D
-  h->lds_tiled = (size_t)6 * h->LV * rs + (size_t)3 * h->LV * (h->dim == 2 ? 8 : rs);
+  // staged E, B in the working precision; currents in FP64 in 2D, int64 in
+  // the deterministic mode
+  h->lds_tiled = (size_t)6 * h->LV * rs + (size_t)3 * h->LV * acc_bytes(h);
 }
 
 struct Layout {
@@ -285,7 +297,7 @@ static int64_t plan(bfpic_ctx* h, int64_t cap, bfpic_ctx* fill, bfpic_sizes* sz)
   for (int c = 0; c < 3; c++) {
     p = P(grid * rs);
     if (fill) fill->Jf[c] = p;
-    p = P(grid * rs);
+    p = P(grid * (int64_t)ovf_bytes(h));
     if (fill) fill->Jo[c] = p;
   }
   int64_t fields = L.total;
@@ -312,7 +324,9 @@ static int64_t plan(bfpic_ctx* h, int64_t cap, bfpic_ctx* fill, bfpic_sizes* sz)
   if (fill) fill->tile_start = (int*)p;
   // tile regions, then one row of tiles that stays zero (read for tile rows
   // outside the co-moving range)
-  p = P(h->tiled ? (h->maxtiles + (int64_t)h->ntx * h->nty) * 3 * (int64_t)h->LV * rs : 0);
+  p = P(h->tiled ? (h->maxtiles + (int64_t)h->ntx * h->nty) * 3 * (int64_t)h->LV *
+                       (int64_t)ovf_bytes(h)
+                 : 0);
   if (fill) fill->scratch = p;
   p = P(cap * 4);
   if (fill) fill->strag = (int*)p;
@@ -405,7 +419,10 @@ struct Impl {
   }
   static Ovf<R> ovf(bfpic_ctx* h) {
     Ovf<R> o;
-    for (int c = 0; c < 3; c++) o.J[c] = (R*)h->Jo[c];
+    for (int c = 0; c < 3; c++) {
+      o.J[c] = (R*)h->Jo[c];
+      o.Jq[c] = (long long*)h->Jo[c];
+    }
     o.rows = h->ovf_rows;
     return o;
   }
@@ -550,6 +567,30 @@ struct Impl {
     return BFPIC_OK;
   }
 
+  // Deterministic mode: one fixed-point unit is 2^-e of the current, with e
+  // chosen so that a single particle's contribution to a node stays below
+  // 2^40 units (int64 sums then hold 2^23 contributions per node).  A
+  // contribution is at most 4 max(k) w_max: Esirkepov prefix sums and the
+  // pair form are bounded by 3 in shape units, the out-of-plane weight by
+  // 13/12 with |v_y| < 1.
+  static void set_fixed_scale(bfpic_ctx* h) {
+    const DensityK& D = h->dens;
+    double nmax = std::fabs(D.n_uniform);
+    for (int m = 0; m < D.nknots; m++) nmax = std::max(nmax, std::fabs(D.kn[m]));
+    const double wmax = D.gamma_b * nmax * D.dV_over_ppc;
+    double k;
+    if (DIM == 2)
+      k = std::max({1.0 / (h->dx * h->dt), 1.0 / (h->dz * h->dt), 1.0 / (h->dz * h->dx)});
+    else
+      k = std::max({1.0 / (h->dx * h->dy * h->dt), 1.0 / (h->dz * h->dy * h->dt),
+                    1.0 / (h->dz * h->dx * h->dt)});
+    const double bound = 4.0 * k * wmax;
+    int e = 0;
+    if (bound > 0 && std::isfinite(bound)) e = (int)std::floor(std::log2(std::ldexp(1.0, 40) / bound));
+    h->fx_scale = std::ldexp(1.0, e);
+    h->fx_inv = std::ldexp(1.0, -e);
+  }
+
   static StepK<R> step_consts(bfpic_ctx* h) {
     StepK<R> P;
     P.g = h->g;
@@ -573,6 +614,11 @@ struct Impl {
       P.kj[2] = (R)(1.0 / (h->dz * h->dx * h->dt));
     }
     P.ky2d = (R)(1.0 / (h->dz * h->dx));
+    if (h->det) {
+      // deterministic mode: the deposit produces fixed-point units directly
+      for (int a = 0; a < 3; a++) P.kj[a] = (R)((double)P.kj[a] * h->fx_scale);
+      P.ky2d = (R)((double)P.ky2d * h->fx_scale);
+    }
     P.ion_moves = h->sb != 0.0;
     P.remove = !h->g.periodic_z;
     P.lim = ORDER + 1;
@@ -581,7 +627,8 @@ struct Impl {
 
   static FoldK<R> fold_consts(bfpic_ctx* h, const StepK<R>& P) {
     FoldK<R> K;
-    K.scratch = (const R*)h->scratch;
+    K.scratch = h->scratch;
+    K.inv_scale = h->fx_inv;
     K.ntz = h->ntz;
     K.ntx = h->ntx;
     K.nty = h->nty;
@@ -615,7 +662,7 @@ struct Impl {
 
   // 2D fold + filter on register columns for up to 6 passes per axis; false
   // when the configuration needs the LDS tile kernel instead.
-  template <int NP>
+  template <int NP, bool DET>
   static void cols(bfpic_ctx* h, const FoldK<R>& K, const FiltK& fk, const Fields<R>& Jf) {
     using TG = TileGeom<2, ORDER, kT2Z, kT2X, 1, kExc>;
     constexpr int FX = 64 - 2 * NP;
@@ -623,9 +670,11 @@ struct Impl {
     const int tz_lo = floor_div(-K.gz0, kT2Z), tz_hi = floor_div(h->nz - K.gz0, kT2Z);
     const int nseg = tz_hi - tz_lo + 1, nbx = (int)cdiv(h->nx, FX);
     const int64_t nw = (int64_t)nseg * nbx;
-    k_fold_filter_cols<R, NP, kT2Z, kT2X, TG::LZ, TG::LX><<<(unsigned)cdiv(nw, 4), 256, 0, h->stream>>>(
-        h->g, K, fk, Jf, tz_lo, nseg, nbx, h->ntz_max);
+    k_fold_filter_cols<R, NP, kT2Z, kT2X, TG::LZ, TG::LX, DET>
+        <<<(unsigned)cdiv(nw, 4), 256, 0, h->stream>>>(h->g, K, fk, Jf, tz_lo, nseg, nbx,
+                                                       h->ntz_max);
   }
+  template <bool DET>
   static bool fold_filter_cols(bfpic_ctx* h, const FoldK<R>& K, const FiltK& fk,
                                const Fields<R>& Jf) {
     if constexpr (DIM != 2) {
@@ -633,29 +682,53 @@ struct Impl {
     } else {
       if (!h->tiled) return false;
       switch (fk.H) {
-        case 0: cols<0>(h, K, fk, Jf); return true;
-        case 1: cols<1>(h, K, fk, Jf); return true;
-        case 2: cols<2>(h, K, fk, Jf); return true;
-        case 3: cols<3>(h, K, fk, Jf); return true;
-        case 4: cols<4>(h, K, fk, Jf); return true;
-        case 5: cols<5>(h, K, fk, Jf); return true;
-        case 6: cols<6>(h, K, fk, Jf); return true;
+        case 0: cols<0, DET>(h, K, fk, Jf); return true;
+        case 1: cols<1, DET>(h, K, fk, Jf); return true;
+        case 2: cols<2, DET>(h, K, fk, Jf); return true;
+        case 3: cols<3, DET>(h, K, fk, Jf); return true;
+        case 4: cols<4, DET>(h, K, fk, Jf); return true;
+        case 5: cols<5, DET>(h, K, fk, Jf); return true;
+        case 6: cols<6, DET>(h, K, fk, Jf); return true;
         default: return false;
       }
     }
   }
 
-  static int one_step(bfpic_ctx* h) {
-    int rc = inject(h);
-    if (rc) return rc;
-    bool sort_due = h->cfg.sort_interval > 0 && h->step > 0 &&
-                    h->step % h->cfg.sort_interval == 0;
-    if (sort_due) {
-      rc = sort(h);
-      if (rc) return rc;
+  template <bool DET>
+  static const void* tiled_kernel() {
+    if constexpr (DIM == 2)
+      return (const void*)k_gpd_tiled<R, 2, ORDER, kT2Z, kT2X, 1, kExc, kGpdThreads<R>, DET>;
+    else
+      return (const void*)k_gpd_tiled<R, 3, ORDER, kT3, kT3, kT3, kExc, kGpdThreads<R>, DET>;
+  }
+
+  // Per-configuration kernel set-up at create: opt in to large dynamic LDS.
+  static int prepare(bfpic_ctx* h) {
+    const int lim = (int)h->lds_limit;
+    for (int det = 0; det < 2; det++) {
+      const void* fn;
+      if (DIM == 2)
+        fn = det ? (const void*)k_fold_filter<R, 2, kF2Z, kF2X, 1, kT2Z, kT2X, 1, true>
+                 : (const void*)k_fold_filter<R, 2, kF2Z, kF2X, 1, kT2Z, kT2X, 1, false>;
+      else
+        fn = det ? (const void*)k_fold_filter<R, 3, kF3, kF3, kF3, kT3, kT3, kT3, true>
+                 : (const void*)k_fold_filter<R, 3, kF3, kF3, kF3, kT3, kT3, kT3, false>;
+      (void)hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, lim);
     }
+    if (h->tiled && h->lds_tiled > 65536) {
+      const void* fn = h->det ? tiled_kernel<true>() : tiled_kernel<false>();
+      if (hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize,
+                              (int)h->lds_tiled) != hipSuccess)
+        h->tiled = false;
+    }
+    return BFPIC_OK;
+  }
+
+  // Gather-push-deposit, current fold and filter; DET selects the
+  // fixed-point current sums of the deterministic mode.
+  template <bool DET>
+  static int particles_and_currents(bfpic_ctx* h, const StepK<R>& P) {
     const Geo& g = h->g;
-    StepK<R> P = step_consts(h);
     Fields<R> F = fields(h);
     PSoA<R> S = soa(h, h->cur);
     Ovf<R> O = ovf(h);
@@ -669,12 +742,12 @@ struct Impl {
       T.zc0 = h->zc0;
       T.strag = h->strag;
       T.nstrag = h->counts + 4;
-      if (DIM == 2)
-        k_gpd_tiled<R, 2, ORDER, kT2Z, kT2X, 1, kExc, kGpdThreads<R>>
-            <<<T.ntiles, kGpdThreads<R>, h->lds_tiled, h->stream>>>(P, F, S, T, (R*)h->scratch);
+      if constexpr (DIM == 2)
+        k_gpd_tiled<R, 2, ORDER, kT2Z, kT2X, 1, kExc, kGpdThreads<R>, DET>
+            <<<T.ntiles, kGpdThreads<R>, h->lds_tiled, h->stream>>>(P, F, S, T, h->scratch);
       else
-        k_gpd_tiled<R, 3, ORDER, kT3, kT3, kT3, kExc, kGpdThreads<R>>
-            <<<T.ntiles, kGpdThreads<R>, h->lds_tiled, h->stream>>>(P, F, S, T, (R*)h->scratch);
+        k_gpd_tiled<R, 3, ORDER, kT3, kT3, kT3, kExc, kGpdThreads<R>, DET>
+            <<<T.ntiles, kGpdThreads<R>, h->lds_tiled, h->stream>>>(P, F, S, T, h->scratch);
       HIPCHK(h, hipGetLastError());
     }
     {
@@ -686,7 +759,7 @@ struct Impl {
                                                  4096);
       if (tl || nglob > 0) {
         Timer t(h, 1);
-        k_gpd_global<R, DIM, ORDER><<<nb, 256, 0, h->stream>>>(
+        k_gpd_global<R, DIM, ORDER, DET><<<nb, 256, 0, h->stream>>>(
             P, F, S, O, h->counts, tl ? 1 : 0, tl ? h->strag : nullptr, h->counts + 4);
         HIPCHK(h, hipGetLastError());
       }
@@ -698,23 +771,39 @@ struct Impl {
       Fields<R> Jf;
       for (int c = 0; c < 3; c++) Jf.F[c] = (R*)h->Jf[c];
       for (int c = 3; c < 6; c++) Jf.F[c] = nullptr;
-      if (DIM == 2 && fold_filter_cols(h, K, fk, Jf)) {
+      if (DIM == 2 && fold_filter_cols<DET>(h, K, fk, Jf)) {
       } else if (DIM == 2) {
         int nbz = (int)cdiv(h->nz + 1, kF2Z), nbx = (int)cdiv(h->nx, kF2X);
         size_t lds = 2 * sizeof(R) * (kF2Z + 2 * fk.H) * (kF2X + 2 * fk.H);
-        k_fold_filter<R, 2, kF2Z, kF2X, 1, kT2Z, kT2X, 1><<<nbz * nbx, 256, lds, h->stream>>>(g, K, fk, Jf, nbz,
-                                                                             nbx, 1);
+        k_fold_filter<R, 2, kF2Z, kF2X, 1, kT2Z, kT2X, 1, DET>
+            <<<nbz * nbx, 256, lds, h->stream>>>(g, K, fk, Jf, nbz, nbx, 1);
       } else {
         int nbz = (int)cdiv(h->nz + 1, kF3), nbx = (int)cdiv(h->nx, kF3),
             nby = (int)cdiv(h->ny, kF3);
         size_t lds = 2 * sizeof(R) * (size_t)(kF3 + 2 * fk.H) * (kF3 + 2 * fk.H) * (kF3 + 2 * fk.H);
-        k_fold_filter<R, 3, kF3, kF3, kF3, kT3, kT3, kT3><<<nbz * nbx * nby, 256, lds, h->stream>>>(
-            g, K, fk, Jf, nbz, nbx, nby);
+        k_fold_filter<R, 3, kF3, kF3, kF3, kT3, kT3, kT3, DET>
+            <<<nbz * nbx * nby, 256, lds, h->stream>>>(g, K, fk, Jf, nbz, nbx, nby);
       }
-      k_ovf_clear<R><<<1024, 256, 0, h->stream>>>(g, O);
+      k_ovf_clear<R, DET><<<1024, 256, 0, h->stream>>>(g, O);
       k_ovf_reset<<<1, 1, 0, h->stream>>>(h->ovf_rows, h->counts + 4);
       HIPCHK(h, hipGetLastError());
     }
+    return BFPIC_OK;
+  }
+
+  static int one_step(bfpic_ctx* h) {
+    int rc = inject(h);
+    if (rc) return rc;
+    bool sort_due = h->cfg.sort_interval > 0 && h->step > 0 &&
+                    h->step % h->cfg.sort_interval == 0;
+    if (sort_due) {
+      rc = sort(h);
+      if (rc) return rc;
+    }
+    const Geo& g = h->g;
+    StepK<R> P = step_consts(h);
+    rc = h->det ? particles_and_currents<true>(h, P) : particles_and_currents<false>(h, P);
+    if (rc) return rc;
     {
       Timer t(h, 3);
       YeeK<R> Y;
@@ -792,11 +881,11 @@ struct Impl {
     for (int c = 0; c < 6; c++) HIPCHK(h, hipMemsetAsync(h->F[c], 0, grid * rs, h->stream));
     for (int c = 0; c < 3; c++) {
       HIPCHK(h, hipMemsetAsync(h->Jf[c], 0, grid * rs, h->stream));
-      HIPCHK(h, hipMemsetAsync(h->Jo[c], 0, grid * rs, h->stream));
+      HIPCHK(h, hipMemsetAsync(h->Jo[c], 0, grid * (int64_t)ovf_bytes(h), h->stream));
     }
     HIPCHK(h, hipMemsetAsync(h->counts, 0, 16 * 4, h->stream));
     if (h->tiled) {
-      const int64_t tile_bytes = 3 * (int64_t)h->LV * rs;
+      const int64_t tile_bytes = 3 * (int64_t)h->LV * (int64_t)ovf_bytes(h);
       HIPCHK(h, hipMemsetAsync((char*)h->scratch + h->maxtiles * tile_bytes, 0,
                                (int64_t)h->ntx * h->nty * tile_bytes, h->stream));
     }
@@ -849,6 +938,7 @@ struct Impl {
       D.dz = h->dz;
       D.dV_over_ppc = h->dz * h->dx * (DIM == 3 ? h->dy : 1.0) / h->cfg.ppc;
       for (int a = 0; a < 3; a++) D.du0[a] = d->du[a];
+      set_fixed_scale(h);
       int64_t count = (int64_t)h->nz * h->nx * h->ny * h->cfg.ppc;
       if (count > h->cap)
         return fail(h, BFPIC_ERR_CAPACITY, "initial particles " + std::to_string(count) +
@@ -991,13 +1081,14 @@ struct Impl {
     }                                                                              \
   } while (0)
 
+static int prepare_kernels(bfpic_ctx* h) { BFPIC_DISPATCH(h, I::prepare(h)); }
+
 // ---------------------------------------------------------------------------
 // C ABI
 // ---------------------------------------------------------------------------
 extern "C" int bfpic_query_sizes(const bfpic_config* cfg, int64_t cap, bfpic_sizes* out) {
   std::string why;
   if (!out || cap < 1 || !check_cfg(cfg, why)) return BFPIC_ERR_ARG;
-  if (cfg->deterministic) return BFPIC_ERR_UNSUPPORTED;
   bfpic_ctx tmp;
   derive(&tmp, cfg);
   plan(&tmp, cap, nullptr, out);
@@ -1011,7 +1102,6 @@ extern "C" int bfpic_create(const bfpic_config* cfg, int64_t cap, void* workspac
   std::string why;
   if (cap < 1 || cap > 0x7fffffffLL || !check_cfg(cfg, why) || !workspace)
     return BFPIC_ERR_ARG;
-  if (cfg->deterministic) return BFPIC_ERR_UNSUPPORTED;
   bfpic_ctx* h = new bfpic_ctx();
   derive(h, cfg);
   h->cap = cap;
@@ -1033,14 +1123,6 @@ extern "C" int bfpic_create(const bfpic_config* cfg, int64_t cap, void* workspac
   // the filter kernels may need more than 64 KB of LDS (3D, FP64, many passes)
   {
     int lim = (int)h->lds_limit;
-    hipFuncSetAttribute((const void*)k_fold_filter<float, 2, kF2Z, kF2X, 1, kT2Z, kT2X, 1>,
-                        hipFuncAttributeMaxDynamicSharedMemorySize, lim);
-    hipFuncSetAttribute((const void*)k_fold_filter<double, 2, kF2Z, kF2X, 1, kT2Z, kT2X, 1>,
-                        hipFuncAttributeMaxDynamicSharedMemorySize, lim);
-    hipFuncSetAttribute((const void*)k_fold_filter<float, 3, kF3, kF3, kF3, kT3, kT3, kT3>,
-                        hipFuncAttributeMaxDynamicSharedMemorySize, lim);
-    hipFuncSetAttribute((const void*)k_fold_filter<double, 3, kF3, kF3, kF3, kT3, kT3, kT3>,
-                        hipFuncAttributeMaxDynamicSharedMemorySize, lim);
     hipFuncSetAttribute((const void*)k_filter_grid<2, kF2Z, kF2X, 1>,
                         hipFuncAttributeMaxDynamicSharedMemorySize, lim);
     hipFuncSetAttribute((const void*)k_filter_grid<3, kF3, kF3, kF3>,
@@ -1056,26 +1138,7 @@ extern "C" int bfpic_create(const bfpic_config* cfg, int64_t cap, void* workspac
       return BFPIC_ERR_UNSUPPORTED;
     }
   }
-  if (h->tiled && h->lds_tiled > 65536) {
-    // opt in to large dynamic LDS for the tiled kernel of this configuration
-    const void* fn = nullptr;
-    const bool f64 = h->fp64;
-    if (h->dim == 2 && h->order == 1)
-      fn = f64 ? (const void*)k_gpd_tiled<double, 2, 1, kT2Z, kT2X, 1, kExc, kGpdThreads<double>>
-               : (const void*)k_gpd_tiled<float, 2, 1, kT2Z, kT2X, 1, kExc, kGpdThreads<float>>;
-    else if (h->dim == 2)
-      fn = f64 ? (const void*)k_gpd_tiled<double, 2, 2, kT2Z, kT2X, 1, kExc, kGpdThreads<double>>
-               : (const void*)k_gpd_tiled<float, 2, 2, kT2Z, kT2X, 1, kExc, kGpdThreads<float>>;
-    else if (h->order == 1)
-      fn = f64 ? (const void*)k_gpd_tiled<double, 3, 1, kT3, kT3, kT3, kExc, kGpdThreads<double>>
-               : (const void*)k_gpd_tiled<float, 3, 1, kT3, kT3, kT3, kExc, kGpdThreads<float>>;
-    else
-      fn = f64 ? (const void*)k_gpd_tiled<double, 3, 2, kT3, kT3, kT3, kExc, kGpdThreads<double>>
-               : (const void*)k_gpd_tiled<float, 3, 2, kT3, kT3, kT3, kExc, kGpdThreads<float>>;
-    if (hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)h->lds_tiled) !=
-        hipSuccess)
-      h->tiled = false;
-  }
+  prepare_kernels(h);
 
   *out = h;
   return BFPIC_OK;

@@ -2,6 +2,8 @@
 // boundaries, window shift, boosted laser initialisation, field copies.
 #pragma once
 
+#include <type_traits>
+
 #include "device_common.hpp"
 #include "kernels_particles.hpp"
 
@@ -18,7 +20,8 @@ __device__ __forceinline__ int half_z_j(int c) { return c == 2; }
 // --------------------------------------------------------------------------
 template <typename R>
 struct FoldK {
-  const R* scratch;  // [tile][3][LV]
+  const void* scratch;  // [tile][3][LV] of R, or of int64 in deterministic mode
+  double inv_scale;     // deterministic mode: value of one fixed-point unit
   int ntz, ntx, nty, ntiles;
   int gz0, gx0, gy0;  // region origin of tile (0,0,0) in grid cells
   int TZ, TX, TY, LZ, LX, LY, LV;
@@ -29,10 +32,12 @@ struct FoldK {
 // and are L <= 2 T long, so node offset q (from the region origin of tile 0)
 // lies in tile h = q / T at local q - h T, and also in tile h - 1 at local
 // q - h T + T when that is below L.
-template <typename R, int DIM, int TZ, int TX, int TY>
+template <typename R, int DIM, int TZ, int TX, int TY, bool DET>
 __device__ __forceinline__ R fold_at(const FoldK<R>& K, const Geo& g, int comp, int i, int j,
                                      int k) {
-  R acc = (R)0;
+  using A = typename std::conditional<DET, long long, R>::type;
+  const A* scratch = reinterpret_cast<const A*>(K.scratch);
+  A acc = (A)0;
   if (g.periodic_z) i = wrap_small(i, g.nz);  // halo rows of the filter may lie beyond the seam
   if (K.ntiles > 0) {
     int qz = i - K.gz0;
@@ -58,7 +63,7 @@ __device__ __forceinline__ R fold_at(const FoldK<R>& K, const Geo& g, int comp, 
           if (ty < 0) ty += K.nty;
           if (DIM == 3 && ry >= K.LY) continue;
           int t = (tz * K.ntx + tx) * K.nty + ty;
-          acc += K.scratch[((int64_t)t * 3 + comp) * K.LV + (rz * K.LX + rx) * K.LY + ry];
+          acc += scratch[((int64_t)t * 3 + comp) * K.LV + (rz * K.LX + rx) * K.LY + ry];
         }
       }
     }
@@ -66,9 +71,14 @@ __device__ __forceinline__ R fold_at(const FoldK<R>& K, const Geo& g, int comp, 
   int r0 = K.o.rows[0], r1 = K.o.rows[1];
   if (i >= r0 && i <= r1) {
     int64_t n = gidx(g, i, j, k);
-    if (n >= 0) acc += K.o.J[comp][n];
+    if constexpr (DET) {
+      if (n >= 0) acc += K.o.Jq[comp][n];
+    } else {
+      if (n >= 0) acc += K.o.J[comp][n];
+    }
   }
-  return acc;
+  if constexpr (DET) return (R)((double)acc * K.inv_scale);
+  else return acc;
 }
 
 // Filter: per axis N passes of (1/4, 1/2, 1/4) then (-N/4, 1 + N/2, -N/4)
@@ -151,17 +161,17 @@ __device__ void filter_tile(const Geo& g, const FiltK& fk, int half_z, int i0, i
   __syncthreads();
 }
 
-template <typename R, int DIM, int TZ, int TX, int TY>
+template <typename R, int DIM, int TZ, int TX, int TY, bool DET>
 struct FoldSrc {
   const FoldK<R>* K;
   Geo g;
   int comp;
   __device__ __forceinline__ R operator()(int i, int j, int k) const {
-    return fold_at<R, DIM, TZ, TX, TY>(*K, g, comp, i, j, k);
+    return fold_at<R, DIM, TZ, TX, TY, DET>(*K, g, comp, i, j, k);
   }
 };
 
-template <typename R, int DIM, int FZ, int FX, int FY, int TZ, int TX, int TY>
+template <typename R, int DIM, int FZ, int FX, int FY, int TZ, int TX, int TY, bool DET>
 __global__ __launch_bounds__(256) void k_fold_filter(Geo g, FoldK<R> K, FiltK fk, Fields<R> Jf,
                                                      int nbz, int nbx, int nby) {
   extern __shared__ __align__(16) unsigned char smem_raw[];
@@ -171,7 +181,7 @@ __global__ __launch_bounds__(256) void k_fold_filter(Geo g, FoldK<R> K, FiltK fk
   int by = b % nby, bx = (b / nby) % nbx, bz = b / (nby * nbx);
   int i0 = bz * FZ, j0 = bx * FX, k0 = by * FY;
   for (int comp = 0; comp < 3; comp++) {
-    FoldSrc<R, DIM, TZ, TX, TY> src{&K, g, comp};
+    FoldSrc<R, DIM, TZ, TX, TY, DET> src{&K, g, comp};
     filter_tile<R, DIM, FZ, FX, FY>(g, fk, half_z_j(comp), i0, j0, k0, src, Jf.F[comp], lds);
   }
 }
@@ -189,7 +199,7 @@ __global__ __launch_bounds__(256) void k_fold_filter(Geo g, FoldK<R> K, FiltK fk
 // The fold sums, per node, the tile whose core holds it, then the tile
 // before it in z, each with the two x candidates, then the overflow grid:
 // the order of fold_at.
-template <typename R, int NP, int TZ, int TX, int LZ, int LX>
+template <typename R, int NP, int TZ, int TX, int LZ, int LX, bool DET>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(1, 4))) void k_fold_filter_cols(Geo g, FoldK<R> K, FiltK fk,
                                                           Fields<R> Jf, int tz_lo, int nseg,
                                                           int nbx, int zero_row) {
@@ -219,6 +229,8 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(1, 4))) voi
   const int xb = vb ? txb * 3 * LV + lx + TX : xa;
   const int jw = wrap_small(j, g.nx);
   // tile rows tzw - 2 .. tzw + 1
+  using A = typename std::conditional<DET, long long, R>::type;  // fold sums
+  const A* scratch = reinterpret_cast<const A*>(K.scratch);
   int64_t trow[4];
 #pragma unroll
   for (int d = 0; d < 4; d++) {
@@ -237,37 +249,46 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(1, 4))) voi
     const bool interior = g.periodic_z || (ilo >= 0 && ihi <= row_hi(g, hz));
     // per-lane pointers to row 0 of each candidate tile; rows are then
     // compile-time offsets
-    const R* pA[4];
-    const R* pB[4];
+    const A* pA[4];
+    const A* pB[4];
 #pragma unroll
     for (int d = 0; d < 4; d++) {
-      pA[d] = K.scratch + trow[d] + comp * LV + xa;
-      pB[d] = K.scratch + trow[d] + comp * LV + xb;
+      pA[d] = scratch + trow[d] + comp * LV + xa;
+      pB[d] = scratch + trow[d] + comp * LV + xb;
     }
-    R v[L];
+    A va[L];
 #pragma unroll
     for (int r = 0; r < L; r++) {
       const int q = r - H;
       const int dt = q >= 0 ? q / TZ : -((TZ - 1 - q) / TZ);
       const int lz = q - dt * TZ;
-      R acc = pA[dt + 2][lz * LX];
-      const R a1 = pB[dt + 2][lz * LX];
-      acc += vb ? a1 : (R)0;
+      A acc = pA[dt + 2][lz * LX];
+      const A a1 = pB[dt + 2][lz * LX];
+      acc += vb ? a1 : (A)0;
       if (lz + TZ < LZ) {
-        const R b0 = pA[dt + 1][(lz + TZ) * LX], b1 = pB[dt + 1][(lz + TZ) * LX];
+        const A b0 = pA[dt + 1][(lz + TZ) * LX], b1 = pB[dt + 1][(lz + TZ) * LX];
         acc += b0;
-        acc += vb ? b1 : (R)0;
+        acc += vb ? b1 : (A)0;
       }
-      v[r] = acc;
+      va[r] = acc;
     }
     if (any_ovf) {
 #pragma unroll
       for (int r = 0; r < L; r++) {
         int i = iw0 - H + r;
         if (g.periodic_z) i = wrap_small(i, g.nz);
-        if (i >= r0 && i <= r1 && i >= -kGuard && i <= g.nz + kGuard)
-          v[r] += K.o.J[comp][(int64_t)(i + kGuard) * g.plane + jw];
+        if (i >= r0 && i <= r1 && i >= -kGuard && i <= g.nz + kGuard) {
+          const int64_t n = (int64_t)(i + kGuard) * g.plane + jw;
+          if constexpr (DET) va[r] += K.o.Jq[comp][n];
+          else va[r] += K.o.J[comp][n];
+        }
       }
+    }
+    R v[L];
+#pragma unroll
+    for (int r = 0; r < L; r++) {
+      if constexpr (DET) v[r] = (R)((double)va[r] * K.inv_scale);
+      else v[r] = va[r];
     }
     if (!interior) {
 #pragma unroll
@@ -309,7 +330,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(1, 4))) voi
 }
 
 // Clear the overflow rows that the global path touched this step.
-template <typename R>
+template <typename R, bool DET>
 __global__ __launch_bounds__(256) void k_ovf_clear(Geo g, Ovf<R> o) {
   int r0 = o.rows[0], r1 = o.rows[1];
   if (r1 < r0) return;
@@ -319,9 +340,10 @@ __global__ __launch_bounds__(256) void k_ovf_clear(Geo g, Ovf<R> o) {
   int64_t base = (int64_t)(r0 + kGuard) * g.plane;
   for (int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; v < n;
        v += (int64_t)gridDim.x * blockDim.x) {
-    o.J[0][base + v] = (R)0;
-    o.J[1][base + v] = (R)0;
-    o.J[2][base + v] = (R)0;
+    for (int c = 0; c < 3; c++) {
+      if constexpr (DET) o.Jq[c][base + v] = 0;
+      else o.J[c][base + v] = (R)0;
+    }
   }
 }
 

@@ -48,8 +48,17 @@ struct StepK {
 template <typename R>
 struct Ovf {
   R* J[3];           // Jx Jy Jz on the grid (zero between steps)
+  long long* Jq[3];  // the same memory as fixed-point sums (deterministic mode)
   int* rows;         // [0] min row touched, [1] max row touched
 };
+
+// Round a value already expressed in fixed-point units to the nearest int64
+// (ties to even), valid for |x| < 2^51: adding 1.5 * 2^52 leaves the rounded
+// integer in the low mantissa bits of the sum.
+__device__ __forceinline__ long long to_fixed(double x) {
+  const double t = x + 6755399441055744.0;
+  return (long long)__double_as_longlong(t) - 0x4338000000000000LL;
+}
 
 // --------------------------------------------------------------------------
 // Field fetchers and current sinks.  Coordinates are node indices in the
@@ -93,10 +102,29 @@ struct LdsSink {
   }
 };
 
+// Deterministic mode: currents arrive pre-scaled to fixed-point units (the
+// scale is folded into the deposit constants) and are summed as int64, so
+// the result does not depend on the order of the atomic adds.
+template <int LX, int LY>
+struct LdsSinkFx {
+  long long* s;  // [3][LZ*LX*LY]
+  int lv;
+  template <typename R>
+  __device__ __forceinline__ void add(int comp, int i, int j, int k, R v) const {
+    atomicAdd(reinterpret_cast<unsigned long long*>(&s[comp * lv + (i * LX + j) * LY + k]),
+              (unsigned long long)to_fixed((double)v));
+  }
+};
+
 // Accumulator type of the tiled kernel's LDS currents (2D: FP64; 3D keeps
-// the working precision so that the staged fields and currents fit in LDS).
-template <typename R, int DIM>
-using LdsAcc = typename std::conditional<DIM == 2, double, R>::type;
+// the working precision so that the staged fields and currents fit in LDS;
+// deterministic mode: int64 fixed point).
+template <typename R, int DIM, bool DET>
+using LdsAcc = typename std::conditional<
+    DET, long long, typename std::conditional<DIM == 2, double, R>::type>::type;
+
+template <typename A, int LX, int LY, bool DET>
+using LdsSinkT = typename std::conditional<DET, LdsSinkFx<LX, LY>, LdsSink<A, LX, LY>>::type;
 
 template <typename R>
 struct GlobalSink {
@@ -106,6 +134,19 @@ struct GlobalSink {
     if (v == (R)0) return;
     int64_t n = gidx(g, i, j, k);
     if (n >= 0) atomicAdd(&o.J[comp][n], v);
+  }
+};
+
+template <typename R>
+struct GlobalSinkFx {
+  Ovf<R> o;
+  Geo g;
+  __device__ __forceinline__ void add(int comp, int i, int j, int k, R v) const {
+    if (v == (R)0) return;
+    int64_t n = gidx(g, i, j, k);
+    if (n >= 0)
+      atomicAdd(reinterpret_cast<unsigned long long*>(&o.Jq[comp][n]),
+                (unsigned long long)to_fixed((double)v));
   }
 };
 
@@ -545,7 +586,7 @@ __device__ __forceinline__ void note_rows(const Ovf<R>& o, const Geo& g, int ce,
 // every slot when the grid is too small to tile.  Fields are read and the
 // current is accumulated in global memory (the overflow sink).
 // --------------------------------------------------------------------------
-template <typename R, int DIM, int ORDER>
+template <typename R, int DIM, int ORDER, bool DET>
 __global__ __launch_bounds__(256) void k_gpd_global(StepK<R> P, Fields<R> F, PSoA<R> S, Ovf<R> O,
                                                     const int* counts, int from_sorted,
                                                     const int* strag, const int* nstrag) {
@@ -553,7 +594,7 @@ __global__ __launch_bounds__(256) void k_gpd_global(StepK<R> P, Fields<R> F, PSo
   const int ntail = counts[0] - first;
   const int total = ntail + (strag ? *nstrag : 0);
   GlobalFetch<R> f{(const R* const*)F.F, P.g};
-  GlobalSink<R> sk{O, P.g};
+  typename std::conditional<DET, GlobalSinkFx<R>, GlobalSink<R>>::type sk{O, P.g};
   for (int q = blockIdx.x * blockDim.x + threadIdx.x; q < total; q += gridDim.x * blockDim.x) {
     const int p = q < ntail ? first + q : strag[q - ntail];
     const int id = S.id[p];
@@ -605,12 +646,12 @@ struct TileGeom {
   static constexpr int LV = LZ * LX * LY;
 };
 
-template <typename R, int DIM, int ORDER, int TZ, int TX, int TY, int EXC, int NT>
+template <typename R, int DIM, int ORDER, int TZ, int TX, int TY, int EXC, int NT, bool DET>
 __global__ __launch_bounds__(NT) void k_gpd_tiled(StepK<R> P, Fields<R> F, PSoA<R> S, TileK T,
-                                                  R* scratch) {
+                                                  void* scratch) {
   using TG = TileGeom<DIM, ORDER, TZ, TX, TY, EXC>;
   constexpr int LZ = TG::LZ, LX = TG::LX, LY = TG::LY, LV = TG::LV;
-  using A = LdsAcc<R, DIM>;
+  using A = LdsAcc<R, DIM, DET>;
   extern __shared__ __align__(16) unsigned char smem_raw[];
   R* sF = reinterpret_cast<R*>(smem_raw);
   A* sJ = reinterpret_cast<A*>(sF + 6 * LV);  // 6 LV sizeof(R) is a multiple of 8
@@ -686,7 +727,7 @@ __global__ __launch_bounds__(NT) void k_gpd_tiled(StepK<R> P, Fields<R> F, PSoA<
   for (int v = threadIdx.x; v < 3 * LV; v += NT) sJ[v] = (A)0;
   __syncthreads();
   LdsFetch<R, LX, LY> lf{sF, LV};
-  LdsSink<A, LX, LY> ls{sJ, LV};
+  LdsSinkT<A, LX, LY, DET> ls{sJ, LV};
   const int p0 = T.start[t], p1 = T.start[t + 1];
   // the whole state of the next particle is loaded while this one is pushed
   int p = p0 + (int)threadIdx.x;
@@ -736,8 +777,13 @@ __global__ __launch_bounds__(NT) void k_gpd_tiled(StepK<R> P, Fields<R> F, PSoA<
     store_state<R, DIM>(S, p, xi, du, dead);
   }
   __syncthreads();
-  R* dst = scratch + (int64_t)t * 3 * LV;
-  for (int v = threadIdx.x; v < 3 * LV; v += NT) dst[v] = (R)sJ[v];
+  if constexpr (DET) {
+    long long* dst = reinterpret_cast<long long*>(scratch) + (int64_t)t * 3 * LV;
+    for (int v = threadIdx.x; v < 3 * LV; v += NT) dst[v] = sJ[v];
+  } else {
+    R* dst = reinterpret_cast<R*>(scratch) + (int64_t)t * 3 * LV;
+    for (int v = threadIdx.x; v < 3 * LV; v += NT) dst[v] = (R)sJ[v];
+  }
 }
 
 // --------------------------------------------------------------------------

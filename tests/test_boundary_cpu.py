@@ -66,8 +66,15 @@ def test_query_sizes_and_bad_configs(P):
     for bad in (dict(dim=4), dict(cfl=1.2), dict(shape_order=3), dict(ppc=0), dict(nz=2)):
         cb = P.make_config(**bad)
         assert P.lib().bfpic_query_sizes(ctypes.byref(cb), 10, ctypes.byref(s)) == -1
-    cd = P.make_config(deterministic=1)
-    assert P.lib().bfpic_query_sizes(ctypes.byref(cd), 10, ctypes.byref(s)) == -5
+    # deterministic mode: accepted; the overflow grid and tile current scratch
+    # hold int64 sums, so an FP32 run needs more workspace
+    cd = P.make_config(dim=2, nz=8192, nx=512, precision=P.FP32_SPLIT, ppc=8,
+                       z_boundary=P.BC_MUR, filter_passes=4, filter_compensate=1,
+                       deterministic=1)
+    sd = P.Sizes()
+    assert P.lib().bfpic_query_sizes(ctypes.byref(cd), 34_000_000, ctypes.byref(sd)) == 0
+    assert sd.field_bytes > s.field_bytes and sd.scratch_bytes > s.scratch_bytes
+    assert sd.particle_bytes == s.particle_bytes
 
 
 def test_create_rejects_small_workspace(P):

@@ -29,8 +29,9 @@ def P():
     return P
 
 
-def run_gpu(P, W, steps=None, precision=None, sort_interval=20, fields=True):
+def run_gpu(P, W, steps=None, precision=None, sort_interval=20, fields=True, det=0):
     cfg, init, nst = resolve_gpu(W, precision=precision, sort_interval=sort_interval)
+    cfg.deterministic = det
     sim = P.Simulation(cfg, capacity=init["capacity"])
     sim.init_boosted_plasma(init["gamma_b"], n_uniform=init["n_lab"], laser=init["laser"])
     sim.pic_step(nst if steps is None else steps)
@@ -135,6 +136,53 @@ def test_boosted_3d_fp32_split_within_tolerance(P):
     do, _ = run_oracle(W)
     assert rel(dg["ue"] + dg["ub"], do["ue"] + do["ub"]) < 1e-3
     assert abs(dg["live"] - do["live"]) <= 1e-3 * do["live"]
+
+
+# --------------------------------------------------------------------------
+# Deterministic mode: int64 fixed-point current sums
+# --------------------------------------------------------------------------
+def _state(P, W, precision, det, steps):
+    cfg, init, _ = resolve_gpu(W, precision=precision, sort_interval=20)
+    cfg.deterministic = det
+    sim = P.Simulation(cfg, capacity=init["capacity"])
+    sim.init_boosted_plasma(init["gamma_b"], n_uniform=init["n_lab"], laser=init["laser"])
+    sim.pic_step(steps)
+    f = {c: sim.get_field(c).cpu().numpy() for c in ("Ex", "Ey", "Ez", "Bx", "By", "Bz",
+                                                      "Jx", "Jy", "Jz")}
+    parts = sim.particles()
+    d = sim.diagnostics(lineout=True)
+    sim.close()
+    return f, parts, d
+
+
+@pytest.mark.parametrize("precision", ["fp32", "fp64"])
+def test_deterministic_mode_repeats_bitwise(P, precision):
+    W = WORKLOADS["boost13_2d_small"]
+    print("case deterministic repeat", precision, flush=True)
+    f1, p1, _ = _state(P, W, precision, 1, 60)
+    f2, p2, _ = _state(P, W, precision, 1, 60)
+    for c in f1:
+        assert np.array_equal(f1[c], f2[c]), c
+    for k in p1:
+        assert np.array_equal(p1[k], p2[k]), k
+
+
+def test_deterministic_mode_fp64_matches_oracle(P):
+    for name in ("lab_2d", "boost13_2d_small"):
+        W = WORKLOADS[name]
+        print("case deterministic fp64", name, flush=True)
+        dg, fg = run_gpu(P, W, precision="fp64", det=1)
+        do, fo = run_oracle(W)
+        check_fp64(dg, fg, do, fo)
+
+
+def test_deterministic_mode_fp32_within_tolerance(P):
+    W = WORKLOADS["boost130_2d_small"]
+    print("case deterministic fp32 boost130_2d_small", flush=True)
+    dg, _ = run_gpu(P, W, precision="fp32", fields=False, det=1)
+    do, _ = run_oracle(W)
+    assert rel(dg["ue"], do["ue"]) < 1e-3
+    assert l2rel(dg["lineout"], do["lineout"]) < 1e-2
 
 
 # --------------------------------------------------------------------------
