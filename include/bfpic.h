@@ -109,6 +109,16 @@ typedef struct bfpic_laser {
   int32_t images_z, images_x, images_y;
 } bfpic_laser;
 
+/* Field loss for the adjoint: L = (1 / nwin) sum over n = step_first ..
+ * step_last of the mean of Ez^n over the node box i0..i1 (z rows of Ez,
+ * inclusive) by j0..j1 (x columns, inclusive), where Ez^n is the field after
+ * step n (steps counted from 1 after init) and nwin = step_last -
+ * step_first + 1. */
+typedef struct bfpic_loss {
+  int32_t step_first, step_last;
+  int32_t i0, i1, j0, j1;
+} bfpic_loss;
+
 typedef struct bfpic_sizes {
   int64_t workspace_bytes;   /* total device bytes to allocate */
   int64_t field_bytes;       /* of which: fields */
@@ -241,6 +251,34 @@ int bfpic_tile_shape(const bfpic_ctx* h, int32_t* tz, int32_t* tx, int32_t* ty);
  * 4 sort, 5 injection, 6 window shift. */
 int bfpic_kernel_timing(bfpic_ctx* h, int32_t enable);
 int bfpic_kernel_time(bfpic_ctx* h, int32_t cls, double* total_ms, int64_t* launches);
+
+/* ---------------------------------------------------------------------------
+ * Adjoint (2D).  The paper prints no adjoint; these calls give the exact
+ * discrete gradient of a field loss (bfpic_loss) through the step above with
+ * respect to the laser amplitude a0 and the lab density profile (the knot
+ * values of init_boosted_plasma, or n_uniform), the two inputs that set a
+ * stage's wake.  The reverse sweep runs the transposes of the Yee update, the
+ * Mur boundary and the filter, and per particle the vector-Jacobian product of
+ * gather, push, move and deposit, backwards over the steps, recomputing each
+ * segment of `interval` steps from its checkpoint.  Runs without a moving
+ * window only (beta_window = 0, auto_window = 0); particles are not re-sorted
+ * during a taped run.
+ *
+ * bfpic_adjoint_tape_bytes: device bytes of the tape for nsteps steps with a
+ *   checkpoint every `interval` steps (checkpoints, one segment of per-step
+ *   state, adjoint arrays).  The caller allocates it (256-byte aligned).
+ * bfpic_forward_loss: from the state right after init_boosted_plasma, runs
+ *   nsteps steps, storing the checkpoints in `tape`, and returns the loss in
+ *   *loss_out (host).  The tape must stay allocated for pic_step_adjoint.
+ *   Synchronises.  ERR_STATE if steps were taken since init.
+ * pic_step_adjoint: reverse sweep of the last bfpic_forward_loss run:
+ *   *dL_da0 (host) and dL_dn[m] (host array of nn >= number of knots, or >= 1
+ *   for a uniform density).  Leaves the simulation state unspecified
+ *   (re-initialise before stepping on).  Synchronises. */
+int bfpic_adjoint_tape_bytes(bfpic_ctx* h, int32_t nsteps, int32_t interval, int64_t* bytes);
+int bfpic_forward_loss(bfpic_ctx* h, int32_t nsteps, int32_t interval, const bfpic_loss* loss,
+                       void* tape, int64_t tape_bytes, double* loss_out);
+int pic_step_adjoint(bfpic_ctx* h, double* dL_da0, double* dL_dn, int32_t nn);
 
 #ifdef __cplusplus
 }

@@ -68,6 +68,11 @@ class Diag(C.Structure):
         return {k: getattr(self, k) for k, _ in self._fields_}
 
 
+class Loss(C.Structure):
+    _fields_ = [("step_first", C.c_int32), ("step_last", C.c_int32), ("i0", C.c_int32),
+                ("i1", C.c_int32), ("j0", C.c_int32), ("j1", C.c_int32)]
+
+
 _lib = None
 
 EXPORTS = ["bfpic_beta", "bfpic_drift_u", "bfpic_group_gamma", "bfpic_boosted_group_beta",
@@ -75,7 +80,8 @@ EXPORTS = ["bfpic_beta", "bfpic_drift_u", "bfpic_group_gamma", "bfpic_boosted_gr
            "bfpic_destroy", "bfpic_last_error", "init_boosted_plasma", "pic_step",
            "moving_window_shift", "bfpic_window_due", "diagnostics", "bfpic_get_field",
            "bfpic_set_field", "bfpic_num_slots", "bfpic_get_particles", "bfpic_sort",
-           "bfpic_last_sort", "bfpic_tile_shape", "bfpic_kernel_timing", "bfpic_kernel_time"]
+           "bfpic_last_sort", "bfpic_tile_shape", "bfpic_kernel_timing", "bfpic_kernel_time",
+           "bfpic_adjoint_tape_bytes", "bfpic_forward_loss", "pic_step_adjoint"]
 
 
 def lib():
@@ -85,6 +91,9 @@ def lib():
         return _lib
     if not os.path.exists(LIB_PATH):
         raise BfpicError(f"{LIB_PATH} is missing: run __graft_entry__.build() (no CPU fallback)")
+    # torch's HIP runtime is loaded first, so that the library binds to the
+    # same runtime torch allocates device memory with
+    import torch  # noqa: F401
     L = C.CDLL(LIB_PATH)
     d, i32, i64, p = C.c_double, C.c_int32, C.c_int64, C.c_void_p
     sig = {
@@ -107,6 +116,9 @@ def lib():
         "bfpic_tile_shape": (C.c_int, [p, C.POINTER(i32), C.POINTER(i32), C.POINTER(i32)]),
         "bfpic_kernel_timing": (C.c_int, [p, i32]),
         "bfpic_kernel_time": (C.c_int, [p, i32, C.POINTER(d), C.POINTER(i64)]),
+        "bfpic_adjoint_tape_bytes": (C.c_int, [p, i32, i32, C.POINTER(i64)]),
+        "bfpic_forward_loss": (C.c_int, [p, i32, i32, C.POINTER(Loss), p, i64, C.POINTER(d)]),
+        "pic_step_adjoint": (C.c_int, [p, C.POINTER(d), C.POINTER(d), i32]),
     }
     for name, (res, args) in sig.items():
         f = getattr(L, name)
@@ -288,3 +300,28 @@ class Simulation:
         ms, n = C.c_double(), C.c_int64()
         _check(lib().bfpic_kernel_time(self.h, cls, C.byref(ms), C.byref(n)), self.h)
         return ms.value, n.value
+
+    # ---- adjoint ----
+    def forward_loss(self, nsteps, interval, step_first, step_last, box) -> float:
+        """Taped run of `nsteps` steps from the state right after init, with a
+        checkpoint every `interval` steps; returns the loss: the mean of Ez over
+        the node box (i0, i1, j0, j1) averaged over steps step_first..step_last."""
+        import torch
+        nb = C.c_int64()
+        _check(lib().bfpic_adjoint_tape_bytes(self.h, nsteps, interval, C.byref(nb)), self.h)
+        self.tape = torch.empty(nb.value, dtype=torch.uint8, device=self.device)
+        i0, i1, j0, j1 = box
+        loss = Loss(step_first, step_last, i0, i1, j0, j1)
+        out = C.c_double()
+        _check(lib().bfpic_forward_loss(self.h, nsteps, interval, C.byref(loss),
+                                        C.c_void_p(self.tape.data_ptr()), nb.value,
+                                        C.byref(out)), self.h)
+        return out.value
+
+    def adjoint(self, nknots=1):
+        """Reverse sweep of the last taped run: (dL/da0, dL/dn) with dL/dn per
+        density knot (one value for a uniform density)."""
+        da0 = C.c_double()
+        dn = (C.c_double * max(nknots, 1))()
+        _check(lib().pic_step_adjoint(self.h, C.byref(da0), dn, max(nknots, 1)), self.h)
+        return da0.value, [dn[m] for m in range(max(nknots, 1))]

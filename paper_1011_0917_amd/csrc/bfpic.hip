@@ -18,6 +18,7 @@
 #include "kernels_fields.hpp"
 #include "kernels_particles.hpp"
 #include "kernels_sort.hpp"
+#include "kernels_adjoint.hpp"
 
 using namespace bfpic;
 
@@ -126,6 +127,21 @@ struct bfpic_ctx {
   int last_sort_tzmin = 0, last_sort_ntz = 0;
   const int* final_perm = nullptr;  // destination -> source slot of the last sort
   bool have_sort = false;
+  // adjoint: taped forward run and reverse sweep
+  struct HostCkpt {
+    int64_t step, window_cells, next_col, slots_bound, tail_bound;
+    int cur;
+  };
+  double laser_a0 = 0.0;
+  bool no_sort = false;      // particle slots stay put (taped runs)
+  bool adj_ready = false;    // the tape holds a forward run
+  bool adj_recompute = false;
+  int adj_nsteps = 0, adj_interval = 0;
+  int64_t adj_slots = 0;     // slots created by the taped run
+  bfpic_loss adj_loss{};
+  std::vector<HostCkpt> ckpt;
+  uint8_t* tape = nullptr;
+  int64_t tape_bytes = 0;
   // timing
   bool timing = false;
   std::vector<std::pair<hipEvent_t, hipEvent_t>> ev[kNumTimers];
@@ -591,7 +607,7 @@ struct Impl {
     h->fx_inv = std::ldexp(1.0, -e);
   }
 
-  static StepK<R> step_consts(bfpic_ctx* h) {
+  static StepK<R> step_consts(bfpic_ctx* h, bool unscaled = false) {
     StepK<R> P;
     P.g = h->g;
     P.L = lattice(h);
@@ -614,7 +630,7 @@ struct Impl {
       P.kj[2] = (R)(1.0 / (h->dz * h->dx * h->dt));
     }
     P.ky2d = (R)(1.0 / (h->dz * h->dx));
-    if (h->det) {
+    if (h->det && !unscaled) {
       // deterministic mode: the deposit produces fixed-point units directly
       for (int a = 0; a < 3; a++) P.kj[a] = (R)((double)P.kj[a] * h->fx_scale);
       P.ky2d = (R)((double)P.ky2d * h->fx_scale);
@@ -791,19 +807,9 @@ struct Impl {
     return BFPIC_OK;
   }
 
-  static int one_step(bfpic_ctx* h) {
-    int rc = inject(h);
-    if (rc) return rc;
-    bool sort_due = h->cfg.sort_interval > 0 && h->step > 0 &&
-                    h->step % h->cfg.sort_interval == 0;
-    if (sort_due) {
-      rc = sort(h);
-      if (rc) return rc;
-    }
+  // Yee update with Mur at open z ends: B half step, E step, B half step.
+  static int yee(bfpic_ctx* h) {
     const Geo& g = h->g;
-    StepK<R> P = step_consts(h);
-    rc = h->det ? particles_and_currents<true>(h, P) : particles_and_currents<false>(h, P);
-    if (rc) return rc;
     {
       Timer t(h, 3);
       YeeK<R> Y;
@@ -828,6 +834,24 @@ struct Impl {
       k_yee_b<R, DIM><<<nb, 256, 0, h->stream>>>(g, Y);
       HIPCHK(h, hipGetLastError());
     }
+    return BFPIC_OK;
+  }
+
+  static int one_step(bfpic_ctx* h) {
+    int rc = inject(h);
+    if (rc) return rc;
+    bool sort_due = h->cfg.sort_interval > 0 && h->step > 0 && !h->no_sort &&
+                    h->step % h->cfg.sort_interval == 0;
+    if (sort_due) {
+      rc = sort(h);
+      if (rc) return rc;
+    }
+    const Geo& g = h->g;
+    StepK<R> P = step_consts(h);
+    rc = h->det ? particles_and_currents<true>(h, P) : particles_and_currents<false>(h, P);
+    if (rc) return rc;
+    rc = yee(h);
+    if (rc) return rc;
     h->step++;
     if (h->cfg.auto_window && !g.periodic_z) {
       double t = (double)h->step * h->dt;
@@ -838,6 +862,312 @@ struct Impl {
       }
     }
     return BFPIC_OK;
+  }
+
+  // ------------------------------------------------------------------------
+  // Adjoint.  The caller's tape holds: one checkpoint of the state every
+  // `interval` steps (fields E, B; particle slots; device counters), the
+  // taped states of one segment (fields and particle state at the start of
+  // each step, after its injection), and the adjoint arrays.  Particle slots
+  // do not move during a taped run (no re-sort), so a slot is one particle
+  // from its injection to its removal.
+  // ------------------------------------------------------------------------
+  struct Tape {
+    uint8_t* ck = nullptr;  // checkpoint 0; checkpoint k at ck + k * ckb
+    int64_t ckb = 0;
+    uint8_t* sg = nullptr;  // taped step 0 of a segment; step s at sg + s * sgb
+    int64_t sgb = 0;
+    R* LE[3] = {};
+    R* LB[3] = {};
+    R* LJf[3] = {};  // adjoint of the filtered current
+    R* LJ[3] = {};   // adjoint of the deposited (unfiltered) current
+    R* mur = nullptr;
+    R* lxi[2] = {};
+    R* ldu[3] = {};
+    double* lw = nullptr;
+    int* idb = nullptr;     // birth id of every slot
+    double* acc = nullptr;  // [0] loss, [1] <lambda_F, F(0)>, [2..] density gradient
+    int64_t total = 0;
+  };
+  static int64_t gbytes(bfpic_ctx* h) { return h->g.rows * h->g.plane * (int64_t)sizeof(R); }
+  static Tape tape_map(bfpic_ctx* h, uint8_t* base, int nsteps, int interval) {
+    Tape T;
+    const int64_t fb = align256(gbytes(h)), ib = align256(h->cap * 4),
+                  rb = align256(h->cap * (int64_t)sizeof(R));
+    T.ckb = 6 * fb + ib + 6 * rb + 256;
+    T.sgb = 6 * fb + ib + 5 * rb + 256;
+    const int64_t ncp = cdiv(nsteps, interval);
+    int64_t o = 0;
+    auto take = [&](int64_t bytes) {
+      uint8_t* p = base ? base + o : nullptr;
+      o += align256(bytes);
+      return p;
+    };
+    T.ck = take(ncp * T.ckb);
+    T.sg = take((int64_t)interval * T.sgb);
+    for (int c = 0; c < 3; c++) T.LE[c] = (R*)take(fb);
+    for (int c = 0; c < 3; c++) T.LB[c] = (R*)take(fb);
+    for (int c = 0; c < 3; c++) T.LJf[c] = (R*)take(fb);
+    for (int c = 0; c < 3; c++) T.LJ[c] = (R*)take(fb);
+    T.mur = (R*)take(4 * h->g.plane * (int64_t)sizeof(R));
+    for (int a = 0; a < 2; a++) T.lxi[a] = (R*)take(rb);
+    for (int a = 0; a < 3; a++) T.ldu[a] = (R*)take(rb);
+    T.lw = (double*)take(h->cap * 8);
+    T.idb = (int*)take(ib);
+    T.acc = (double*)take(8 * (2 + kMaxKnots));
+    T.total = o;
+    return T;
+  }
+  // byte offsets inside a checkpoint (ck = true) or a taped step
+  static int64_t off_f(bfpic_ctx* h, int c) { return c * align256(gbytes(h)); }
+  static int64_t off_id(bfpic_ctx* h) { return 6 * align256(gbytes(h)); }
+  static int64_t off_r(bfpic_ctx* h, int k) {  // k: xi0 xi1 du0 du1 du2 w
+    return off_id(h) + align256(h->cap * 4) + k * align256(h->cap * (int64_t)sizeof(R));
+  }
+  static int64_t off_tail(bfpic_ctx* h, bool ck) { return off_r(h, ck ? 6 : 5); }
+
+  static int copy(bfpic_ctx* h, void* dst, const void* src, int64_t bytes) {
+    if (bytes > 0)
+      HIPCHK(h, hipMemcpyAsync(dst, src, (size_t)bytes, hipMemcpyDeviceToDevice, h->stream));
+    return BFPIC_OK;
+  }
+
+  // Copy the state to (save) or from (!save) checkpoint k.
+  static int checkpoint(bfpic_ctx* h, const Tape& T, int k, bool save) {
+    uint8_t* b = T.ck + (int64_t)k * T.ckb;
+    if (!save) {
+      const bfpic_ctx::HostCkpt& c = h->ckpt[k];
+      h->step = c.step;
+      h->window_cells = c.window_cells;
+      h->next_col = c.next_col;
+      h->slots_bound = c.slots_bound;
+      h->tail_bound = c.tail_bound;
+      h->cur = c.cur;
+    }
+    const int64_t n = h->slots_bound, gb = gbytes(h);
+    void* parts[7] = {h->pid[h->cur], h->pxi[h->cur][0], h->pxi[h->cur][1], h->pdu[h->cur][0],
+                      h->pdu[h->cur][1], h->pdu[h->cur][2], h->pw[h->cur]};
+    int rc = 0;
+    for (int c = 0; c < 6 && !rc; c++)
+      rc = save ? copy(h, b + off_f(h, c), h->F[c], gb) : copy(h, h->F[c], b + off_f(h, c), gb);
+    for (int q = 0; q < 7 && !rc; q++) {
+      uint8_t* t = b + (q == 0 ? off_id(h) : off_r(h, q - 1));
+      const int64_t bytes = n * (q == 0 ? 4 : (int64_t)sizeof(R));
+      rc = save ? copy(h, t, parts[q], bytes) : copy(h, parts[q], t, bytes);
+    }
+    if (!rc)
+      rc = save ? copy(h, b + off_tail(h, true), h->counts, 16 * 4)
+                : copy(h, h->counts, b + off_tail(h, true), 16 * 4);
+    if (rc) return rc;
+    if (save) h->ckpt[k] = {h->step, h->window_cells, h->next_col, h->slots_bound, h->tail_bound,
+                            h->cur};
+    return BFPIC_OK;
+  }
+
+  // One step of a taped run; slot >= 0 also stores the state at the start of
+  // the step (after injection) as taped step `slot`.
+  static int taped_step(bfpic_ctx* h, const Tape& T, int slot) {
+    int rc = inject(h);
+    if (rc) return rc;
+    const int64_t n = h->slots_bound;
+    if (n > 0)
+      k_note_ids<<<(unsigned)cdiv(n, 256), 256, 0, h->stream>>>((const int*)h->pid[h->cur],
+                                                                 h->counts, T.idb);
+    if (slot >= 0) {
+      uint8_t* b = T.sg + (int64_t)slot * T.sgb;
+      const int64_t gb = gbytes(h);
+      for (int c = 0; c < 6 && !rc; c++) rc = copy(h, b + off_f(h, c), h->F[c], gb);
+      void* parts[6] = {h->pid[h->cur], h->pxi[h->cur][0], h->pxi[h->cur][1], h->pdu[h->cur][0],
+                        h->pdu[h->cur][1], h->pdu[h->cur][2]};
+      for (int q = 0; q < 6 && !rc; q++)
+        rc = copy(h, b + (q == 0 ? off_id(h) : off_r(h, q - 1)), parts[q],
+                  n * (q == 0 ? 4 : (int64_t)sizeof(R)));
+      if (!rc) rc = copy(h, b + off_tail(h, false), h->counts, 4);
+      if (rc) return rc;
+    }
+    StepK<R> P = step_consts(h);
+    rc = h->det ? particles_and_currents<true>(h, P) : particles_and_currents<false>(h, P);
+    if (rc) return rc;
+    rc = yee(h);
+    if (rc) return rc;
+    h->step++;
+    const bfpic_loss& L = h->adj_loss;
+    if (!h->adj_recompute && h->step >= L.step_first && h->step <= L.step_last) {
+      const int nb = (L.i1 - L.i0 + 1) * (L.j1 - L.j0 + 1);
+      const double sc = 1.0 / ((double)(L.step_last - L.step_first + 1) * nb);
+      k_loss_ez<R><<<(unsigned)std::min<int64_t>(cdiv(nb, 256), 256), 256, 0, h->stream>>>(
+          h->g, (const R*)h->F[2], L.i0, L.i1, L.j0, L.j1, sc, T.acc);
+      HIPCHK(h, hipGetLastError());
+    }
+    return BFPIC_OK;
+  }
+
+  static int adjoint_check(bfpic_ctx* h, int nsteps, int interval) {
+    if constexpr (DIM != 2) {
+      return fail(h, BFPIC_ERR_UNSUPPORTED, "the adjoint is built for 2D runs");
+    } else {
+      if (!h->inited) return fail(h, BFPIC_ERR_STATE, "init_boosted_plasma first");
+      if (nsteps < 1 || interval < 1) return fail(h, BFPIC_ERR_ARG, "nsteps, interval >= 1");
+      if (h->cfg.auto_window || h->cfg.beta_window != 0.0)
+        return fail(h, BFPIC_ERR_UNSUPPORTED, "the adjoint is built for runs without window");
+      return BFPIC_OK;
+    }
+  }
+
+  static int forward_loss(bfpic_ctx* h, int nsteps, int interval, const bfpic_loss* L,
+                          void* tape, int64_t tape_bytes, double* out) {
+    int rc = adjoint_check(h, nsteps, interval);
+    if (rc) return rc;
+    if (h->step != 0) return fail(h, BFPIC_ERR_STATE, "a taped run starts right after init");
+    const int rz = h->g.periodic_z ? h->nz - 1 : h->nz - 1;
+    if (L->step_first < 1 || L->step_last > nsteps || L->step_first > L->step_last ||
+        L->i0 < 0 || L->i1 > rz || L->i0 > L->i1 || L->j0 < 0 || L->j1 >= h->nx || L->j0 > L->j1)
+      return fail(h, BFPIC_ERR_ARG, "loss window or box out of range");
+    Tape T = tape_map(h, (uint8_t*)tape, nsteps, interval);
+    if (!tape || tape_bytes < T.total || ((uintptr_t)tape & 255))
+      return fail(h, BFPIC_ERR_ARG, "tape too small or misaligned");
+    h->tape = (uint8_t*)tape;
+    h->tape_bytes = tape_bytes;
+    h->adj_nsteps = nsteps;
+    h->adj_interval = interval;
+    h->adj_loss = *L;
+    h->adj_ready = false;
+    h->adj_recompute = false;
+    h->no_sort = true;
+    h->ckpt.assign((size_t)cdiv(nsteps, interval), bfpic_ctx::HostCkpt{});
+    HIPCHK(h, hipMemsetAsync(T.acc, 0, 8 * (2 + kMaxKnots), h->stream));
+    HIPCHK(h, hipMemsetAsync(T.idb, 0xff, (size_t)h->cap * 4, h->stream));
+    for (int s = 0; s < nsteps; s++) {
+      if (s % interval == 0) {
+        rc = checkpoint(h, T, s / interval, true);
+        if (rc) return rc;
+      }
+      rc = taped_step(h, T, -1);
+      if (rc) return rc;
+    }
+    h->adj_slots = h->slots_bound;
+    double v = 0.0;
+    HIPCHK(h, hipMemcpyAsync(&v, T.acc, 8, hipMemcpyDeviceToHost, h->stream));
+    HIPCHK(h, hipStreamSynchronize(h->stream));
+    *out = v;
+    h->adj_ready = true;
+    return BFPIC_OK;
+  }
+
+  static int adjoint(bfpic_ctx* h, double* da0, double* dn, int nn) {
+    if constexpr (DIM != 2) {
+      return fail(h, BFPIC_ERR_UNSUPPORTED, "the adjoint is built for 2D runs");
+    } else {
+      if (!h->adj_ready) return fail(h, BFPIC_ERR_STATE, "no taped forward run");
+      const int nk = h->dens.nknots >= 2 ? h->dens.nknots : 1;
+      if (nn < nk) return fail(h, BFPIC_ERR_ARG, "density gradient needs one value per knot");
+      const int nsteps = h->adj_nsteps, interval = h->adj_interval;
+      Tape T = tape_map(h, h->tape, nsteps, interval);
+      const Geo& g = h->g;
+      const int64_t gb = gbytes(h);
+      for (int c = 0; c < 3; c++) {
+        HIPCHK(h, hipMemsetAsync(T.LE[c], 0, gb, h->stream));
+        HIPCHK(h, hipMemsetAsync(T.LB[c], 0, gb, h->stream));
+        HIPCHK(h, hipMemsetAsync(T.LJf[c], 0, gb, h->stream));
+        HIPCHK(h, hipMemsetAsync(T.LJ[c], 0, gb, h->stream));
+      }
+      const int64_t rb = h->cap * (int64_t)sizeof(R);
+      for (int a = 0; a < 2; a++) HIPCHK(h, hipMemsetAsync(T.lxi[a], 0, rb, h->stream));
+      for (int a = 0; a < 3; a++) HIPCHK(h, hipMemsetAsync(T.ldu[a], 0, rb, h->stream));
+      HIPCHK(h, hipMemsetAsync(T.lw, 0, h->cap * 8, h->stream));
+      const bfpic_loss& L = h->adj_loss;
+      const int nbox = (L.i1 - L.i0 + 1) * (L.j1 - L.j0 + 1);
+      const R lsc = (R)(1.0 / ((double)(L.step_last - L.step_first + 1) * nbox));
+      AdjYeeK<R> Y;
+      for (int c = 0; c < 3; c++) {
+        Y.LE[c] = T.LE[c];
+        Y.LB[c] = T.LB[c];
+        Y.LJ[c] = T.LJf[c];
+      }
+      Y.idz = (R)(1.0 / h->dz);
+      Y.idx = (R)(1.0 / h->dx);
+      const R mur = (R)((h->dt - h->dz) / (h->dt + h->dz));
+      const int64_t nrow = g.periodic_z ? h->nz : h->nz + 1;
+      const unsigned nbg = (unsigned)cdiv(nrow * g.plane, 256);
+      const unsigned nbp = (unsigned)cdiv(g.plane, 256);
+      FiltK fk = filt(h);
+      const int fnbz = (int)cdiv(h->nz + 1, kF2Z), fnbx = (int)cdiv(h->nx, kF2X);
+      const size_t flds = 2 * sizeof(R) * (kF2Z + 2 * fk.H) * (kF2X + 2 * fk.H);
+      Fields<R> LJ, LF;
+      for (int c = 0; c < 3; c++) {
+        LJ.F[c] = T.LJ[c];
+        LF.F[c] = T.LE[c];
+        LF.F[3 + c] = T.LB[c];
+        LJ.F[3 + c] = nullptr;
+      }
+      AdjSlots<R> A;
+      for (int a = 0; a < 2; a++) A.lxi[a] = T.lxi[a];
+      for (int a = 0; a < 3; a++) A.ldu[a] = T.ldu[a];
+      A.lw = T.lw;
+      const int ncp = (int)cdiv(nsteps, interval);
+      for (int k = ncp - 1; k >= 0; k--) {
+        const int s0 = k * interval, s1 = std::min(nsteps, s0 + interval);
+        int rc = checkpoint(h, T, k, false);
+        if (rc) return rc;
+        h->adj_recompute = true;
+        for (int s = s0; s < s1; s++) {
+          rc = taped_step(h, T, s - s0);
+          if (rc) return rc;
+        }
+        for (int s = s1 - 1; s >= s0; s--) {
+          if (s + 1 >= L.step_first && s + 1 <= L.step_last)
+            k_loss_ez_adj<R><<<(unsigned)cdiv(nbox, 256), 256, 0, h->stream>>>(
+                g, T.LE[2], L.i0, L.i1, L.j0, L.j1, lsc);
+          Y.h = (R)(0.5 * h->dt);
+          k_adj_yee_b<R><<<nbg, 256, 0, h->stream>>>(g, Y);
+          if (!g.periodic_z) k_adj_mur_pre<R><<<nbp, 256, 0, h->stream>>>(g, Y, mur, T.mur);
+          Y.h = (R)h->dt;
+          k_adj_yee_e<R><<<nbg, 256, 0, h->stream>>>(g, Y);
+          if (!g.periodic_z) k_adj_mur_post<R><<<nbp, 256, 0, h->stream>>>(g, Y, T.mur);
+          Y.h = (R)(0.5 * h->dt);
+          k_adj_yee_b<R><<<nbg, 256, 0, h->stream>>>(g, Y);
+          for (int c = 0; c < 3; c++)
+            k_filter_grid_r<R, kF2Z, kF2X><<<(unsigned)(fnbz * fnbx), 256, flds, h->stream>>>(
+                g, fk, T.LJf[c], T.LJ[c], c == 2 ? 1 : 0, fnbz, fnbx);
+          // particles of step s
+          uint8_t* b = T.sg + (int64_t)(s - s0) * T.sgb;
+          const int64_t save_step = h->step;
+          h->step = s;
+          StepK<R> P = step_consts(h, true);
+          h->step = save_step;
+          Fields<R> F;
+          for (int c = 0; c < 6; c++) F.F[c] = (R*)(b + off_f(h, c));
+          TapeParticles<R> TP;
+          TP.id = (const int*)(b + off_id(h));
+          for (int a = 0; a < 2; a++) TP.xi[a] = (const R*)(b + off_r(h, a));
+          for (int a = 0; a < 3; a++) TP.du[a] = (const R*)(b + off_r(h, 2 + a));
+          TP.w = (const R*)h->pw[h->cur];
+          TP.count = (const int*)(b + off_tail(h, false));
+          const unsigned nbq = (unsigned)std::max<int64_t>(1, std::min<int64_t>(
+                                   cdiv(std::max<int64_t>(h->slots_bound, 1), 256), 4096));
+          k_adj_particles<R, ORDER><<<nbq, 256, 0, h->stream>>>(P, F, TP, LJ, LF, A);
+          HIPCHK(h, hipGetLastError());
+        }
+      }
+      h->adj_recompute = false;
+      // parameter gradients
+      HIPCHK(h, hipMemsetAsync(T.acc + 1, 0, 8 * (1 + kMaxKnots), h->stream));
+      for (int c = 0; c < 6; c++) {
+        const R* lam = c < 3 ? T.LE[c] : T.LB[c - 3];
+        k_dot_fields<R><<<256, 256, 0, h->stream>>>(lam, (const R*)(T.ck + off_f(h, c)),
+                                                   g.rows * g.plane, T.acc + 1);
+      }
+      // every slot the forward run created
+      const int64_t nslots = h->adj_slots;
+      k_knot_grad<<<256, 256, 0, h->stream>>>(T.idb, T.lw, nslots, lattice(h), h->dens, T.acc + 2);
+      HIPCHK(h, hipGetLastError());
+      double host[2 + kMaxKnots];
+      HIPCHK(h, hipMemcpyAsync(host, T.acc, sizeof(host), hipMemcpyDeviceToHost, h->stream));
+      HIPCHK(h, hipStreamSynchronize(h->stream));
+      *da0 = h->laser_a0 != 0.0 ? host[1] / h->laser_a0 : 0.0;
+      for (int m = 0; m < nk; m++) dn[m] = host[2 + m];
+      return BFPIC_OK;
+    }
   }
 
   static int steps(bfpic_ctx* h, int n) {
@@ -873,6 +1203,9 @@ struct Impl {
     h->window_cells = 0;
     h->next_col = 0;
     h->has_plasma = d != nullptr;
+    h->laser_a0 = laser ? laser->a0 : 0.0;
+    h->adj_ready = false;
+    h->no_sort = false;
     h->slots_bound = 0;
     h->tail_bound = 0;
     h->have_sort = false;
@@ -1082,6 +1415,9 @@ struct Impl {
   } while (0)
 
 static int prepare_kernels(bfpic_ctx* h) { BFPIC_DISPATCH(h, I::prepare(h)); }
+static int tape_bytes_of(bfpic_ctx* h, int nsteps, int interval, int64_t* out) {
+  BFPIC_DISPATCH(h, (*out = I::tape_map(h, nullptr, nsteps, interval).total, BFPIC_OK));
+}
 
 // ---------------------------------------------------------------------------
 // C ABI
@@ -1283,4 +1619,26 @@ extern "C" int bfpic_kernel_time(bfpic_ctx* h, int32_t cls, double* total_ms, in
   *total_ms = tot;
   *launches = (int64_t)h->ev[cls].size();
   return BFPIC_OK;
+}
+
+// ---------------------------------------------------------------------------
+// Adjoint
+// ---------------------------------------------------------------------------
+extern "C" int bfpic_adjoint_tape_bytes(bfpic_ctx* h, int32_t nsteps, int32_t interval,
+                                        int64_t* bytes) {
+  if (!h || !bytes || nsteps < 1 || interval < 1) return BFPIC_ERR_ARG;
+  if (h->dim != 2) return fail(h, BFPIC_ERR_UNSUPPORTED, "the adjoint is built for 2D runs");
+  return tape_bytes_of(h, nsteps, interval, bytes);
+}
+
+extern "C" int bfpic_forward_loss(bfpic_ctx* h, int32_t nsteps, int32_t interval,
+                                  const bfpic_loss* loss, void* tape, int64_t tape_bytes,
+                                  double* loss_out) {
+  if (!h || !loss || !loss_out) return BFPIC_ERR_ARG;
+  BFPIC_DISPATCH(h, I::forward_loss(h, nsteps, interval, loss, tape, tape_bytes, loss_out));
+}
+
+extern "C" int pic_step_adjoint(bfpic_ctx* h, double* dL_da0, double* dL_dn, int32_t nn) {
+  if (!h || !dL_da0 || !dL_dn) return BFPIC_ERR_ARG;
+  BFPIC_DISPATCH(h, I::adjoint(h, dL_da0, dL_dn, nn));
 }

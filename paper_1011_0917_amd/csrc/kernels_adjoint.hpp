@@ -1,0 +1,499 @@
+// kernels_adjoint.hpp -- reverse sweep of the 2D PIC step, for the gradient
+// of a field loss with respect to the laser amplitude and the plasma density
+// profile.
+//
+// The step is the composition
+//   gather -> push -> move -> deposit -> filter -> Yee (B half, E + Mur, B half)
+// and its adjoint runs the transposes in reverse order:
+//   * Yee and Mur are linear; their transposes are written out term by term
+//     from the forward updates (k_adj_yee_b, k_adj_yee_e, k_adj_mur_*);
+//   * the binomial filter with its open-boundary masking is symmetric, so its
+//     transpose is the filter itself, applied to the current adjoint;
+//   * per particle, the vector-Jacobian product of gather, push, move and
+//     deposit is formed with forward-mode dual numbers: the same templated
+//     step the forward kernels run is evaluated once per input direction
+//     (positions 2, momenta 3, weight 1, gathered E and B 6) and contracted
+//     with the adjoints of its outputs; the gathered-field directions are then
+//     scattered to the field adjoint with the gather's own weights.
+#pragma once
+
+#include <type_traits>
+
+#include "device_common.hpp"
+#include "kernels_fields.hpp"
+#include "kernels_particles.hpp"
+
+namespace bfpic {
+
+// --------------------------------------------------------------------------
+// Forward-mode dual number: value v and one tangent d.  Comparisons order by
+// value; equality also compares the tangent, so that a branch that skips a
+// zero value (an out-of-plane current with v_y = 0) still runs when the value
+// has a non-zero derivative.  The math functions are hidden friends, found
+// only through argument-dependent lookup.
+// --------------------------------------------------------------------------
+template <typename T>
+struct Dual {
+  T v, d;
+  __device__ __forceinline__ Dual() : v((T)0), d((T)0) {}
+  __device__ __forceinline__ Dual(double x) : v((T)x), d((T)0) {}
+  __device__ __forceinline__ static Dual mk(T v, T d) {
+    Dual r;
+    r.v = v;
+    r.d = d;
+    return r;
+  }
+  __device__ __forceinline__ explicit operator int() const { return (int)v; }
+
+  friend __device__ __forceinline__ Dual operator+(Dual a, Dual b) { return mk(a.v + b.v, a.d + b.d); }
+  friend __device__ __forceinline__ Dual operator-(Dual a, Dual b) { return mk(a.v - b.v, a.d - b.d); }
+  friend __device__ __forceinline__ Dual operator-(Dual a) { return mk(-a.v, -a.d); }
+  friend __device__ __forceinline__ Dual operator*(Dual a, Dual b) {
+    return mk(a.v * b.v, a.d * b.v + a.v * b.d);
+  }
+  friend __device__ __forceinline__ Dual operator/(Dual a, Dual b) {
+    const T q = a.v / b.v;
+    return mk(q, (a.d - q * b.d) / b.v);
+  }
+  __device__ __forceinline__ Dual& operator+=(Dual b) { return *this = *this + b; }
+  __device__ __forceinline__ Dual& operator-=(Dual b) { return *this = *this - b; }
+  __device__ __forceinline__ Dual& operator*=(Dual b) { return *this = *this * b; }
+  __device__ __forceinline__ Dual& operator/=(Dual b) { return *this = *this / b; }
+  friend __device__ __forceinline__ bool operator<(Dual a, Dual b) { return a.v < b.v; }
+  friend __device__ __forceinline__ bool operator<=(Dual a, Dual b) { return a.v <= b.v; }
+  friend __device__ __forceinline__ bool operator>(Dual a, Dual b) { return a.v > b.v; }
+  friend __device__ __forceinline__ bool operator>=(Dual a, Dual b) { return a.v >= b.v; }
+  friend __device__ __forceinline__ bool operator==(Dual a, Dual b) { return a.v == b.v && a.d == b.d; }
+  friend __device__ __forceinline__ bool operator!=(Dual a, Dual b) { return !(a == b); }
+  friend __device__ __forceinline__ Dual floor(Dual a) { return mk(floor(a.v), (T)0); }
+  friend __device__ __forceinline__ Dual sqrt(Dual a) {
+    const T s = sqrt(a.v);
+    return mk(s, s > (T)0 ? a.d / (s + s) : (T)0);
+  }
+  friend __device__ __forceinline__ Dual rcp(Dual a) {
+    const T r = rcp(a.v);
+    return mk(r, -a.d * r * r);
+  }
+};
+
+template <typename T>
+__device__ __forceinline__ PushC<Dual<T>> dualize(const PushC<T>& p) {
+  PushC<Dual<T>> q;
+  q.ub = p.ub;
+  q.gb = p.gb;
+  q.gb2 = p.gb2;
+  q.qdt2 = p.qdt2;
+  return q;
+}
+
+template <typename T>
+__device__ __forceinline__ Drift<Dual<T>> dualize(const Drift<T>& p) {
+  Drift<Dual<T>> q;
+  q.Dint = p.Dint;
+  q.Dfrac = p.Dfrac;
+  return q;
+}
+
+template <typename T>
+__device__ __forceinline__ StepK<Dual<T>> dualize(const StepK<T>& p) {
+  StepK<Dual<T>> q;
+  q.g = p.g;
+  q.L = p.L;
+  q.push = dualize(p.push);
+  q.D0 = dualize(p.D0);
+  q.D1 = dualize(p.D1);
+  for (int a = 0; a < 3; a++) {
+    q.dtd[a] = p.dtd[a];
+    q.kj[a] = p.kj[a];
+  }
+  q.ky2d = p.ky2d;
+  q.ion_moves = p.ion_moves;
+  q.remove = p.remove;
+  q.lim = p.lim;
+  return q;
+}
+
+// Field fetch of constant grid values as duals.
+template <typename T>
+struct DualFetch {
+  const T* const* F;
+  Geo g;
+  __device__ __forceinline__ Dual<T> operator()(int comp, int i, int j, int k) const {
+    const int64_t n = gidx(g, i, j, k);
+    return Dual<T>(n < 0 ? 0.0 : (double)F[comp][n]);
+  }
+};
+
+// Current "sink" of the adjoint: contracts each current contribution's
+// tangent with the current adjoint at its node.
+template <typename T>
+struct AdjJSink {
+  const T* const* lj;  // adjoint of the unfiltered current, Jx Jy Jz
+  Geo g;
+  T* acc;
+  __device__ __forceinline__ void add(int comp, int i, int j, int k, Dual<T> v) const {
+    const int64_t n = gidx(g, i, j, k);
+    if (n >= 0) *acc += lj[comp][n] * v.d;
+  }
+};
+
+// Seeds the tangent of one gathered field component (direction 6..11).
+template <typename T>
+struct SeedFields {
+  int dir;
+  __device__ __forceinline__ void operator()(Dual<T>* E, Dual<T>* B) const {
+    if (dir >= 6 && dir < 9) E[dir - 6].d = (T)1;
+    if (dir >= 9 && dir < 12) B[dir - 9].d = (T)1;
+  }
+};
+
+// Transpose of the gather: g times the gather weight of every node, added to
+// the field adjoint (same shapes and staggering as `gather`).
+// Nodes outside a component's domain rows hold constant zeros, not state:
+// they take no adjoint.
+template <typename R, int ORDER>
+__device__ __forceinline__ void scatter_node_weights(R* const* lf, const Geo& g, int comp, int bz,
+                                                     const R* wz, int bx, const R* wx, R gv) {
+  if (gv == (R)0) return;
+  const int hz = half_z_eb(comp);
+#pragma unroll
+  for (int a = 0; a <= ORDER; a++) {
+    if (!g.periodic_z && !in_domain(g, hz, bz + a)) continue;
+#pragma unroll
+    for (int b = 0; b <= ORDER; b++) {
+      const int64_t n = gidx(g, bz + a, bx + b, 0);
+      if (n >= 0) atomicAdd(&lf[comp][n], gv * wz[a] * wx[b]);
+    }
+  }
+}
+
+template <typename R, int ORDER>
+__device__ __forceinline__ void gather_transpose(R* const* lf, const Geo& g, const Pos<R>& p,
+                                                 const R gE[3], const R gB[3]) {
+  R wz0[ORDER + 1], wz1[ORDER + 1], wx0[ORDER + 1], wx1[ORDER + 1];
+  const int z0 = shape<R, ORDER>(p.c[0], p.o[0], 0, wz0);
+  const int z1 = shape<R, ORDER>(p.c[0], p.o[0], 1, wz1);
+  const int x0 = shape<R, ORDER>(p.c[1], p.o[1], 0, wx0);
+  const int x1 = shape<R, ORDER>(p.c[1], p.o[1], 1, wx1);
+  // staggering (z, x): Ex (0,h) Ey (0,0) Ez (h,0) Bx (h,0) By (h,h) Bz (0,h)
+  scatter_node_weights<R, ORDER>(lf, g, 0, z0, wz0, x1, wx1, gE[0]);
+  scatter_node_weights<R, ORDER>(lf, g, 1, z0, wz0, x0, wx0, gE[1]);
+  scatter_node_weights<R, ORDER>(lf, g, 2, z1, wz1, x0, wx0, gE[2]);
+  scatter_node_weights<R, ORDER>(lf, g, 3, z1, wz1, x0, wx0, gB[0]);
+  scatter_node_weights<R, ORDER>(lf, g, 4, z1, wz1, x1, wx1, gB[1]);
+  scatter_node_weights<R, ORDER>(lf, g, 5, z0, wz0, x1, wx1, gB[2]);
+}
+
+// Per-slot adjoint state: adjoints of the displacement and momentum carried
+// backwards from step to step, and the accumulated weight adjoint.
+template <typename R>
+struct AdjSlots {
+  R* lxi[2];
+  R* ldu[3];
+  double* lw;
+};
+
+// Particle state of one taped step (after that step's injection).
+template <typename R>
+struct TapeParticles {
+  const int* id;
+  const R* xi[2];
+  const R* du[3];
+  const R* w;         // weights (constant per slot)
+  const int* count;   // number of slots during the step
+};
+
+// One reverse particle step (2D): for every live slot, the vector-Jacobian
+// product of (xi, du, w, E_p, B_p) -> (xi', du', J) with the adjoints of xi',
+// du' (in A, overwritten with those of xi, du) and of J (lj); the weight
+// adjoint accumulates; the E_p, B_p directions go to the field adjoint lf.
+template <typename R, int ORDER>
+__global__ __launch_bounds__(256) void k_adj_particles(StepK<R> P, Fields<R> F,
+                                                       TapeParticles<R> T, Fields<R> LJ,
+                                                       Fields<R> LF, AdjSlots<R> A) {
+  using D = Dual<R>;
+  const StepK<D> PD = dualize(P);
+  const Geo& g = P.g;
+  const int n = *T.count;
+  DualFetch<R> fetch{(const R* const*)F.F, g};
+  for (int p = blockIdx.x * blockDim.x + threadIdx.x; p < n; p += gridDim.x * blockDim.x) {
+    const int id = T.id[p];
+    if (id < 0) continue;
+    const R xi0 = T.xi[0][p], xi1 = T.xi[1][p];
+    const R du0 = T.du[0][p], du1 = T.du[1][p], du2 = T.du[2][p];
+    const R w = T.w[p];
+    const Birth b = decode_id(P.L, id);
+    R r[3];
+    birth_offsets<R, 2>(P.L, id, r);
+    D rd[3] = {D((double)r[0]), D((double)r[1]), D(0.0)};
+    const Pos<D> i0 = ion_at<D, 2>(b, rd, PD.D0);
+    const Pos<D> i1 = ion_at<D, 2>(b, rd, PD.D1);
+    const R lx0 = A.lxi[0][p], lx1 = A.lxi[1][p];
+    const R lu0 = A.ldu[0][p], lu1 = A.ldu[1][p], lu2 = A.ldu[2][p];
+    R gdir[12];
+#pragma unroll 1
+    for (int dir = 0; dir < 12; dir++) {
+      D xi[3] = {D((double)xi0), D((double)xi1), D(0.0)};
+      D du[3] = {D((double)du0), D((double)du1), D((double)du2)};
+      D wd = D((double)w);
+      if (dir < 2) xi[dir].d = (R)1;
+      else if (dir < 5) du[dir - 2].d = (R)1;
+      else if (dir == 5) wd.d = (R)1;
+      R acc = (R)0;
+      AdjJSink<R> snk{(const R* const*)LJ.F, g, &acc};
+      const Pos<D> e0 = add_xi<D, 2>(i0, xi);
+      const int bc[3] = {e0.c[0], e0.c[1], 0};
+      (void)particle_step<D, 2, ORDER>(PD, fetch, snk, bc, e0, i0, i1, xi, du, wd,
+                                       SeedFields<R>{dir});
+      gdir[dir] = acc + lx0 * xi[0].d + lx1 * xi[1].d + lu0 * du[0].d + lu1 * du[1].d +
+                  lu2 * du[2].d;
+    }
+    A.lxi[0][p] = gdir[0];
+    A.lxi[1][p] = gdir[1];
+    A.ldu[0][p] = gdir[2];
+    A.ldu[1][p] = gdir[3];
+    A.ldu[2][p] = gdir[4];
+    A.lw[p] += (double)gdir[5];
+    // gather transpose at the primal position
+    R xr[3] = {xi0, xi1, (R)0};
+    const Pos<R> e0p = add_xi<R, 2>(ion_at<R, 2>(b, r, P.D0), xr);
+    const R gE[3] = {gdir[6], gdir[7], gdir[8]}, gB[3] = {gdir[9], gdir[10], gdir[11]};
+    gather_transpose<R, ORDER>(LF.F, g, e0p, gE, gB);
+  }
+}
+
+// --------------------------------------------------------------------------
+// Transposes of the 2D Yee updates.  The forward updates are
+//   B half step (h = dt/2), rows [0, nrow):
+//     Bx(i)   += h (Ey(i+1) - Ey(i)) / dz                      [half-z rows]
+//     By(i,j) += h ((Ez(i,j+1) - Ez(i,j)) / dx - (Ex(i+1) - Ex(i)) / dz)  [half-z rows]
+//     Bz(i,j) -= h (Ey(i,j+1) - Ey(i,j)) / dx
+//   E step (h = dt), Ex, Ey on rows R (open z: 1..nz-1, the ends are Mur's):
+//     Ez(i,j) += h ((By(i,j) - By(i,j-1)) / dx - Jz)          [half-z rows]
+//     Ex(i)   += h (-(By(i) - By(i-1)) / dz - Jx)
+//     Ey(i,j) += h ((Bx(i) - Bx(i-1)) / dz - (Bz(i,j) - Bz(i,j-1)) / dx - Jy)
+// Adjoint arrays are zero outside each component's domain rows, so the
+// neighbour reads below need no row tests beyond R.
+// --------------------------------------------------------------------------
+template <typename R>
+struct AdjYeeK {
+  R* LE[3];
+  R* LB[3];
+  R* LJ[3];  // adjoint of the filtered current (written by the E transpose)
+  R idz, idx;
+  R h;
+};
+
+// lambda_E += h K_E^T lambda_B (the B half step's transpose; lambda_B unchanged)
+template <typename R>
+__global__ __launch_bounds__(256) void k_adj_yee_b(Geo g, AdjYeeK<R> Y) {
+  const int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int nrow = g.periodic_z ? g.nz : g.nz + 1;
+  if (v >= (int64_t)nrow * g.plane) return;
+  const int i = (int)(v / g.plane);
+  const int j = (int)(v - (int64_t)i * g.plane);
+  const int64_t n = gidx(g, i, j, 0);
+  const R* LBx = Y.LB[0];
+  const R* LBy = Y.LB[1];
+  const R* LBz = Y.LB[2];
+  const R h = Y.h;
+  Y.LE[0][n] += h * Y.idz * (LBy[n] - at(g, LBy, i - 1, j, 0));
+  Y.LE[1][n] += h * Y.idz * (at(g, LBx, i - 1, j, 0) - LBx[n]) +
+                h * Y.idx * (LBz[n] - at(g, LBz, i, j - 1, 0));
+  if (i <= row_hi(g, 1)) Y.LE[2][n] += h * Y.idx * (at(g, LBy, i, j - 1, 0) - LBy[n]);
+}
+
+// lambda_B += h K_B^T lambda_E|R ; lambda_J = -h lambda_E|R (lambda_E unchanged)
+template <typename R>
+__device__ __forceinline__ R lam_r(const Geo& g, const R* L, int i, int j) {
+  // lambda_E of Ex / Ey restricted to the rows the E step updates
+  if (!g.periodic_z && (i <= 0 || i >= g.nz)) return (R)0;
+  return at(g, L, i, j, 0);
+}
+
+template <typename R>
+__global__ __launch_bounds__(256) void k_adj_yee_e(Geo g, AdjYeeK<R> Y) {
+  const int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int nrow = g.periodic_z ? g.nz : g.nz + 1;
+  if (v >= (int64_t)nrow * g.plane) return;
+  const int i = (int)(v / g.plane);
+  const int j = (int)(v - (int64_t)i * g.plane);
+  const int64_t n = gidx(g, i, j, 0);
+  const R* LEx = Y.LE[0];
+  const R* LEy = Y.LE[1];
+  const R* LEz = Y.LE[2];
+  const R h = Y.h;
+  if (i <= row_hi(g, 1)) {
+    Y.LB[1][n] += h * Y.idx * (LEz[n] - at(g, LEz, i, j + 1, 0)) +
+                  h * Y.idz * (lam_r(g, LEx, i + 1, j) - lam_r(g, LEx, i, j));
+    Y.LB[0][n] += h * Y.idz * (lam_r(g, LEy, i, j) - lam_r(g, LEy, i + 1, j));
+    Y.LJ[2][n] = -h * LEz[n];
+  }
+  Y.LB[2][n] += h * Y.idx * (lam_r(g, LEy, i, j + 1) - lam_r(g, LEy, i, j));
+  Y.LJ[0][n] = -h * lam_r(g, LEx, i, j);
+  Y.LJ[1][n] = -h * lam_r(g, LEy, i, j);
+}
+
+// Mur at both z ends, forward: E(0) <- E_old(1) + m (E_new(1) - E_old(0)), the
+// same at nz from nz-1.  Transpose in two parts around the E transpose: first
+// the adjoint of E_new(1) takes m lambda(0) and lambda(0) becomes -m lambda(0)
+// (the adjoint of E_old(0)); after the E transpose the adjoint of E_old(1)
+// takes the saved lambda(0).
+template <typename R>
+__global__ __launch_bounds__(256) void k_adj_mur_pre(Geo g, AdjYeeK<R> Y, R mur, R* save) {
+  const int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (q >= g.plane) return;
+  const int j = (int)q;
+  for (int c = 0; c < 2; c++) {
+    R* L = Y.LE[c];
+    const int64_t n0 = gidx(g, 0, j, 0), n1 = gidx(g, 1, j, 0);
+    const int64_t m0 = gidx(g, g.nz, j, 0), m1 = gidx(g, g.nz - 1, j, 0);
+    const R t0 = L[n0], tm = L[m0];
+    save[(0 * 2 + c) * g.plane + q] = t0;
+    save[(1 * 2 + c) * g.plane + q] = tm;
+    L[n1] += mur * t0;
+    L[m1] += mur * tm;
+    L[n0] = -mur * t0;
+    L[m0] = -mur * tm;
+  }
+}
+
+template <typename R>
+__global__ __launch_bounds__(256) void k_adj_mur_post(Geo g, AdjYeeK<R> Y, const R* save) {
+  const int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (q >= g.plane) return;
+  const int j = (int)q;
+  for (int c = 0; c < 2; c++) {
+    R* L = Y.LE[c];
+    L[gidx(g, 1, j, 0)] += save[(0 * 2 + c) * g.plane + q];
+    L[gidx(g, g.nz - 1, j, 0)] += save[(1 * 2 + c) * g.plane + q];
+  }
+}
+
+// --------------------------------------------------------------------------
+// The filter on a plain grid array of the working precision (the current
+// adjoint); rows outside the component's domain are not written.
+// --------------------------------------------------------------------------
+template <typename R>
+struct GridSrcR {
+  const R* a;
+  Geo g;
+  __device__ __forceinline__ R operator()(int i, int j, int k) const {
+    const int64_t n = gidx(g, i, j, k);
+    return n < 0 ? (R)0 : a[n];
+  }
+};
+
+template <typename R, int FZ, int FX>
+__global__ __launch_bounds__(256) void k_filter_grid_r(Geo g, FiltK fk, const R* in, R* out,
+                                                       int half_z, int nbz, int nbx) {
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  R* lds = reinterpret_cast<R*>(smem_raw);
+  const int b = blockIdx.x;
+  const int bx = b % nbx, bz = b / nbx;
+  GridSrcR<R> src{in, g};
+  filter_tile<R, 2, FZ, FX, 1>(g, fk, half_z, bz * FZ, bx * FX, 0, src, out, lds);
+}
+
+// --------------------------------------------------------------------------
+// Loss: the mean of Ez over a node box [i0, i1] x [j0, j1], scaled, added to
+// acc (forward) or added to the Ez adjoint (reverse).
+// --------------------------------------------------------------------------
+template <typename R>
+__global__ __launch_bounds__(256) void k_loss_ez(Geo g, const R* Ez, int i0, int i1, int j0,
+                                                 int j1, double scale, double* acc) {
+  __shared__ double sh[256];
+  const int ni = i1 - i0 + 1, nj = j1 - j0 + 1;
+  double s = 0.0;
+  for (int q = blockIdx.x * blockDim.x + threadIdx.x; q < ni * nj; q += gridDim.x * blockDim.x) {
+    const int i = i0 + q / nj, j = j0 + q % nj;
+    s += (double)Ez[gidx(g, i, j, 0)];
+  }
+  sh[threadIdx.x] = s;
+  __syncthreads();
+  for (int o = 128; o > 0; o >>= 1) {
+    if ((int)threadIdx.x < o) sh[threadIdx.x] += sh[threadIdx.x + o];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) atomicAdd(acc, sh[0] * scale);
+}
+
+template <typename R>
+__global__ __launch_bounds__(256) void k_loss_ez_adj(Geo g, R* LEz, int i0, int i1, int j0,
+                                                     int j1, R scale) {
+  const int ni = i1 - i0 + 1, nj = j1 - j0 + 1;
+  const int q = blockIdx.x * blockDim.x + threadIdx.x;
+  if (q >= ni * nj) return;
+  LEz[gidx(g, i0 + q / nj, j0 + q % nj, 0)] += scale;
+}
+
+// --------------------------------------------------------------------------
+// Parameter gradients.
+//   a0: the initial fields are a0 times the unit pulse, so
+//       dL/da0 = <lambda_F(0), F(0)> / a0   (block partial sums of the product)
+//   density: w = gamma_b n_lab(z_lab) dV / ppc with n_lab piecewise linear in
+//       the knot values, so dL/dn_m = sum_p lambda_w gamma_b dV/ppc phi_m(z_lab)
+//       with phi_m the hat function of knot m (one value for a uniform n).
+// --------------------------------------------------------------------------
+template <typename R>
+__global__ __launch_bounds__(256) void k_dot_fields(const R* a, const R* b, int64_t n,
+                                                    double* out) {
+  __shared__ double sh[256];
+  double s = 0.0;
+  for (int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; q < n;
+       q += (int64_t)gridDim.x * blockDim.x)
+    s += (double)a[q] * (double)b[q];
+  sh[threadIdx.x] = s;
+  __syncthreads();
+  for (int o = 128; o > 0; o >>= 1) {
+    if ((int)threadIdx.x < o) sh[threadIdx.x] += sh[threadIdx.x + o];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) atomicAdd(out, sh[0]);
+}
+
+constexpr int kMaxKnots = 32;
+
+__global__ __launch_bounds__(256) void k_knot_grad(const int* id_birth, const double* lw,
+                                                   int64_t nslots, LatticeP L, DensityK d,
+                                                   double* out /* [kMaxKnots] */) {
+  __shared__ double sh[kMaxKnots];
+  const int nk = d.nknots >= 2 ? d.nknots : 1;
+  if ((int)threadIdx.x < kMaxKnots) sh[threadIdx.x] = 0.0;
+  __syncthreads();
+  for (int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; p < nslots;
+       p += (int64_t)gridDim.x * blockDim.x) {
+    const int id = id_birth[p];
+    if (id < 0) continue;
+    const double c = lw[p] * d.gamma_b * d.dV_over_ppc;
+    if (d.nknots < 2) {
+      atomicAdd(&sh[0], c);
+      continue;
+    }
+    const Birth b = decode_id(L, id);
+    const double rz = (double)birth_offset<double>(L, id, 0);
+    const double zl = d.gamma_b * ((double)b.k + rz) * d.dz;
+    if (zl < d.kz[0] || zl > d.kz[d.nknots - 1]) continue;
+    for (int m = 0; m + 1 < d.nknots; m++) {
+      if (zl <= d.kz[m + 1]) {
+        const double f = (zl - d.kz[m]) / (d.kz[m + 1] - d.kz[m]);
+        atomicAdd(&sh[m], c * (1.0 - f));
+        atomicAdd(&sh[m + 1], c * f);
+        break;
+      }
+    }
+  }
+  __syncthreads();
+  if ((int)threadIdx.x < nk) atomicAdd(&out[threadIdx.x], sh[threadIdx.x]);
+}
+
+// Birth ids of the slots: a slot keeps the id it was created with after its
+// particle is removed (the weight adjoint is needed for every particle).
+__global__ __launch_bounds__(256) void k_note_ids(const int* id, const int* counts, int* id_birth) {
+  const int p = blockIdx.x * blockDim.x + threadIdx.x;
+  if (p >= counts[0]) return;
+  const int v = id[p];
+  if (v >= 0) id_birth[p] = v;
+}
+
+}  // namespace bfpic

@@ -513,13 +513,20 @@ __device__ __forceinline__ void deposit3d(const StepK<R>& P, const Snk& snk, con
 // One particle step after its positions are known: gather at e0, push, move,
 // deposit, decide removal.  Returns the new displacement through xi.
 // --------------------------------------------------------------------------
-template <typename R, int DIM, int ORDER, class F, class Snk>
+// Called with the gathered fields before the push (the adjoint seeds them).
+struct NoHook {
+  template <typename R>
+  __device__ __forceinline__ void operator()(R*, R*) const {}
+};
+
+template <typename R, int DIM, int ORDER, class F, class Snk, class Hook = NoHook>
 __device__ __forceinline__ bool particle_step(const StepK<R>& P, const F& fetch, const Snk& snk,
                                               const int bc[3], const Pos<R>& e0,
                                               const Pos<R>& i0, const Pos<R>& i1, R xi[3],
-                                              R du[3], R w) {
+                                              R du[3], R w, const Hook& hook = Hook()) {
   R E[3], B[3], dv[3], gam;
   gather<R, DIM, ORDER>(fetch, bc, e0, E, B);
+  hook(E, B);
   boris_split(P.push, E, B, du, dv, gam);
   const R xi_old[3] = {xi[0], xi[1], xi[2]};
   // position axes (z, x, y) <- velocity components (z, x, y) = dv[2], dv[0], dv[1]

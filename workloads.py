@@ -52,6 +52,57 @@ WORKLOADS = {
 }
 
 
+# adjoint_2d: gamma_boost = 13, 1024 x 128, 4 ppc, 500 steps, a checkpoint every
+# 50 steps; lab density 1e-3 n_crit times a 16-knot piecewise-linear profile
+# (values 1 +- 0.1, seeded) over the lab length that crosses the box; loss =
+# mean of Ez over the last 100 steps in a box behind the pulse on axis.
+WORKLOADS["adjoint_2d"] = dict(
+    dim=2, nz=1024, nx=128, ny=1, gamma_b=13.0, dz_cells_per_wavelength=16, dx_lambda0=0.5,
+    cfl=0.95, n_lab=1e-3, ppc=4, order=1, filter_passes=4, filter_compensate=1, zbc="mur",
+    precision="fp32", steps=500, seed=1016, window=None, interval=50, nknots=16,
+    loss_steps=100,
+    laser=dict(a0=1.0, w0_lambda0=8.0, L_lambda0=4.0, place="front", front_gap=4.5,
+               collimated=1))
+
+
+def adjoint_setup(W, dz, beta, dt):
+    """Density knots (lab z, values), loss window and Ez box of an adjoint run.
+
+    The knots cover the lab length of every lattice column the run holds
+    (the box at t' = 0 plus the columns injected over the run).  The box spans
+    rows [i_L - 2.5 L', i_L - L'] behind the pulse centre i_L (L' the boosted
+    envelope length in cells), |j - nx/2| <= 4: within the 500 steps of the
+    adjoint configuration the wake forms just behind the pulse (an FP64 run
+    puts its on-axis Ez, ~1e-3, at rows 576..671 over steps 400..500, with
+    the pulse centre at row 736 at t' = 0); a box too short for that (a pulse
+    as long as a small box) is 9 rows centred on i_L."""
+    import numpy as np
+    g = W["gamma_b"]
+    sb = beta(g) * dt / dz
+    cols = W["nz"] + W["steps"] * sb + 8
+    nk = W.get("nknots", 4)
+    kz = list(np.linspace(-2.0 * g * dz, g * dz * cols, nk))
+    rng = np.random.default_rng(W["seed"])
+    kn = list(W["n_lab"] * (1.0 + 0.1 * rng.uniform(-1.0, 1.0, nk)))
+    las = W["laser"]
+    doppler = 1.0 / (g * (1.0 + beta(g)))
+    L = las["L_lambda0"] * LAMBDA0
+    if las["place"] == "box_center":
+        iL = 0.5 * W["nz"]
+    else:
+        iL = W["nz"] - las["front_gap"] * L / doppler / dz
+    Lc = L / doppler / dz
+    i0 = int(max(0, np.floor(iL - 2.5 * Lc)))
+    i1 = int(min(W["nz"] - 1, np.ceil(iL - Lc)))
+    if i1 - i0 < 8:  # a box shorter than that: 9 rows centred on iL
+        i0, i1 = int(max(0, iL - 4)), int(min(W["nz"] - 1, iL + 4))
+    j0, j1 = W["nx"] // 2 - 4, W["nx"] // 2 + 4
+    n = W["steps"]
+    win = (n - W.get("loss_steps", max(1, n // 5)) + 1, n)
+    return dict(knots_z=kz, knots_n=kn, box=(i0, i1, j0, j1), window=win,
+                interval=W.get("interval", 10))
+
+
 def small(name, **over):
     """A smaller box with the physics of `name`; the pulse sits at the box centre."""
     w = dict(WORKLOADS[name])
@@ -65,6 +116,10 @@ WORKLOADS["boost130_2d_small"] = small("boost130_2d", nz=256, nx=64, ppc=4, step
 WORKLOADS["boost100_3d_small"] = small("boost100_3d", nz=48, nx=16, ny=16, steps=30)
 WORKLOADS["lab_2d_fp32"] = small("lab_2d", precision="fp32")
 SMOKE = small("boost13_2d", nz=96, nx=64, ppc=2, steps=20, precision="fp64")
+WORKLOADS["adjoint_2d_small"] = small("adjoint_2d", nz=128, nx=32, ppc=2, steps=60,
+                                      interval=10, nknots=5, loss_steps=20)
+WORKLOADS["adjoint_2d_tiny"] = small("adjoint_2d", nz=64, nx=16, ppc=2, steps=40,
+                                     interval=10, nknots=4, loss_steps=10)
 
 
 def _resolve(W, beta, boosted_dz, yee_dt, group_beta):
