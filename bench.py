@@ -115,6 +115,33 @@ def run_gpu(name, precision, steps, warmup, sort_interval, with_kernel_times=Tru
             "diag_end": d1, "W": W}
 
 
+def run_adjoint(name="adjoint_2d", precision="fp32"):
+    """Taped forward and reverse sweep of the adjoint configuration, timed."""
+    import torch
+    import paper_1011_0917_amd as P
+    from workloads import WORKLOADS, adjoint_setup, resolve_gpu
+    W = WORKLOADS[name]
+    cfg, init, nst = resolve_gpu(W, precision=precision, sort_interval=0)
+    dt = P.yee_dt(2, cfg.dz, cfg.dx, 1.0, cfg.cfl)
+    a = adjoint_setup(W, cfg.dz, P.beta, dt)
+    sim = P.Simulation(cfg, capacity=init["capacity"])
+    sim.init_boosted_plasma(init["gamma_b"], knots_z=a["knots_z"], knots_n=a["knots_n"],
+                            laser=init["laser"])
+    n0 = sim.num_slots()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    loss = sim.forward_loss(nst, a["interval"], a["window"][0], a["window"][1], a["box"])
+    t1 = time.perf_counter()
+    da0, dn = sim.adjoint(len(a["knots_n"]))
+    t2 = time.perf_counter()
+    sim.close()
+    return {"workload": name, "precision": precision, "steps": nst,
+            "checkpoint_interval": a["interval"], "particles": n0, "loss": loss,
+            "dL_da0": da0, "forward_ms_per_step": (t1 - t0) * 1e3 / nst,
+            "adjoint_ms_per_step": (t2 - t1) * 1e3 / nst,
+            "adjoint_particle_steps_per_s": n0 * nst / (t2 - t1)}
+
+
 def cpu_baseline(name, nz_sample=256, steps=20):
     """The FP64 oracle, single-threaded, on a slab of the same workload."""
     import oracle as O
@@ -142,6 +169,8 @@ def main():
     ap.add_argument("--sort-interval", type=int, default=50)
     ap.add_argument("--no-fp64", action="store_true")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-adjoint", action="store_true",
+                    help="skip timing the adjoint configuration's reverse sweep")
     ap.add_argument("--no-deterministic", action="store_true",
                     help="skip timing the deterministic (fixed-point current) FP32 form")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
@@ -202,6 +231,9 @@ def main():
         out["deterministic"] = {
             "value": rd["particles"] * rd["steps"] / (rd["ms"] * 1e-3),
             "unit": "particle-steps/s", "ms_per_step": rd["ms"] / rd["steps"]}
+    if not args.no_adjoint:
+        log("bench: adjoint_2d taped forward + reverse sweep (fp32)")
+        out["adjoint"] = run_adjoint()
     if not args.no_cpu_baseline:
         log("bench: oracle cpu baseline")
         out["cpu_baseline"] = cpu_baseline(args.workload)
