@@ -710,6 +710,49 @@ struct Impl {
     }
   }
 
+  // 3D fold + filter as separable z, x, y sweeps; the window-shift buffers
+  // (not state during a step) hold the intermediate grids.
+  template <int NP, bool DET>
+  static void filt3(bfpic_ctx* h, const FoldK<R>& K, const FiltK& fk, const Fields<R>& Jf) {
+    constexpr int SZ = 16, SX = 16, FY = 64 - 2 * NP;
+    const Geo& g = h->g;
+    Fields<R> T1, T2;
+    for (int c = 0; c < 3; c++) {
+      T1.F[c] = (R*)h->Fs[c];
+      T2.F[c] = (R*)h->Fs[3 + c];
+      T1.F[3 + c] = T2.F[3 + c] = nullptr;
+    }
+    const int nsz = (int)cdiv(h->nz + 1, SZ);
+    k_filt3_z<R, NP, SZ, kT3, kT3, kT3, DET>
+        <<<dim3((unsigned)cdiv((int64_t)nsz * g.plane, 256), 1, 3), 256, 0, h->stream>>>(
+            g, K, fk, T1, nsz);
+    const int nsx = (int)cdiv(h->nx, SX);
+    k_filt3_x<R, NP, SX>
+        <<<dim3((unsigned)cdiv((int64_t)(h->nz + 1) * nsx * h->ny, 256), 1, 3), 256, 0,
+           h->stream>>>(g, fk, T1, T2, nsx);
+    const int nsy = (int)cdiv(h->ny, FY);
+    k_filt3_y<R, NP><<<dim3((unsigned)cdiv((int64_t)(h->nz + 1) * h->nx * nsy, 4), 1, 3), 256, 0,
+                       h->stream>>>(g, fk, T2, Jf, nsy);
+  }
+  template <bool DET>
+  static bool fold_filter3(bfpic_ctx* h, const FoldK<R>& K, const FiltK& fk,
+                           const Fields<R>& Jf) {
+    if constexpr (DIM != 3) {
+      return false;
+    } else {
+      switch (fk.H) {
+        case 0: filt3<0, DET>(h, K, fk, Jf); return true;
+        case 1: filt3<1, DET>(h, K, fk, Jf); return true;
+        case 2: filt3<2, DET>(h, K, fk, Jf); return true;
+        case 3: filt3<3, DET>(h, K, fk, Jf); return true;
+        case 4: filt3<4, DET>(h, K, fk, Jf); return true;
+        case 5: filt3<5, DET>(h, K, fk, Jf); return true;
+        case 6: filt3<6, DET>(h, K, fk, Jf); return true;
+        default: return false;
+      }
+    }
+  }
+
   template <bool DET>
   static const void* tiled_kernel() {
     if constexpr (DIM == 2)
@@ -793,6 +836,7 @@ struct Impl {
         size_t lds = 2 * sizeof(R) * (kF2Z + 2 * fk.H) * (kF2X + 2 * fk.H);
         k_fold_filter<R, 2, kF2Z, kF2X, 1, kT2Z, kT2X, 1, DET>
             <<<nbz * nbx, 256, lds, h->stream>>>(g, K, fk, Jf, nbz, nbx, 1);
+      } else if (DIM == 3 && fold_filter3<DET>(h, K, fk, Jf)) {
       } else {
         int nbz = (int)cdiv(h->nz + 1, kF3), nbx = (int)cdiv(h->nx, kF3),
             nby = (int)cdiv(h->ny, kF3);

@@ -329,6 +329,128 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(1, 4))) voi
   }
 }
 
+// 3D fold + filter as three separable sweeps over plain grids, one per axis,
+// each applying all of that axis's passes to a register window: z (also folds
+// the tile regions and the overflow grid), then x, then y (lane shuffles).
+// Lanes run along y, the contiguous axis.  Each sweep reads its input about
+// once (window halos) and writes its output once.
+template <typename R>
+__device__ __forceinline__ R filt_pass_w(const FiltK& fk, int p) {
+  return p < fk.passes ? (R)0.25 : (R)fk.a_c;
+}
+template <typename R>
+__device__ __forceinline__ R filt_pass_c(const FiltK& fk, int p) {
+  return p < fk.passes ? (R)0.5 : (R)fk.b_c;
+}
+
+// z sweep: thread = one (j, k) column and one window of SZ output rows.
+template <typename R, int NP, int SZ, int TZ, int TX, int TY, bool DET>
+__global__ __launch_bounds__(256) void k_filt3_z(Geo g, FoldK<R> K, FiltK fk, Fields<R> out,
+                                                 int nseg) {
+  constexpr int H = NP, L = SZ + 2 * H;
+  const int comp = blockIdx.z;
+  const int hz = half_z_j(comp);
+  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= (int64_t)nseg * g.plane) return;
+  const int seg = (int)(t / g.plane);
+  const int q = (int)(t - (int64_t)seg * g.plane);
+  const int j = q / g.ny, k = q - j * g.ny;
+  const int i0 = seg * SZ;
+  R v[L];
+#pragma unroll
+  for (int r = 0; r < L; r++) {
+    const int i = i0 - H + r;
+    v[r] = (g.periodic_z || in_domain(g, hz, i)) ? fold_at<R, 3, TZ, TX, TY, DET>(K, g, comp, i, j, k)
+                                                 : (R)0;
+  }
+#pragma unroll
+  for (int p = 0; p < NP; p++) {
+    const R a = filt_pass_w<R>(fk, p), b = filt_pass_c<R>(fk, p);
+    R prev = v[0];
+#pragma unroll
+    for (int r = 1; r < L - 1; r++) {
+      const R cur = v[r];
+      v[r] = a * prev + b * cur + a * v[r + 1];
+      prev = cur;
+    }
+    if (!g.periodic_z) {
+#pragma unroll
+      for (int r = 0; r < L; r++)
+        if (!in_domain(g, hz, i0 - H + r)) v[r] = (R)0;
+    }
+  }
+  R* o = out.F[comp];
+#pragma unroll
+  for (int r = H; r < H + SZ; r++) {
+    const int i = i0 + r - H;
+    if (in_domain(g, hz, i)) o[(int64_t)(i + kGuard) * g.plane + q] = v[r];
+  }
+}
+
+// x sweep (periodic): thread = one (i, k) line and one window of SX outputs.
+template <typename R, int NP, int SX>
+__global__ __launch_bounds__(256) void k_filt3_x(Geo g, FiltK fk, Fields<R> in, Fields<R> out,
+                                                 int nseg) {
+  constexpr int H = NP, L = SX + 2 * H;
+  const int comp = blockIdx.z;
+  const int hz = half_z_j(comp);
+  const int nrow = row_hi(g, hz) + 1;
+  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= (int64_t)nrow * nseg * g.ny) return;
+  const int k = (int)(t % g.ny);
+  const int64_t rest = t / g.ny;
+  const int seg = (int)(rest % nseg), i = (int)(rest / nseg);
+  const int j0 = seg * SX;
+  const R* a_in = in.F[comp] + (int64_t)(i + kGuard) * g.plane + k;
+  R v[L];
+#pragma unroll
+  for (int r = 0; r < L; r++) v[r] = a_in[(int64_t)wrap_small(j0 - H + r, g.nx) * g.ny];
+#pragma unroll
+  for (int p = 0; p < NP; p++) {
+    const R a = filt_pass_w<R>(fk, p), b = filt_pass_c<R>(fk, p);
+    R prev = v[0];
+#pragma unroll
+    for (int r = 1; r < L - 1; r++) {
+      const R cur = v[r];
+      v[r] = a * prev + b * cur + a * v[r + 1];
+      prev = cur;
+    }
+  }
+  R* o = out.F[comp] + (int64_t)(i + kGuard) * g.plane + k;
+#pragma unroll
+  for (int r = H; r < H + SX; r++) {
+    const int j = j0 + r - H;
+    if (j < g.nx) o[(int64_t)j * g.ny] = v[r];
+  }
+}
+
+// y sweep (periodic): one wave per (i, j) line and window of 64 - 2 NP outputs.
+template <typename R, int NP>
+__global__ __launch_bounds__(256) void k_filt3_y(Geo g, FiltK fk, Fields<R> in, Fields<R> out,
+                                                 int nseg) {
+  constexpr int H = NP, FY = 64 - 2 * H;
+  const int comp = blockIdx.z;
+  const int hz = half_z_j(comp);
+  const int nrow = row_hi(g, hz) + 1;
+  const int lane = threadIdx.x & 63;
+  const int w = __builtin_amdgcn_readfirstlane((int)(blockIdx.x * (blockDim.x >> 6) +
+                                                     (threadIdx.x >> 6)));
+  if (w >= nrow * g.nx * nseg) return;  // the whole wave leaves together
+  const int seg = w % nseg, line = w / nseg;
+  const int i = line / g.nx, j = line - i * g.nx;
+  const int k = seg * FY - H + lane;
+  const int64_t base = ((int64_t)(i + kGuard) * g.nx + j) * g.ny;
+  R x = in.F[comp][base + wrap_small(k, g.ny)];
+  const int kl = lane == 0 ? 63 : lane - 1, kr = lane == 63 ? 0 : lane + 1;
+#pragma unroll
+  for (int p = 0; p < NP; p++) {
+    const R a = filt_pass_w<R>(fk, p), b = filt_pass_c<R>(fk, p);
+    const R l = __shfl(x, kl), r = __shfl(x, kr);
+    x = a * l + b * x + a * r;
+  }
+  if (lane >= H && lane < 64 - H && k < g.ny) out.F[comp][base + k] = x;
+}
+
 // Clear the overflow rows that the global path touched this step.
 template <typename R, bool DET>
 __global__ __launch_bounds__(256) void k_ovf_clear(Geo g, Ovf<R> o) {
