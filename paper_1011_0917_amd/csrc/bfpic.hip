@@ -90,6 +90,7 @@ struct bfpic_ctx {
   int LZ = 1, LX = 1, LY = 1, LV = 1;
   int64_t maxtiles = 0, maxkeys = 0;
   size_t lds_tiled = 0, lds_limit = 65536;
+  bool stage = true;  // tiled kernel stages E, B in LDS (else gathers from global)
   // deterministic mode: currents summed as int64 in units of 1 / fx_scale
   bool det = false;
   double fx_scale = 1.0, fx_inv = 1.0;
@@ -261,9 +262,11 @@ static void derive(bfpic_ctx* h, const bfpic_config* c) {
     else set_region<TileGeom<3, 2, kT3, kT3, kT3, kExc>>(h);
   }
   h->LV = h->LZ * h->LX * h->LY;
-  bool fit_x = h->nx % h->TX == 0 && h->LX <= h->nx && h->LX <= 2 * h->TX;
-  bool fit_y = h->dim == 2 || (h->ny % h->TY == 0 && h->LY <= h->ny && h->LY <= 2 * h->TY);
-  bool fit_z = !g.periodic_z || (h->nz % h->TZ == 0 && h->LZ <= h->nz && h->LZ <= 2 * h->TZ);
+  // the fold gathers a node from at most three tile regions per axis
+  bool fit_x = h->nx % h->TX == 0 && h->LX <= h->nx && h->LX <= 3 * h->TX;
+  bool fit_y = h->dim == 2 || (h->ny % h->TY == 0 && h->LY <= h->ny && h->LY <= 3 * h->TY);
+  bool fit_z = h->LZ <= 3 * h->TZ &&
+               (!g.periodic_z || (h->nz % h->TZ == 0 && h->LZ <= h->nz));
   h->tiled = fit_x && fit_y && fit_z;
   // key tile shape when the LDS path is off: whole transverse planes
   if (!fit_x) h->TX = h->nx;
@@ -696,7 +699,8 @@ struct Impl {
     if constexpr (DIM != 2) {
       return false;
     } else {
-      if (!h->tiled) return false;
+      // the column kernel takes at most two tile regions per axis
+      if (!h->tiled || h->LX > 2 * h->TX || h->LZ > 2 * h->TZ) return false;
       switch (fk.H) {
         case 0: cols<0, DET>(h, K, fk, Jf); return true;
         case 1: cols<1, DET>(h, K, fk, Jf); return true;
@@ -754,11 +758,14 @@ struct Impl {
   }
 
   template <bool DET>
-  static const void* tiled_kernel() {
+  static const void* tiled_kernel(bool stage) {
     if constexpr (DIM == 2)
       return (const void*)k_gpd_tiled<R, 2, ORDER, kT2Z, kT2X, 1, kExc, kGpdThreads<R>, DET>;
-    else
+    else if (stage)
       return (const void*)k_gpd_tiled<R, 3, ORDER, kT3, kT3, kT3, kExc, kGpdThreads<R>, DET>;
+    else
+      return (const void*)k_gpd_tiled<R, 3, ORDER, kT3, kT3, kT3, kExc, kGpdThreads<R>, DET,
+                                      false>;
   }
 
   // Per-configuration kernel set-up at create: opt in to large dynamic LDS.
@@ -775,7 +782,7 @@ struct Impl {
       (void)hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, lim);
     }
     if (h->tiled && h->lds_tiled > 65536) {
-      const void* fn = h->det ? tiled_kernel<true>() : tiled_kernel<false>();
+      const void* fn = h->det ? tiled_kernel<true>(h->stage) : tiled_kernel<false>(h->stage);
       if (hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize,
                               (int)h->lds_tiled) != hipSuccess)
         h->tiled = false;
@@ -804,8 +811,11 @@ struct Impl {
       if constexpr (DIM == 2)
         k_gpd_tiled<R, 2, ORDER, kT2Z, kT2X, 1, kExc, kGpdThreads<R>, DET>
             <<<T.ntiles, kGpdThreads<R>, h->lds_tiled, h->stream>>>(P, F, S, T, h->scratch);
-      else
+      else if (h->stage)
         k_gpd_tiled<R, 3, ORDER, kT3, kT3, kT3, kExc, kGpdThreads<R>, DET>
+            <<<T.ntiles, kGpdThreads<R>, h->lds_tiled, h->stream>>>(P, F, S, T, h->scratch);
+      else
+        k_gpd_tiled<R, 3, ORDER, kT3, kT3, kT3, kExc, kGpdThreads<R>, DET, false>
             <<<T.ntiles, kGpdThreads<R>, h->lds_tiled, h->stream>>>(P, F, S, T, h->scratch);
       HIPCHK(h, hipGetLastError());
     }
@@ -1499,6 +1509,12 @@ extern "C" int bfpic_create(const bfpic_config* cfg, int64_t cap, void* workspac
   if (hipGetDevice(&dev) == hipSuccess &&
       hipDeviceGetAttribute(&lds, hipDeviceAttributeMaxSharedMemoryPerBlock, dev) == hipSuccess)
     h->lds_limit = (size_t)lds;
+  if (h->lds_tiled > h->lds_limit && h->dim == 3) {
+    // 3D tiles whose staged fields do not fit: gather from global memory and
+    // keep only the FP64 (or int64) currents in LDS
+    h->stage = false;
+    h->lds_tiled = (size_t)3 * h->LV * 8;
+  }
   if (h->lds_tiled > h->lds_limit) h->tiled = false;
   // the filter kernels may need more than 64 KB of LDS (3D, FP64, many passes)
   {

@@ -29,9 +29,9 @@ struct FoldK {
 };
 
 // Candidate tiles of a node along one axis: the regions are spaced T apart
-// and are L <= 2 T long, so node offset q (from the region origin of tile 0)
-// lies in tile h = q / T at local q - h T, and also in tile h - 1 at local
-// q - h T + T when that is below L.
+// and are L <= 3 T long, so node offset q (from the region origin of tile 0)
+// lies in tile h = q / T at local q - h T, and in tiles h - 1, h - 2 at local
+// q - h T + T, + 2 T when that is below L.
 template <typename R, int DIM, int TZ, int TX, int TY, bool DET>
 __device__ __forceinline__ R fold_at(const FoldK<R>& K, const Geo& g, int comp, int i, int j,
                                      int k) {
@@ -48,17 +48,17 @@ __device__ __forceinline__ R fold_at(const FoldK<R>& K, const Geo& g, int comp, 
     const int hx = qx / TX, hy = DIM == 3 ? qy / TY : 0;
     const int lz = qz - hz * TZ, lx = qx - hx * TX, ly = qy - hy * TY;
 #pragma unroll
-    for (int a = 0; a < 2; a++) {
+    for (int a = 0; a < 3; a++) {
       int tz = hz - a, rz = lz + a * TZ;
       if (g.periodic_z && tz < 0) tz += K.ntz;
       if (tz < 0 || tz >= K.ntz || rz >= K.LZ) continue;
 #pragma unroll
-      for (int b = 0; b < 2; b++) {
+      for (int b = 0; b < 3; b++) {
         int tx = hx - b, rx = lx + b * TX;
         if (tx < 0) tx += K.ntx;
         if (rx >= K.LX) continue;
 #pragma unroll
-        for (int c = 0; c < (DIM == 3 ? 2 : 1); c++) {
+        for (int c = 0; c < (DIM == 3 ? 3 : 1); c++) {
           int ty = hy - c, ry = ly + c * TY;
           if (ty < 0) ty += K.nty;
           if (DIM == 3 && ry >= K.LY) continue;

@@ -74,6 +74,18 @@ struct LdsFetch {
   }
 };
 
+// Global fetch addressed in a tile's region coordinates (region origin g0).
+template <typename R>
+struct RegionFetch {
+  const R* const* F;
+  Geo g;
+  int gz0, gx0, gy0;
+  __device__ __forceinline__ R operator()(int comp, int i, int j, int k) const {
+    int64_t n = gidx(g, i + gz0, j + gx0, k + gy0);
+    return n < 0 ? (R)0 : F[comp][n];
+  }
+};
+
 template <typename R>
 struct GlobalFetch {
   const R* const* F;
@@ -116,12 +128,13 @@ struct LdsSinkFx {
   }
 };
 
-// Accumulator type of the tiled kernel's LDS currents (2D: FP64; 3D keeps
-// the working precision so that the staged fields and currents fit in LDS;
-// deterministic mode: int64 fixed point).
-template <typename R, int DIM, bool DET>
+// Accumulator type of the tiled kernel's LDS currents: FP64, except 3D with
+// staged fields, which keeps the working precision so that fields and
+// currents fit in LDS; deterministic mode: int64 fixed point.
+template <typename R, int DIM, bool DET, bool STAGE = true>
 using LdsAcc = typename std::conditional<
-    DET, long long, typename std::conditional<DIM == 2, double, R>::type>::type;
+    DET, long long,
+    typename std::conditional<DIM == 2 || !STAGE, double, R>::type>::type;
 
 template <typename A, int LX, int LY, bool DET>
 using LdsSinkT = typename std::conditional<DET, LdsSinkFx<LX, LY>, LdsSink<A, LX, LY>>::type;
@@ -653,15 +666,20 @@ struct TileGeom {
   static constexpr int LV = LZ * LX * LY;
 };
 
-template <typename R, int DIM, int ORDER, int TZ, int TX, int TY, int EXC, int NT, bool DET>
+// STAGE = false: the fields are gathered from global memory (L2-resident
+// tile neighbourhoods) and only the currents live in LDS -- for tiles whose
+// staged fields would not fit (3D quadratic shapes).
+template <typename R, int DIM, int ORDER, int TZ, int TX, int TY, int EXC, int NT, bool DET,
+          bool STAGE = true>
 __global__ __launch_bounds__(NT) void k_gpd_tiled(StepK<R> P, Fields<R> F, PSoA<R> S, TileK T,
                                                   void* scratch) {
   using TG = TileGeom<DIM, ORDER, TZ, TX, TY, EXC>;
   constexpr int LZ = TG::LZ, LX = TG::LX, LY = TG::LY, LV = TG::LV;
-  using A = LdsAcc<R, DIM, DET>;
+  using A = LdsAcc<R, DIM, DET, STAGE>;
   extern __shared__ __align__(16) unsigned char smem_raw[];
   R* sF = reinterpret_cast<R*>(smem_raw);
-  A* sJ = reinterpret_cast<A*>(sF + 6 * LV);  // 6 LV sizeof(R) is a multiple of 8
+  // 6 LV sizeof(R) is a multiple of 8
+  A* sJ = reinterpret_cast<A*>(STAGE ? (unsigned char*)(sF + 6 * LV) : smem_raw);
   const int t = xcd_remap(blockIdx.x, T.ntiles);
   const int ty = DIM == 3 ? t % T.nty : 0;
   const int tx = (t / T.nty) % T.ntx;
@@ -674,7 +692,8 @@ __global__ __launch_bounds__(NT) void k_gpd_tiled(StepK<R> P, Fields<R> F, PSoA<
   // lies outside the stored grid).  2D: one wave per (component, row), lanes
   // along x, every row of a wave issued before any is stored; the x wrap of a
   // lane and the row offsets are computed once.
-  if constexpr (DIM == 2) {
+  if constexpr (!STAGE) {
+  } else if constexpr (DIM == 2) {
     static_assert(LX <= 64, "one wave spans a staged row");
     constexpr int NW = NT / 64, NPAIR = 6 * LZ, PERW = (NPAIR + NW - 1) / NW;
     const int lane = threadIdx.x & 63;
@@ -733,7 +752,9 @@ __global__ __launch_bounds__(NT) void k_gpd_tiled(StepK<R> P, Fields<R> F, PSoA<
   }
   for (int v = threadIdx.x; v < 3 * LV; v += NT) sJ[v] = (A)0;
   __syncthreads();
-  LdsFetch<R, LX, LY> lf{sF, LV};
+  typename std::conditional<STAGE, LdsFetch<R, LX, LY>, RegionFetch<R>>::type lf;
+  if constexpr (STAGE) lf = LdsFetch<R, LX, LY>{sF, LV};
+  else lf = RegionFetch<R>{(const R* const*)F.F, g, gz0, gx0, gy0};
   LdsSinkT<A, LX, LY, DET> ls{sJ, LV};
   const int p0 = T.start[t], p1 = T.start[t + 1];
   // the whole state of the next particle is loaded while this one is pushed

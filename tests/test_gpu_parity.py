@@ -121,17 +121,19 @@ def test_boosted_2d_fp32_split_within_tolerance(P, name):
     assert abs(dg["live"] - do["live"]) <= 1e-3 * do["live"]
 
 
-def test_boosted_3d_fp64_matches_oracle(P):
-    W = WORKLOADS["boost100_3d_small"]
-    print("case boost100_3d_small fp64", flush=True)
+@pytest.mark.parametrize("name", ["boost100_3d_small", "boost100_3d_tiled"])
+def test_boosted_3d_fp64_matches_oracle(P, name):
+    W = WORKLOADS[name]
+    print("case", name, "fp64", flush=True)
     dg, fg = run_gpu(P, W, precision="fp64")
     do, fo = run_oracle(W)
     check_fp64(dg, fg, do, fo)
 
 
-def test_boosted_3d_fp32_split_within_tolerance(P):
-    W = WORKLOADS["boost100_3d_small"]
-    print("case boost100_3d_small fp32", flush=True)
+@pytest.mark.parametrize("name", ["boost100_3d_small", "boost100_3d_tiled"])
+def test_boosted_3d_fp32_split_within_tolerance(P, name):
+    W = WORKLOADS[name]
+    print("case", name, "fp32", flush=True)
     dg, _ = run_gpu(P, W, precision="fp32", fields=False)
     do, _ = run_oracle(W)
     assert rel(dg["ue"] + dg["ub"], do["ue"] + do["ub"]) < 1e-3

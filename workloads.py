@@ -114,6 +114,9 @@ def small(name, **over):
 WORKLOADS["boost13_2d_small"] = small("boost13_2d", nz=256, nx=64, ppc=4, steps=100)
 WORKLOADS["boost130_2d_small"] = small("boost130_2d", nz=256, nx=64, ppc=4, steps=100)
 WORKLOADS["boost100_3d_small"] = small("boost100_3d", nz=48, nx=16, ny=16, steps=30)
+# wide enough in x and y (24 >= the 17-node region of a quadratic 8^3 tile) to
+# run the tiled 3D path
+WORKLOADS["boost100_3d_tiled"] = small("boost100_3d", nz=48, nx=24, ny=24, steps=20)
 WORKLOADS["lab_2d_fp32"] = small("lab_2d", precision="fp32")
 SMOKE = small("boost13_2d", nz=96, nx=64, ppc=2, steps=20, precision="fp64")
 WORKLOADS["adjoint_2d_small"] = small("adjoint_2d", nz=128, nx=32, ppc=2, steps=60,
