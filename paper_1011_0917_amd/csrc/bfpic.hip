@@ -63,6 +63,16 @@ constexpr int kF2Z = 16, kF2X = 64;  // filter output tiles
 #endif
 template <typename R>
 constexpr int kGpdThreads = sizeof(R) == 4 ? BFPIC_GPD_THREADS32 : BFPIC_GPD_THREADS64;
+// 3D tiles that gather from global memory (one workgroup per CU by LDS)
+#ifndef BFPIC_GPD3_THREADS
+#define BFPIC_GPD3_THREADS 512
+#endif
+constexpr int kGpd3Threads = BFPIC_GPD3_THREADS;
+// Rows per band of the fused 2D Yee kernel (one wave marches one band)
+#ifndef BFPIC_YEE_ROWS
+#define BFPIC_YEE_ROWS 16
+#endif
+constexpr int kYeeRows = BFPIC_YEE_ROWS;
 constexpr int kF3 = 8;
 constexpr int kNumTimers = 7;
 
@@ -764,7 +774,7 @@ struct Impl {
     else if (stage)
       return (const void*)k_gpd_tiled<R, 3, ORDER, kT3, kT3, kT3, kExc, kGpdThreads<R>, DET>;
     else
-      return (const void*)k_gpd_tiled<R, 3, ORDER, kT3, kT3, kT3, kExc, kGpdThreads<R>, DET,
+      return (const void*)k_gpd_tiled<R, 3, ORDER, kT3, kT3, kT3, kExc, kGpd3Threads, DET,
                                       false>;
   }
 
@@ -815,8 +825,8 @@ struct Impl {
         k_gpd_tiled<R, 3, ORDER, kT3, kT3, kT3, kExc, kGpdThreads<R>, DET>
             <<<T.ntiles, kGpdThreads<R>, h->lds_tiled, h->stream>>>(P, F, S, T, h->scratch);
       else
-        k_gpd_tiled<R, 3, ORDER, kT3, kT3, kT3, kExc, kGpdThreads<R>, DET, false>
-            <<<T.ntiles, kGpdThreads<R>, h->lds_tiled, h->stream>>>(P, F, S, T, h->scratch);
+        k_gpd_tiled<R, 3, ORDER, kT3, kT3, kT3, kExc, kGpd3Threads, DET, false>
+            <<<T.ntiles, kGpd3Threads, h->lds_tiled, h->stream>>>(P, F, S, T, h->scratch);
       HIPCHK(h, hipGetLastError());
     }
     {
@@ -864,6 +874,31 @@ struct Impl {
   // Yee update with Mur at open z ends: B half step, E step, B half step.
   static int yee(bfpic_ctx* h) {
     const Geo& g = h->g;
+    if constexpr (DIM == 2) {
+      // one fused kernel, E and B double-buffered (F -> Fs, then swapped)
+      Timer t(h, 3);
+      YeeF<R> Y;
+      for (int c = 0; c < 3; c++) {
+        Y.E[c] = (const R*)h->F[c];
+        Y.B[c] = (const R*)h->F[3 + c];
+        Y.J[c] = (const R*)h->Jf[c];
+        Y.Eo[c] = (R*)h->Fs[c];
+        Y.Bo[c] = (R*)h->Fs[3 + c];
+      }
+      Y.idz = (R)(1.0 / h->dz);
+      Y.idx = (R)(1.0 / h->dx);
+      Y.h1 = (R)(0.5 * h->dt);
+      Y.h = (R)h->dt;
+      Y.mur = (R)((h->dt - h->dz) / (h->dt + h->dz));
+      const int nrow = g.periodic_z ? h->nz : h->nz + 1;
+      const int tz = kYeeRows;
+      const int nband = std::max(1, nrow / tz), nwx = (int)cdiv(h->nx, kYeeCols);
+      const int64_t waves = (int64_t)nband * nwx;
+      k_yee2d<R><<<(unsigned)cdiv(waves, 4), 256, 0, h->stream>>>(g, Y, nwx, tz, nband);
+      HIPCHK(h, hipGetLastError());
+      for (int c = 0; c < 6; c++) std::swap(h->F[c], h->Fs[c]);
+      return BFPIC_OK;
+    }
     {
       Timer t(h, 3);
       YeeK<R> Y;
@@ -1265,7 +1300,10 @@ struct Impl {
     h->have_sort = false;
     const int64_t rs = h->fp64 ? 8 : 4;
     const int64_t grid = g.rows * g.plane;
-    for (int c = 0; c < 6; c++) HIPCHK(h, hipMemsetAsync(h->F[c], 0, grid * rs, h->stream));
+    for (int c = 0; c < 6; c++) {
+      HIPCHK(h, hipMemsetAsync(h->F[c], 0, grid * rs, h->stream));
+      HIPCHK(h, hipMemsetAsync(h->Fs[c], 0, grid * rs, h->stream));
+    }
     for (int c = 0; c < 3; c++) {
       HIPCHK(h, hipMemsetAsync(h->Jf[c], 0, grid * rs, h->stream));
       HIPCHK(h, hipMemsetAsync(h->Jo[c], 0, grid * (int64_t)ovf_bytes(h), h->stream));

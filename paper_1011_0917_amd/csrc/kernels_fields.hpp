@@ -551,6 +551,127 @@ __global__ __launch_bounds__(256) void k_yee_e(Geo g, YeeK<R> Y) {
                       (Bz[n] - at(g, Bz, i, j - 1, k)) * Y.idx - Y.J[1][n]);
 }
 
+// 2D Yee step fused into one kernel: B half step, E step with the filtered
+// current, Mur at open z ends, B half step -- the same updates as k_yee_b,
+// k_yee_e, k_mur, k_yee_b, node by node.  Each lane owns one x column and a
+// wave marches along z through a band of rows, keeping the few rows each
+// update needs in registers; x neighbours come from the adjacent lanes.  The
+// dependency cone of one output node spans one column to the left and two
+// to the right, so a wave holds 64 consecutive columns and writes the 61
+// inner ones.  The kernel reads E, B from one set of arrays and writes the
+// other (neighbouring bands read its halo rows), so the caller swaps the two
+// sets afterwards.
+template <typename R>
+struct YeeF {
+  const R* E[3];
+  const R* B[3];
+  const R* J[3];
+  R* Eo[3];
+  R* Bo[3];
+  R idz, idx;
+  R h1, h;   // dt / 2 and dt
+  R mur;
+};
+
+constexpr int kYeeCols = 61;  // output columns per wave
+
+template <typename R>
+__device__ __forceinline__ R lane_next(R v) { return __shfl_down(v, 1, 64); }
+template <typename R>
+__device__ __forceinline__ R lane_prev(R v) { return __shfl_up(v, 1, 64); }
+
+// Waves are numbered band-major (band = wave / nwx); band b covers rows
+// [b tz, (b + 1) tz), the last band also the remainder.
+template <typename R>
+__global__ __launch_bounds__(256) void k_yee2d(Geo g, YeeF<R> Y, int nwx, int tz,
+                                                int nband) {
+  const int lane = threadIdx.x & 63;
+  const int wid = blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6);
+  const int band = wid / nwx, w = wid - band * nwx;
+  if (band >= nband) return;  // whole wave
+  const bool open = !g.periodic_z;
+  const int nrow = open ? g.nz + 1 : g.nz;
+  const int rh1 = row_hi(g, 1);
+  const int i0 = band * tz, i1 = band == nband - 1 ? nrow : i0 + tz;
+  const int cu = w * kYeeCols + lane - 1;  // unwrapped column of this lane
+  const int j = wrapi(cu, g.nx);
+  const bool out = lane >= 1 && lane <= kYeeCols && cu < g.nx;
+  // every row touched lies in [i0 - 2, i1 + 2] within storage (open z) or
+  // wraps (periodic z)
+  auto at = [&](int i) -> int64_t {
+    const int r = open ? i : wrapi(i, g.nz);
+    return (int64_t)(r + kGuard) * g.nx + j;
+  };
+  const R idz = Y.idz, idx = Y.idx, h1 = Y.h1, h = Y.h, m = Y.mur;
+  auto in_b = [&](int i) { return !open || (i >= 0 && i <= rh1); };    // Bx, By, Ez
+  auto in_z = [&](int i) { return !open || (i >= 0 && i < nrow); };    // Bz
+  auto in_e = [&](int i) { return !open || (i >= 1 && i <= g.nz - 1); };  // Ex, Ey
+  struct V3 { R x, y, z; };
+  auto ld = [&](const R* const* A, int64_t n) { return V3{A[0][n], A[1][n], A[2][n]}; };
+  // B half step of row i from E rows i (with its right neighbours) and i + 1
+  auto bhalf = [&](V3 b, int i, V3 e, V3 e1) {
+    const R ezr = lane_next(e.z), eyr = lane_next(e.y);
+    if (in_b(i)) {
+      b.x += h1 * ((e1.y - e.y) * idz);
+      b.y += h1 * ((ezr - e.z) * idx - (e1.x - e.x) * idz);
+    }
+    if (in_z(i)) b.z += h1 * (-(eyr - e.y) * idx);
+    return b;
+  };
+  // E step of row i from B rows i (with its left neighbours) and i - 1
+  auto estep = [&](V3 e, int i, V3 b, V3 bm, V3 jc) {
+    const R byl = lane_prev(b.y), bzl = lane_prev(b.z);
+    if (in_b(i)) e.z += h * ((b.y - byl) * idx - jc.z);
+    if (in_e(i)) {
+      e.x += h * (-(b.y - bm.y) * idz - jc.x);
+      e.y += h * ((b.x - bm.x) * idz - (b.z - bzl) * idx - jc.y);
+    }
+    return e;
+  };
+  // prologue: B half on rows i0 - 2 and i0 - 1, E step on row i0 - 1
+  V3 eo_m = ld(Y.E, at(i0 - 2)), eo = ld(Y.E, at(i0 - 1)), eo_p = ld(Y.E, at(i0));
+  V3 bh_m = bhalf(ld(Y.B, at(i0 - 2)), i0 - 2, eo_m, eo);
+  V3 bh = bhalf(ld(Y.B, at(i0 - 1)), i0 - 1, eo, eo_p);
+  V3 en = estep(eo, i0 - 1, bh, bh_m, ld(Y.J, at(i0 - 1)));
+  // Mur rewrites row 0 at i = 1 and row nz at i = nz, inside the loop, from
+  // the previous row's old and new E (the prologue's for the first i)
+  V3 nb = ld(Y.B, at(i0)), nj = ld(Y.J, at(i0)), ne = ld(Y.E, at(i0 + 1));
+  for (int i = i0; i <= i1; i++) {
+    // row i: old E (eo_p), B, J; old E of row i + 1 (ne)
+    const V3 eo_c = eo_p, bi = nb, ji = nj, e1 = ne;
+    if (i < i1) {
+      nb = ld(Y.B, at(i + 1));
+      nj = ld(Y.J, at(i + 1));
+      ne = ld(Y.E, at(i + 2));
+    }
+    const V3 bh_c = bhalf(bi, i, eo_c, e1);
+    V3 en_c = estep(eo_c, i, bh_c, bh, ji);
+    if (open && i == 1) {  // Mur at z = 0 rewrites row 0 from row 1
+      en.x = eo_c.x + m * (en_c.x - eo.x);
+      en.y = eo_c.y + m * (en_c.y - eo.y);
+    }
+    if (open && i == g.nz) {  // Mur at z = nz rewrites row nz from row nz - 1
+      en_c.x = eo.x + m * (en.x - eo_c.x);
+      en_c.y = eo.y + m * (en.y - eo_c.y);
+    }
+    // B half step of row i - 1 with the new E, then store row i - 1
+    const V3 bf = bhalf(bh, i - 1, en, en_c);
+    if (i > i0 && out) {
+      const int64_t n = at(i - 1);
+      Y.Eo[0][n] = en.x;
+      Y.Eo[1][n] = en.y;
+      Y.Eo[2][n] = en.z;
+      Y.Bo[0][n] = bf.x;
+      Y.Bo[1][n] = bf.y;
+      Y.Bo[2][n] = bf.z;
+    }
+    eo = eo_c;
+    eo_p = e1;
+    bh = bh_c;
+    en = en_c;
+  }
+}
+
 // First-order Mur at normal incidence: E0' = E1 + m (E1' - E0) at both z ends.
 template <typename R>
 __global__ __launch_bounds__(256) void k_mur(Geo g, YeeK<R> Y) {
