@@ -132,14 +132,17 @@ uint64_t orc_splitmix64(uint64_t seed, uint64_t n) {
 }
 
 /* In-cell offset of slot s of lattice cell (k, l, j) along axis (0 z, 1 x,
- * 2 y): the top 24 bits of one generator output, times 2^-24, so that the
- * value is exact in FP32 and FP64. */
+ * 2 y): a 24-bit field of a generator output, times 2^-24, so that the value
+ * is exact in FP32 and FP64.  With id the slot's running index, output
+ * 2 id + 1 gives z (bits 63..40) and x (bits 39..16), output 2 id + 2 gives
+ * y (bits 63..40). */
 double orc_cell_offset(uint64_t seed, int64_t k, int64_t l, int64_t j, int32_t s,
                        int32_t axis, int32_t nx, int32_t nyy, int32_t ppc) {
-  uint64_t key = ((((uint64_t)k * (uint64_t)nyy + (uint64_t)l) * (uint64_t)nx +
-                   (uint64_t)j) * (uint64_t)ppc + (uint64_t)s) * 4ULL + (uint64_t)axis;
-  uint64_t r = orc_splitmix64(seed, key + 1ULL);
-  return (double)(r >> 40) * (1.0 / 16777216.0);
+  uint64_t id = (((uint64_t)k * (uint64_t)nyy + (uint64_t)l) * (uint64_t)nx +
+                 (uint64_t)j) * (uint64_t)ppc + (uint64_t)s;
+  uint64_t r = orc_splitmix64(seed, 2ULL * id + 1ULL + (axis == 2 ? 1ULL : 0ULL));
+  uint64_t field = axis == 1 ? (r >> 16) & 0xFFFFFFULL : r >> 40;
+  return (double)field * (1.0 / 16777216.0);
 }
 
 /* ------------------------------------------------------------------------ */

@@ -93,6 +93,12 @@ __device__ __forceinline__ Birth decode_id(const LatticeP& L, int id) {
   return b;
 }
 
+// One period of wrap, without branches: exact for x in [-n, 2n); callers that
+// test the result against a range inside [0, n) reject anything else.
+__device__ __forceinline__ int wrap_once(int x, int n) {
+  return x + (x < 0 ? n : 0) - (x >= n ? n : 0);
+}
+
 // Wrap into [0, n) for x in (-n, 2n); other values take the full modulo.
 __device__ __forceinline__ int wrap_small(int x, int n) {
   if (x < 0) x += n;
@@ -101,11 +107,29 @@ __device__ __forceinline__ int wrap_small(int x, int n) {
   return x;
 }
 
+// In-cell birth offsets: 24-bit fields of SplitMix64 outputs times 2^-24
+// (exact in FP32 and FP64).  Output 2 id + 1 gives z (bits 63..40) and x
+// (bits 39..16); output 2 id + 2 gives y (bits 63..40).
+__device__ __forceinline__ uint64_t birth_bits(const LatticeP& L, int id, int second) {
+  return splitmix64(L.seed, 2ULL * (uint64_t)id + 1ULL + (uint64_t)second);
+}
+
+// Fields are taken from 32-bit halves (a 64-bit integer costs more to convert).
+template <typename R>
+__device__ __forceinline__ R offset_hi(uint64_t r) {
+  return (R)((uint32_t)(r >> 32) >> 8) * (R)(1.0 / 16777216.0);
+}
+template <typename R>
+__device__ __forceinline__ R offset_mid(uint64_t r) {
+  return (R)(((uint32_t)r >> 16) | (((uint32_t)(r >> 32) & 0xFFu) << 16)) *
+         (R)(1.0 / 16777216.0);
+}
+
 template <typename R>
 __device__ __forceinline__ R birth_offset(const LatticeP& L, int id, int axis) {
   if (L.load) return (R)0.5;
-  uint64_t r = splitmix64(L.seed, 4ULL * (uint64_t)id + (uint64_t)axis + 1ULL);
-  return (R)(uint32_t)(r >> 40) * (R)(1.0 / 16777216.0);
+  const uint64_t r = birth_bits(L, id, axis == 2);
+  return axis == 1 ? offset_mid<R>(r) : offset_hi<R>(r);
 }
 
 // A particle position as an integer cell plus an offset in [0, 1).
@@ -156,9 +180,15 @@ __device__ __forceinline__ Pos<R> ion_at(const Birth& b, const R r[3], const Dri
 
 template <typename R, int DIM>
 __device__ __forceinline__ void birth_offsets(const LatticeP& L, int id, R r[3]) {
-  r[0] = birth_offset<R>(L, id, 0);
-  r[1] = birth_offset<R>(L, id, 1);
-  r[2] = DIM == 3 ? birth_offset<R>(L, id, 2) : (R)0;
+  if (L.load) {
+    r[0] = r[1] = (R)0.5;
+    r[2] = DIM == 3 ? (R)0.5 : (R)0;
+    return;
+  }
+  const uint64_t a = birth_bits(L, id, 0);
+  r[0] = offset_hi<R>(a);
+  r[1] = offset_mid<R>(a);
+  r[2] = DIM == 3 ? offset_hi<R>(birth_bits(L, id, 1)) : (R)0;
 }
 
 template <typename R, int DIM>
@@ -240,10 +270,14 @@ struct PushC {
 __device__ __forceinline__ float rcp(float x) { return __builtin_amdgcn_rcpf(x); }
 __device__ __forceinline__ double rcp(double x) { return 1.0 / x; }
 
+// Square root: the hardware instruction (1 ulp) in FP32, correctly rounded in FP64.
+__device__ __forceinline__ float root(float x) { return __builtin_amdgcn_sqrtf(x); }
+__device__ __forceinline__ double root(double x) { return sqrt(x); }
+
 template <typename R>
 __device__ __forceinline__ R gamma_minus_gb(const PushC<R>& P, R dux, R duy, R duz) {
   R c = (R)2 * P.ub * duz + (dux * dux + duy * duy + duz * duz);
-  return c * rcp(P.gb + sqrt(P.gb2 + c));
+  return c * rcp(P.gb + root(P.gb2 + c));
 }
 
 template <typename R>

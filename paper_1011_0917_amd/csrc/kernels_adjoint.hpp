@@ -70,6 +70,10 @@ struct Dual {
     const T s = sqrt(a.v);
     return mk(s, s > (T)0 ? a.d / (s + s) : (T)0);
   }
+  friend __device__ __forceinline__ Dual root(Dual a) {
+    const T s = root(a.v);
+    return mk(s, s > (T)0 ? a.d / (s + s) : (T)0);
+  }
   friend __device__ __forceinline__ Dual rcp(Dual a) {
     const T r = rcp(a.v);
     return mk(r, -a.d * r * r);

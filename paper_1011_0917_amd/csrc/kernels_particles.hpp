@@ -65,12 +65,21 @@ __device__ __forceinline__ long long to_fixed(double x) {
 // fetcher's own frame: LDS-relative for the tiled path, absolute (unwrapped)
 // grid indices for the global path.
 // --------------------------------------------------------------------------
+// Offset of node (i, j, k) in an LDS region of LX x LY columns.  Region
+// coordinates are small and non-negative, so the products use the full-rate
+// 24-bit multiply.
+template <int LX, int LY>
+__device__ __forceinline__ int lds_index(int i, int j, int k) {
+  const unsigned r = __umul24((unsigned)i, (unsigned)LX) + (unsigned)j;
+  return (int)(LY == 1 ? r : __umul24(r, (unsigned)LY) + (unsigned)k);
+}
+
 template <typename R, int LX, int LY>
 struct LdsFetch {
   const R* s;   // [6][LZ*LX*LY]
   int lv;
   __device__ __forceinline__ R operator()(int comp, int i, int j, int k) const {
-    return s[comp * lv + (i * LX + j) * LY + k];
+    return s[comp * lv + lds_index<LX, LY>(i, j, k)];
   }
 };
 
@@ -110,7 +119,7 @@ struct LdsSink {
     if constexpr (sizeof(A) == 4) {
       if (v == (R)0) return;
     }
-    atomicAdd(&s[comp * lv + (i * LX + j) * LY + k], (A)v);
+    atomicAdd(&s[comp * lv + lds_index<LX, LY>(i, j, k)], (A)v);
   }
 };
 
@@ -123,7 +132,7 @@ struct LdsSinkFx {
   int lv;
   template <typename R>
   __device__ __forceinline__ void add(int comp, int i, int j, int k, R v) const {
-    atomicAdd(reinterpret_cast<unsigned long long*>(&s[comp * lv + (i * LX + j) * LY + k]),
+    atomicAdd(reinterpret_cast<unsigned long long*>(&s[comp * lv + lds_index<LX, LY>(i, j, k)]),
               (unsigned long long)to_fixed((double)v));
   }
 };
@@ -782,16 +791,16 @@ __global__ __launch_bounds__(NT) void k_gpd_tiled(StepK<R> P, Fields<R> F, PSoA<
     // cells relative to the LDS region (wrapped where the axis is periodic)
     int rz = e0.c[0] - gz0, riz = i0.c[0] - gz0;
     if (g.periodic_z) {
-      rz = wrap_small(rz, g.nz);
-      riz = wrap_small(riz, g.nz);
+      rz = wrap_once(rz, g.nz);
+      riz = wrap_once(riz, g.nz);
     }
-    const int rx = wrap_small(e0.c[1] - gx0, g.nx), rix = wrap_small(i0.c[1] - gx0, g.nx);
+    const int rx = wrap_once(e0.c[1] - gx0, g.nx), rix = wrap_once(i0.c[1] - gx0, g.nx);
     bool inside = rz >= TG::HLO && rz < LZ - TG::HHI && riz >= TG::HLO && riz < LZ - TG::HHI &&
                   rx >= TG::HLO && rx < LX - TG::HHI && rix >= TG::HLO && rix < LX - TG::HHI;
     int ry = 0;
     if (DIM == 3) {
-      ry = wrap_small(e0.c[2] - gy0, g.ny);
-      const int riy = wrap_small(i0.c[2] - gy0, g.ny);
+      ry = wrap_once(e0.c[2] - gy0, g.ny);
+      const int riy = wrap_once(i0.c[2] - gy0, g.ny);
       inside = inside && ry >= TG::HLO && ry < LY - TG::HHI && riy >= TG::HLO &&
                riy < LY - TG::HHI;
     }

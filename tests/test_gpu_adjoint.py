@@ -15,9 +15,11 @@ the number of particle-steps (at h = 1e-6 and ~5e5 particle-steps, about one
 parameter in ten), and a straddled kink moves the quotient by ~1e-5 relative
 (seen at h = 1e-4 on adjoint_2d_small: -1.5e-5, gone at h = 1e-6).  Hence
 tolerances of 1e-4 against differences of step h = 1e-6, where FP64 round-off
-in the quotient is ~1e-10 for a0; the difference runs use the deterministic
-mode so that they carry no run-to-run summation noise.  The knot gradient is
-compared relative to its largest entry.
+in the quotient is ~1e-10 for a0.  The difference runs use the plain FP64
+mode: its run-to-run noise (the order of the atomic sums) is ~1e-16 of the
+loss, while the deterministic mode rounds every current contribution to 2^-40
+of the largest one, which puts ~1e-4 of noise into a quotient at h = 1e-6.
+The knot gradient is compared relative to its largest entry.
 """
 import numpy as np
 import pytest
@@ -65,9 +67,8 @@ def gpu_run(P, cfg, init, nst, a, a0, kn, grad=False, interval=None):
 
 def fd_gpu(P, cfg64, init, nst, a, which, h=H):
     """Central differences of the FP64 GPU loss for the parameters in `which`
-    (-1: a0, m >= 0: knot m).  The runs use the deterministic mode, so that the
-    two runs of a difference carry no run-to-run summation noise."""
-    cfg64.deterministic = 1
+    (-1: a0, m >= 0: knot m), in the plain FP64 mode (the least noisy one)."""
+    cfg64.deterministic = 0
     a0, kn = init["laser"].a0, np.array(a["knots_n"])
     out = {}
     for m in which:
@@ -82,7 +83,6 @@ def fd_gpu(P, cfg64, init, nst, a, which, h=H):
             lp = gpu_run(P, cfg64, init, nst, a, a0, kp)[0]
             lm = gpu_run(P, cfg64, init, nst, a, a0, km)[0]
             out[m] = (lp - lm) / (2 * h * kn[m])
-    cfg64.deterministic = 0
     return out
 
 
@@ -106,11 +106,13 @@ def as_dict(da0, dn):
 
 
 def test_adjoint_matches_differences_fp64(P):
+    """No kink is straddled on this case at h = 1e-6: the observed agreement is
+    ~1e-10 relative, so the tolerance is 1e-6."""
     print("case adjoint_2d_small fp64 vs differences", flush=True)
     W, cfg, init, nst, a = setup(P, "adjoint_2d_small", "fp64")
     L, da0, dn = gpu_run(P, cfg, init, nst, a, init["laser"].a0, a["knots_n"], grad=True)
     fd = fd_gpu(P, cfg, init, nst, a, [-1] + list(range(len(dn))))
-    compare(as_dict(da0, dn), fd, 1e-4)
+    compare(as_dict(da0, dn), fd, 1e-6)
 
 
 def test_adjoint_fp32_against_fp64_differences(P):
