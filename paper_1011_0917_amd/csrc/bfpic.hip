@@ -699,9 +699,12 @@ struct Impl {
     const int tz_lo = floor_div(-K.gz0, kT2Z), tz_hi = floor_div(h->nz - K.gz0, kT2Z);
     const int nseg = tz_hi - tz_lo + 1, nbx = (int)cdiv(h->nx, FX);
     const int64_t nw = (int64_t)nseg * nbx;
-    k_fold_filter_cols<R, NP, kT2Z, kT2X, TG::LZ, TG::LX, DET>
-        <<<(unsigned)cdiv(nw, 4), 256, 0, h->stream>>>(h->g, K, fk, Jf, tz_lo, nseg, nbx,
-                                                       h->ntz_max);
+    // FP64 windows run one component per wave (more waves in flight hide the
+    // loads); FP32 ones all three (measured faster)
+    constexpr int NC = sizeof(R) == 8 ? 1 : 3;
+    k_fold_filter_cols<R, NP, kT2Z, kT2X, TG::LZ, TG::LX, DET, NC>
+        <<<dim3((unsigned)cdiv(nw, 4), 3 / NC), 256, 0, h->stream>>>(h->g, K, fk, Jf, tz_lo,
+                                                                     nseg, nbx, h->ntz_max);
   }
   template <bool DET>
   static bool fold_filter_cols(bfpic_ctx* h, const FoldK<R>& K, const FiltK& fk,

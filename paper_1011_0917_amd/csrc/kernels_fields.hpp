@@ -186,10 +186,10 @@ __global__ __launch_bounds__(256) void k_fold_filter(Geo g, FoldK<R> K, FiltK fk
   }
 }
 
-// 2D fold + filter on register columns.  A wave owns a window of TZ output
-// rows (the z extent of one row of co-moving tiles, so that every row's
-// candidate tiles and local row are fixed at compile time) by 64 - 2 NP
-// output columns.  Lane c holds column j0 - NP + c over the TZ + 2 NP rows
+// 2D fold + filter on register columns.  A wave owns NC of the three current
+// components (1 or 3; blockIdx.y picks them) over a window of TZ output rows (the z extent of one row of
+// co-moving tiles, so that every row's candidate tiles and local row are
+// fixed at compile time) by 64 - 2 NP output columns.  Lane c holds column j0 - NP + c over the TZ + 2 NP rows
 // the filter needs; the z passes run in registers, the x passes exchange
 // neighbours across lanes.  After NP passes along an axis the values NP or
 // more nodes inside the window are exact; those are stored.  Tile rows
@@ -199,8 +199,11 @@ __global__ __launch_bounds__(256) void k_fold_filter(Geo g, FoldK<R> K, FiltK fk
 // The fold sums, per node, the tile whose core holds it, then the tile
 // before it in z, each with the two x candidates, then the overflow grid:
 // the order of fold_at.
-template <typename R, int NP, int TZ, int TX, int LZ, int LX, bool DET>
-__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(1, 4))) void k_fold_filter_cols(Geo g, FoldK<R> K, FiltK fk,
+// A wave that folds all three components gets the register budget of four
+// waves per SIMD, so that each window's loads are all in flight at once.
+template <typename R, int NP, int TZ, int TX, int LZ, int LX, bool DET, int NC>
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(1, NC == 3 ? 4 : 8))) void
+k_fold_filter_cols(Geo g, FoldK<R> K, FiltK fk,
                                                           Fields<R> Jf, int tz_lo, int nseg,
                                                           int nbx, int zero_row) {
   constexpr int H = NP, L = TZ + 2 * H;
@@ -244,7 +247,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(1, 4))) voi
   const int ilo = iw0 - H, ihi = iw0 - H + L - 1;  // rows of the window (unwrapped)
   const bool any_ovf = g.periodic_z ? r1 >= r0 : (ihi >= r0 && ilo <= r1);
 #pragma unroll 1
-  for (int comp = 0; comp < 3; comp++) {
+  for (int comp = blockIdx.y * NC; comp < (int)(blockIdx.y + 1) * NC; comp++) {
     const int hz = half_z_j(comp);
     const bool interior = g.periodic_z || (ilo >= 0 && ihi <= row_hi(g, hz));
     // per-lane pointers to row 0 of each candidate tile; rows are then

@@ -83,17 +83,45 @@ struct LdsFetch {
   }
 };
 
-// Global fetch addressed in a tile's region coordinates (region origin g0).
+// Global fetch addressed in a tile's region coordinates.  The origin
+// (gz0, gx0, gy0) lies within one period below the grid (periodic z: the
+// caller wraps it into [0, nz)), and a region spans at most one period, so a
+// single branchless wrap per axis suffices.  Besides the node-wise call, the
+// fetch exposes its axes (row offset, column offset, y offset) so that
+// gather_axes forms each once per particle; a row outside storage (open z)
+// maps to offset 0 and reports !ok, and its weight is then zeroed.
 template <typename R>
 struct RegionFetch {
   const R* const* F;
   Geo g;
   int gz0, gx0, gy0;
+  __device__ __forceinline__ int64_t row(int i, bool& ok) const {
+    int z = i + gz0;
+    if (g.periodic_z) {
+      z = wrap_once(z, g.nz);
+      ok = true;
+    } else {
+      ok = z >= -kGuard && z <= g.nz + kGuard;
+    }
+    return ok ? (int64_t)(z + kGuard) * g.plane : (int64_t)0;
+  }
+  __device__ __forceinline__ int col(int j) const { return wrap_once(j + gx0, g.nx) * g.ny; }
+  __device__ __forceinline__ int dep(int k) const {
+    return g.ny > 1 ? wrap_once(k + gy0, g.ny) : 0;
+  }
+  __device__ __forceinline__ const R* base(int comp, int64_t r) const { return F[comp] + r; }
   __device__ __forceinline__ R operator()(int comp, int i, int j, int k) const {
-    int64_t n = gidx(g, i + gz0, j + gx0, k + gy0);
-    return n < 0 ? (R)0 : F[comp][n];
+    bool ok;
+    const int64_t r = row(i, ok);
+    const R v = base(comp, r)[ok ? col(j) + dep(k) : 0];
+    return ok ? v : (R)0;
   }
 };
+
+template <class F>
+struct HasAxes : std::false_type {};
+template <typename R>
+struct HasAxes<RegionFetch<R>> : std::true_type {};
 
 template <typename R>
 struct GlobalFetch {
@@ -200,9 +228,75 @@ __device__ __forceinline__ R interp(const F& f, int comp, int bz, const R* wz, i
   return acc;
 }
 
+// Gather through a fetch that exposes its axes: per staggering set (integer,
+// half) and axis, the node offsets are formed once, then each component's
+// stencil reads base(comp, row)[col + dep].
 template <typename R, int DIM, int ORDER, class F>
-__device__ __forceinline__ void gather(const F& f, const int bc[3], const Pos<R>& p, R E[3],
-                                       R B[3]) {
+__device__ __forceinline__ R interp_axes(const F& f, int comp, const int64_t* zr, const R* wz,
+                                         const int* xc, const R* wx, const int* yc,
+                                         const R* wy) {
+  R acc = (R)0;
+#pragma unroll
+  for (int a = 0; a <= ORDER; a++) {
+    const R* rp = f.base(comp, zr[a]);
+    R rowz = (R)0;
+#pragma unroll
+    for (int b = 0; b <= ORDER; b++) {
+      if (DIM == 3) {
+        R cy = (R)0;
+#pragma unroll
+        for (int c = 0; c <= ORDER; c++) cy += rp[xc[b] + yc[c]] * wy[c];
+        rowz += cy * wx[b];
+      } else {
+        rowz += rp[xc[b]] * wx[b];
+      }
+    }
+    acc += rowz * wz[a];
+  }
+  return acc;
+}
+
+template <typename R, int DIM, int ORDER, class F>
+__device__ __forceinline__ void gather_axes(const F& f, const int bc[3], const Pos<R>& p, R E[3],
+                                            R B[3]) {
+  R wz[2][ORDER + 1], wx[2][ORDER + 1], wy[2][ORDER + 1];
+  int64_t zr[2][ORDER + 1];
+  int xc[2][ORDER + 1], yc[2][ORDER + 1];
+#pragma unroll
+  for (int h = 0; h < 2; h++) {
+    const int bz = shape<R, ORDER>(p.c[0], p.o[0], h, wz[h]) - p.c[0] + bc[0];
+    const int bx = shape<R, ORDER>(p.c[1], p.o[1], h, wx[h]) - p.c[1] + bc[1];
+#pragma unroll
+    for (int a = 0; a <= ORDER; a++) {
+      bool ok;
+      zr[h][a] = f.row(bz + a, ok);
+      wz[h][a] = ok ? wz[h][a] : (R)0;
+      xc[h][a] = f.col(bx + a);
+    }
+    if (DIM == 3) {
+      const int by = shape<R, ORDER>(p.c[2], p.o[2], h, wy[h]) - p.c[2] + bc[2];
+#pragma unroll
+      for (int c = 0; c <= ORDER; c++) yc[h][c] = f.dep(by + c);
+    } else {
+#pragma unroll
+      for (int c = 0; c <= ORDER; c++) {
+        wy[h][c] = (R)0;
+        yc[h][c] = 0;
+      }
+    }
+  }
+  // staggering (z, x, y): Ex (0,h,0) Ey (0,0,h) Ez (h,0,0) Bx (h,0,h) By (h,h,0) Bz (0,h,h)
+  E[0] = interp_axes<R, DIM, ORDER>(f, 0, zr[0], wz[0], xc[1], wx[1], yc[0], wy[0]);
+  E[1] = interp_axes<R, DIM, ORDER>(f, 1, zr[0], wz[0], xc[0], wx[0], yc[1], wy[1]);
+  E[2] = interp_axes<R, DIM, ORDER>(f, 2, zr[1], wz[1], xc[0], wx[0], yc[0], wy[0]);
+  B[0] = interp_axes<R, DIM, ORDER>(f, 3, zr[1], wz[1], xc[0], wx[0], yc[1], wy[1]);
+  B[1] = interp_axes<R, DIM, ORDER>(f, 4, zr[1], wz[1], xc[1], wx[1], yc[0], wy[0]);
+  B[2] = interp_axes<R, DIM, ORDER>(f, 5, zr[0], wz[0], xc[1], wx[1], yc[1], wy[1]);
+}
+
+template <typename R, int DIM, int ORDER, class F>
+__device__ __forceinline__ void gather_nodes(const F& f, const int bc[3], const Pos<R>& p,
+                                             R E[3], R B[3]) {
   R wz0[ORDER + 1], wz1[ORDER + 1], wx0[ORDER + 1], wx1[ORDER + 1];
   R wy0[ORDER + 1], wy1[ORDER + 1];
   int z0 = shape<R, ORDER>(p.c[0], p.o[0], 0, wz0) - p.c[0] + bc[0];
@@ -221,6 +315,13 @@ __device__ __forceinline__ void gather(const F& f, const int bc[3], const Pos<R>
   B[0] = interp<R, DIM, ORDER>(f, 3, z1, wz1, x0, wx0, y1, wy1);
   B[1] = interp<R, DIM, ORDER>(f, 4, z1, wz1, x1, wx1, y0, wy0);
   B[2] = interp<R, DIM, ORDER>(f, 5, z0, wz0, x1, wx1, y1, wy1);
+}
+
+template <typename R, int DIM, int ORDER, class F>
+__device__ __forceinline__ void gather(const F& f, const int bc[3], const Pos<R>& p, R E[3],
+                                       R B[3]) {
+  if constexpr (HasAxes<F>::value) gather_axes<R, DIM, ORDER>(f, bc, p, E, B);
+  else gather_nodes<R, DIM, ORDER>(f, bc, p, E, B);
 }
 
 // --------------------------------------------------------------------------
@@ -763,7 +864,7 @@ __global__ __launch_bounds__(NT) void k_gpd_tiled(StepK<R> P, Fields<R> F, PSoA<
   __syncthreads();
   typename std::conditional<STAGE, LdsFetch<R, LX, LY>, RegionFetch<R>>::type lf;
   if constexpr (STAGE) lf = LdsFetch<R, LX, LY>{sF, LV};
-  else lf = RegionFetch<R>{(const R* const*)F.F, g, gz0, gx0, gy0};
+  else lf = RegionFetch<R>{(const R* const*)F.F, g, g.periodic_z ? wrapi(gz0, g.nz) : gz0, gx0, gy0};
   LdsSinkT<A, LX, LY, DET> ls{sJ, LV};
   const int p0 = T.start[t], p1 = T.start[t + 1];
   // the whole state of the next particle is loaded while this one is pushed
