@@ -507,12 +507,19 @@ __device__ __forceinline__ bool deposit2d_pair(const StepK<R>& P, const Snk& snk
     CSi[a2] = CSi[a2 - 1] + kz * dSi[a2];
     Ce[a2] = Ce[a2 - 1] + kz * eps[a2];
   }
+  // A column is all zeros when eta = 0 and Ce (or fxe) = 0: a pair whose
+  // electron keeps its offset from the partner deposits nothing at all.  The
+  // tests are per lane, so a wave whose lanes all have zeros skips the column.
+  const bool ce_any = Ce[0] != (R)0 || Ce[1] != (R)0 || Ce[2] != (R)0;
 #pragma unroll
   for (int b = 0; b < 4; b++) {
     const R eta = (R)0.5 * (dx0[b] + dx1[b]);
     const R fxe = Sx[b] + eta;
+    if (eta != (R)0 || (ce_any && fxe != (R)0)) {
 #pragma unroll
-    for (int a2 = 0; a2 < 3; a2++) snk.add(2, rz + a2, rx + b, 0, CSi[a2] * eta + Ce[a2] * fxe);
+      for (int a2 = 0; a2 < 3; a2++)
+        snk.add(2, rz + a2, rx + b, 0, CSi[a2] * eta + Ce[a2] * fxe);
+    }
   }
   // Jx, Jy: the electron alone, on its own 3-node stencil.
   //   Jx(a, b + 1/2) = fz[a] * kx sum_{b' <= b} dSx[b'],  fz = S0z + dSz / 2
@@ -530,10 +537,13 @@ __device__ __forceinline__ bool deposit2d_pair(const StepK<R>& P, const Snk& snk
     fx[m] = S0x[m] + (R)0.5 * dSx[m];
   }
   const R cx0 = kx * dSx[0], cx1 = cx0 + kx * dSx[1];
+  if (cx0 != (R)0) {  // zero without motion along x (as cx1)
 #pragma unroll
-  for (int a2 = 0; a2 < NS; a2++) {
-    snk.add(0, ez + a2, ex + 0, 0, fz[a2] * cx0);
-    snk.add(0, ez + a2, ex + 1, 0, fz[a2] * cx1);
+    for (int a2 = 0; a2 < NS; a2++) snk.add(0, ez + a2, ex + 0, 0, fz[a2] * cx0);
+  }
+  if (cx1 != (R)0) {
+#pragma unroll
+    for (int a2 = 0; a2 < NS; a2++) snk.add(0, ez + a2, ex + 1, 0, fz[a2] * cx1);
   }
   if (vy != (R)0) {
     const R ky = -P.ky2d * w * vy;
