@@ -823,13 +823,13 @@ struct Impl {
       T.nstrag = h->counts + 4;
       if constexpr (DIM == 2)
         k_gpd_tiled<R, 2, ORDER, kT2Z, kT2X, 1, kExc, kGpdThreads<R>, DET>
-            <<<T.ntiles, kGpdThreads<R>, h->lds_tiled, h->stream>>>(P, F, S, T, h->scratch);
+            <<<T.ntiles, kGpdThreads<R>, h->lds_tiled, h->stream>>>(P, F, S, T, O, h->scratch);
       else if (h->stage)
         k_gpd_tiled<R, 3, ORDER, kT3, kT3, kT3, kExc, kGpdThreads<R>, DET>
-            <<<T.ntiles, kGpdThreads<R>, h->lds_tiled, h->stream>>>(P, F, S, T, h->scratch);
+            <<<T.ntiles, kGpdThreads<R>, h->lds_tiled, h->stream>>>(P, F, S, T, O, h->scratch);
       else
         k_gpd_tiled<R, 3, ORDER, kT3, kT3, kT3, kExc, kGpd3Threads, DET, false>
-            <<<T.ntiles, kGpd3Threads, h->lds_tiled, h->stream>>>(P, F, S, T, h->scratch);
+            <<<T.ntiles, kGpd3Threads, h->lds_tiled, h->stream>>>(P, F, S, T, O, h->scratch);
       HIPCHK(h, hipGetLastError());
     }
     {

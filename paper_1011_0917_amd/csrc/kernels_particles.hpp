@@ -10,6 +10,7 @@
 // rigid drift D of the lab-rest plasma (plus the window displacement).
 #pragma once
 
+#include <climits>
 #include <type_traits>
 
 #include "device_common.hpp"
@@ -362,15 +363,15 @@ __device__ __forceinline__ int esk_axis(int c0, R o0, int c1, R o1, R* S0, R* dS
 template <typename R, int ORDER, class Snk>
 __device__ __forceinline__ void deposit2d(const StepK<R>& P, const Snk& snk, const int bc[3],
                                           const Pos<R>& e0, const Pos<R>& e1, const Pos<R>& i0,
-                                          const Pos<R>& i1, R w, R vy) {
+                                          const Pos<R>& i1, R w, R vy, bool with_ion = true) {
   constexpr int NS = ORDER + 2;
   R S0z[NS], dSz[NS], S0x[NS], dSx[NS];
   int bz = esk_axis<R, ORDER>(e0.c[0], e0.o[0], e1.c[0], e1.o[0], S0z, dSz);
   int bx = esk_axis<R, ORDER>(e0.c[1], e0.o[1], e1.c[1], e1.o[1], S0x, dSx);
   const int rz = bc[0] + (bz - e0.c[0]), rx = bc[1] + (bx - e0.c[1]);
-  // partner: moves along z only
+  // partner: moves along z only (with_ion = false: the caller deposits it)
   R I0z[NS], dIz[NS], Ix[NS];
-  bool ion = P.ion_moves;
+  bool ion = P.ion_moves && with_ion;
   bool comb = false;
   int ibz = 0, ibx = 0;
   if (ion) {
@@ -566,7 +567,7 @@ __device__ __forceinline__ R wmix(R s0a, R dsa, R s0b, R dsb) {
 template <typename R, int ORDER, class Snk>
 __device__ __forceinline__ void deposit3d(const StepK<R>& P, const Snk& snk, const int bc[3],
                                           const Pos<R>& e0, const Pos<R>& e1, const Pos<R>& i0,
-                                          const Pos<R>& i1, R w) {
+                                          const Pos<R>& i1, R w, bool with_ion = true) {
   constexpr int NS = ORDER + 2;
   R S0z[NS], dSz[NS], S0x[NS], dSx[NS], S0y[NS], dSy[NS];
   int bz = esk_axis<R, ORDER>(e0.c[0], e0.o[0], e1.c[0], e1.o[0], S0z, dSz);
@@ -575,7 +576,7 @@ __device__ __forceinline__ void deposit3d(const StepK<R>& P, const Snk& snk, con
   const int rz = bc[0] + (bz - e0.c[0]), rx = bc[1] + (bx - e0.c[1]),
             ry = bc[2] + (by - e0.c[2]);
   R I0z[NS], dIz[NS], Ix[NS], Iy[NS];
-  bool ion = P.ion_moves, comb = false;
+  bool ion = P.ion_moves && with_ion, comb = false;
   int ibz = 0, ibx = 0, iby = 0;
   R wxi[ORDER + 1], wyi[ORDER + 1];
   if (ion) {
@@ -656,7 +657,8 @@ template <typename R, int DIM, int ORDER, class F, class Snk, class Hook = NoHoo
 __device__ __forceinline__ bool particle_step(const StepK<R>& P, const F& fetch, const Snk& snk,
                                               const int bc[3], const Pos<R>& e0,
                                               const Pos<R>& i0, const Pos<R>& i1, R xi[3],
-                                              R du[3], R w, const Hook& hook = Hook()) {
+                                              R du[3], R w, const Hook& hook = Hook(),
+                                              bool near = true) {
   R E[3], B[3], dv[3], gam;
   gather<R, DIM, ORDER>(fetch, bc, e0, E, B);
   hook(E, B);
@@ -669,11 +671,13 @@ __device__ __forceinline__ bool particle_step(const StepK<R>& P, const F& fetch,
   Pos<R> e1 = add_xi<R, DIM>(i1, xi);
   if (DIM == 2) {
     bool done = false;
+    // near = false: the partner is out of the sink's reach and the caller
+    // deposits it (partner_far); the electron deposits alone
     if constexpr (ORDER == 1)
-      done = deposit2d_pair<R>(P, snk, bc, e0, e1, i0, i1, xi_old, xi, w, dv[1]);
-    if (!done) deposit2d<R, ORDER>(P, snk, bc, e0, e1, i0, i1, w, dv[1]);
+      if (near) done = deposit2d_pair<R>(P, snk, bc, e0, e1, i0, i1, xi_old, xi, w, dv[1]);
+    if (!done) deposit2d<R, ORDER>(P, snk, bc, e0, e1, i0, i1, w, dv[1], near);
   } else {
-    deposit3d<R, ORDER>(P, snk, bc, e0, e1, i0, i1, w);
+    deposit3d<R, ORDER>(P, snk, bc, e0, e1, i0, i1, w, near);
   }
   if (!P.remove) return false;
   // outside [-lim, nz + lim] along z, for both members of the pair
@@ -681,6 +685,34 @@ __device__ __forceinline__ bool particle_step(const StepK<R>& P, const F& fetch,
   bool eo = e1.c[0] <= lo || e1.c[0] > hi || (e1.c[0] == hi && e1.o[0] > (R)0);
   bool io = i1.c[0] <= lo || i1.c[0] > hi || (i1.c[0] == hi && i1.o[0] > (R)0);
   return eo && io;
+}
+
+// Current of a partner deposited on its own, at absolute nodes: it moves
+// along z only, so its Esirkepov current is Jz alone (the separate-stencil
+// terms of deposit2d / deposit3d, in the same order).
+template <typename R, int DIM, int ORDER, class G>
+__device__ __forceinline__ void partner_far(const StepK<R>& P, const G& glob, const Pos<R>& i0,
+                                            const Pos<R>& i1, R w) {
+  if (!P.ion_moves) return;
+  constexpr int NS = ORDER + 2;
+  constexpr int NY = DIM == 3 ? ORDER + 1 : 1;
+  R I0z[NS], dIz[NS], wx[ORDER + 1], wy[ORDER + 1];
+  const int ibz = esk_axis<R, ORDER>(i0.c[0], i0.o[0], i1.c[0], i1.o[0], I0z, dIz);
+  const int ibx = shape<R, ORDER>(i0.c[1], i0.o[1], 0, wx);
+  const int iby = DIM == 3 ? shape<R, ORDER>(i0.c[2], i0.o[2], 0, wy) : 0;
+  const R kz = P.kj[0] * w;
+#pragma unroll
+  for (int b = 0; b <= ORDER; b++)
+#pragma unroll
+    for (int c = 0; c < NY; c++) {
+      R acc = (R)0;
+#pragma unroll
+      for (int a = 0; a < NS - 1; a++) {
+        if (DIM == 3) acc -= kz * dIz[a] * wx[b] * wy[c];
+        else acc -= kz * dIz[a] * wx[b];
+        glob.add(2, ibz + a, ibx + b, iby + c, acc);
+      }
+    }
 }
 
 template <typename R>
@@ -760,9 +792,10 @@ __global__ __launch_bounds__(256) void k_gpd_global(StepK<R> P, Fields<R> F, PSo
 // a margin of EXC cells of peculiar excursion, one row of drift and the
 // stencil reach; each particle of the tile gathers from LDS and deposits with
 // LDS atomics; the J region is then stored whole to the tile's scratch slot,
-// to be folded into the grid by the filter kernel.  A particle whose stencil
-// would leave the region is appended to the straggler list instead and is
-// advanced by the global path in the same step.
+// to be folded into the grid by the filter kernel.  A particle whose own
+// stencil would leave the region is appended to the straggler list instead
+// and is advanced by the global path in the same step; one whose partner
+// lies out of reach deposits the partner's current to the overflow grid.
 // --------------------------------------------------------------------------
 struct TileK {
   const int* start;  // particle range of tile t: [start[t], start[t+1])
@@ -792,7 +825,7 @@ struct TileGeom {
 template <typename R, int DIM, int ORDER, int TZ, int TX, int TY, int EXC, int NT, bool DET,
           bool STAGE = true>
 __global__ __launch_bounds__(NT) void k_gpd_tiled(StepK<R> P, Fields<R> F, PSoA<R> S, TileK T,
-                                                  void* scratch) {
+                                                  Ovf<R> O, void* scratch) {
   using TG = TileGeom<DIM, ORDER, TZ, TX, TY, EXC>;
   constexpr int LZ = TG::LZ, LX = TG::LX, LY = TG::LY, LV = TG::LV;
   using A = LdsAcc<R, DIM, DET, STAGE>;
@@ -871,6 +904,12 @@ __global__ __launch_bounds__(NT) void k_gpd_tiled(StepK<R> P, Fields<R> F, PSoA<
     }
   }
   for (int v = threadIdx.x; v < 3 * LV; v += NT) sJ[v] = (A)0;
+  // overflow rows reached by far partners, gathered per tile
+  __shared__ int far_rows[2];
+  if (threadIdx.x == 0) {
+    far_rows[0] = INT_MAX;
+    far_rows[1] = INT_MIN;
+  }
   __syncthreads();
   typename std::conditional<STAGE, LdsFetch<R, LX, LY>, RegionFetch<R>>::type lf;
   if constexpr (STAGE) lf = LdsFetch<R, LX, LY>{sF, LV};
@@ -906,14 +945,16 @@ __global__ __launch_bounds__(NT) void k_gpd_tiled(StepK<R> P, Fields<R> F, PSoA<
       riz = wrap_once(riz, g.nz);
     }
     const int rx = wrap_once(e0.c[1] - gx0, g.nx), rix = wrap_once(i0.c[1] - gx0, g.nx);
-    bool inside = rz >= TG::HLO && rz < LZ - TG::HHI && riz >= TG::HLO && riz < LZ - TG::HHI &&
-                  rx >= TG::HLO && rx < LX - TG::HHI && rix >= TG::HLO && rix < LX - TG::HHI;
+    // the electron's stencil must lie in the region; the partner's may not
+    // (its separate stencil then reaches the overflow grid)
+    bool inside = rz >= TG::HLO && rz < LZ - TG::HHI && rx >= TG::HLO && rx < LX - TG::HHI;
+    bool near = riz >= TG::HLO && riz < LZ - TG::HHI && rix >= TG::HLO && rix < LX - TG::HHI;
     int ry = 0;
     if (DIM == 3) {
       ry = wrap_once(e0.c[2] - gy0, g.ny);
       const int riy = wrap_once(i0.c[2] - gy0, g.ny);
-      inside = inside && ry >= TG::HLO && ry < LY - TG::HHI && riy >= TG::HLO &&
-               riy < LY - TG::HHI;
+      inside = inside && ry >= TG::HLO && ry < LY - TG::HHI;
+      near = near && riy >= TG::HLO && riy < LY - TG::HHI;
     }
     if (!inside) {
       T.strag[atomicAdd(T.nstrag, 1)] = p;
@@ -921,10 +962,20 @@ __global__ __launch_bounds__(NT) void k_gpd_tiled(StepK<R> P, Fields<R> F, PSoA<
     }
     Pos<R> i1 = ion_at<R, DIM>(b, r, P.D1);
     int bc[3] = {rz, rx, ry};
-    bool dead = particle_step<R, DIM, ORDER>(P, lf, ls, bc, e0, i0, i1, xi, du, w);
+    bool dead = particle_step<R, DIM, ORDER>(P, lf, ls, bc, e0, i0, i1, xi, du, w, NoHook(), near);
+    if (!near) {
+      atomicMin(&far_rows[0], min(e0.c[0], i0.c[0]) - ORDER - 1);
+      atomicMax(&far_rows[1], max(e0.c[0], i0.c[0]) + ORDER + 2);
+      typename std::conditional<DET, GlobalSinkFx<R>, GlobalSink<R>>::type glob{O, g};
+      partner_far<R, DIM, ORDER>(P, glob, i0, i1, w);
+    }
     store_state<R, DIM>(S, p, xi, du, dead);
   }
   __syncthreads();
+  if (threadIdx.x == 0 && far_rows[0] <= far_rows[1]) {
+    atomicMin(&O.rows[0], g.periodic_z ? 0 : far_rows[0]);
+    atomicMax(&O.rows[1], g.periodic_z ? g.nz : far_rows[1]);
+  }
   if constexpr (DET) {
     long long* dst = reinterpret_cast<long long*>(scratch) + (int64_t)t * 3 * LV;
     for (int v = threadIdx.x; v < 3 * LV; v += NT) dst[v] = sJ[v];

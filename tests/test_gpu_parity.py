@@ -141,6 +141,44 @@ def test_boosted_3d_fp32_split_within_tolerance(P, name):
 
 
 # --------------------------------------------------------------------------
+# Pairs pulled apart: electrons born with u_x = 10 (0.57 cells per step) drift
+# about 15 cells across the 64-cell box in 100 steps, past their tile between
+# sorts (stragglers) and away from their partners, whose current then leaves
+# the tile's region (the far-partner deposit to the overflow grid).
+# --------------------------------------------------------------------------
+def test_separated_pairs_fp64_match_oracle(P):
+    W = WORKLOADS["boost13_2d_small"]
+    du = (10.0, 0.0, 0.0)
+    print("case boost13_2d_small fp64 du_x = 10", flush=True)
+    cfg, init, nst = resolve_gpu(W, precision="fp64", sort_interval=20)
+    sim = P.Simulation(cfg, capacity=init["capacity"])
+    sim.init_boosted_plasma(init["gamma_b"], n_uniform=init["n_lab"], laser=init["laser"], du=du)
+    sim.pic_step(nst)
+    dg = sim.diagnostics(lineout=True)
+    fg = {c: sim.get_field(c).cpu().numpy() for c in ("Ex", "Ey", "Ez", "Bx", "By", "Bz")}
+    parts = sim.particles()
+    sim.close()
+    kw, oinit = resolve_oracle(W)
+    s = O.Sim(**kw)
+    s.init(n_uniform=oinit["n_lab"], laser=oinit["laser"], du=du)
+    s.step(nst)
+    do = s.diagnostics(lineout=True)
+    fo = {c: s.get_field(c) for c in ("Ex", "Ey", "Ez", "Bx", "By", "Bz")}
+    check_fp64(dg, fg, do, fo)
+    # the pairs really are apart: electron x against the partner's birth x
+    live = parts["id"] >= 0
+    ids = parts["id"][live].astype(np.int64)
+    nx, ppc = W["nx"], W["ppc"]
+    j = (ids // ppc) % nx
+    k = ids // (ppc * nx)
+    xs = np.array([j_ + O.cell_offset(W["seed"], k_, 0, j_, s_, 1, nx, 1, ppc)
+                   for j_, k_, s_ in zip(j, k, ids % ppc)])
+    sep = np.abs((parts["x"][live] - xs + nx / 2) % nx - nx / 2)
+    print("median separation (cells)", float(np.median(sep)), flush=True)
+    assert np.mean(sep > 6.0) > 0.5
+
+
+# --------------------------------------------------------------------------
 # Deterministic mode: int64 fixed-point current sums
 # --------------------------------------------------------------------------
 def _state(P, W, precision, det, steps):
