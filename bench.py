@@ -4,8 +4,11 @@ Prints ONE JSON line.  The timed region is K full steps of ``pic_step`` (every
 step: injection, periodic sort, gather/push/deposit, current fold + filter,
 Yee update) on the gamma_boost = 130, 8192 x 512 cell, 8 particles/cell
 workload (33.5 M electrons with implicit ion partners) in the FP32 split
-precision form, all inputs resident in HBM.  Beside it: the same workload in
-FP64, per-kernel HIP-event times of the dominant kernel against the HBM
+precision form, all inputs resident in HBM.  K defaults to the workload's
+whole run (5000 steps): the cost of a step grows as the wake forms and pulls
+electrons away from their partners, so a short window at the start would
+overstate the rate.  Beside it: the same run in FP64 and in the deterministic
+mode, per-kernel HIP-event times of the dominant kernel against the HBM
 roofline, and the FP64 oracle timed on the host cores on a bounded sample.
 """
 import argparse
@@ -163,7 +166,8 @@ def cpu_baseline(name, nz_sample=256, steps=20):
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=200)
+    ap.add_argument("--steps", type=int, default=None,
+                    help="timed steps (default: the workload's whole run)")
     ap.add_argument("--warmup", type=int, default=20)
     ap.add_argument("--workload", default="boost130_2d")
     ap.add_argument("--sort-interval", type=int, default=50)
@@ -180,6 +184,9 @@ def main():
         print("bench.py measures one GPU: this build runs on a single MI355X "
               "(multi-GPU sharding is a design note, not built)", file=sys.stderr)
         sys.exit(2)
+    from workloads import WORKLOADS
+    if args.steps is None:
+        args.steps = WORKLOADS[args.workload]["steps"]
     import torch
     torch.cuda.set_device(0)
     log(f"bench: {args.workload} fp32 split, {args.warmup} warmup + {args.steps} timed steps")
@@ -218,16 +225,16 @@ def main():
     }
     if not args.no_fp64:
         log("bench: fp64 plain form")
-        r64 = run_gpu(args.workload, "fp64", max(args.steps // 2, 10), args.warmup,
-                      args.sort_interval, with_kernel_times=False)
+        r64 = run_gpu(args.workload, "fp64", args.steps, args.warmup, args.sort_interval,
+                      with_kernel_times=False)
         pps64 = r64["particles"] * r64["steps"] / (r64["ms"] * 1e-3)
         out["fp64"] = {"value": pps64, "unit": "particle-steps/s",
                        "ms_per_step": r64["ms"] / r64["steps"]}
         out["fp32_over_fp64"] = pps / pps64
     if not args.no_deterministic:
         log("bench: fp32 deterministic (int64 fixed-point currents)")
-        rd = run_gpu(args.workload, "fp32", max(args.steps // 2, 10), args.warmup,
-                     args.sort_interval, with_kernel_times=False, det=1)
+        rd = run_gpu(args.workload, "fp32", args.steps, args.warmup, args.sort_interval,
+                     with_kernel_times=False, det=1)
         out["deterministic"] = {
             "value": rd["particles"] * rd["steps"] / (rd["ms"] * 1e-3),
             "unit": "particle-steps/s", "ms_per_step": rd["ms"] / rd["steps"]}
