@@ -68,6 +68,11 @@ constexpr int kGpdThreads = sizeof(R) == 4 ? BFPIC_GPD_THREADS32 : BFPIC_GPD_THR
 #define BFPIC_GPD3_THREADS 512
 #endif
 constexpr int kGpd3Threads = BFPIC_GPD3_THREADS;
+// Tiles dispatched largest first (1) or in XCD-aware grid order (0)
+#ifndef BFPIC_TILE_ORDER
+#define BFPIC_TILE_ORDER 1
+#endif
+constexpr bool kTileOrder = BFPIC_TILE_ORDER != 0;
 // Rows per band of the fused 2D Yee kernel (one wave marches one band)
 #ifndef BFPIC_YEE_ROWS
 #define BFPIC_YEE_ROWS 16
@@ -121,6 +126,7 @@ struct bfpic_ctx {
   int* strag = nullptr;
   int* ovf_rows = nullptr;
   int* tile_start = nullptr;
+  int* tile_order = nullptr;
   void* scratch = nullptr;
   int* key = nullptr;
   int* rank = nullptr;
@@ -351,6 +357,8 @@ static int64_t plan(bfpic_ctx* h, int64_t cap, bfpic_ctx* fill, bfpic_sizes* sz)
   if (fill) fill->ovf_rows = (int*)p;
   p = P((h->maxtiles + 1) * 4);
   if (fill) fill->tile_start = (int*)p;
+  p = P(h->maxtiles * 4);
+  if (fill) fill->tile_order = (int*)p;
   // tile regions, then one row of tiles that stays zero (read for tile rows
   // outside the co-moving range)
   p = P(h->tiled ? (h->maxtiles + (int64_t)h->ntx * h->nty) * 3 * (int64_t)h->LV *
@@ -584,6 +592,12 @@ struct Impl {
     int ntiles = ntz * h->ntx * h->nty;
     k_tile_starts<<<(unsigned)cdiv(ntiles + 1, 256), 256, 0, h->stream>>>(
         h->off, h->tile_start, ntiles, (int)cpt, h->counts, (int)nkeys);
+    if (kTileOrder && ntiles > 0) {
+      // bins of 2^shift particles, the mean tile near bin 32
+      int shift = 0;
+      while (((int64_t)cpt * h->cfg.ppc >> (shift + 1)) >= 32) shift++;
+      k_tile_order<<<1, 1024, 0, h->stream>>>(h->tile_start, ntiles, shift, h->tile_order);
+    }
     HIPCHK(h, hipGetLastError());
     h->cur = 1 - h->cur;
     h->ntz = ntz;
@@ -815,6 +829,10 @@ struct Impl {
       Timer t(h, 0);
       TileK T;
       T.start = h->tile_start;
+      // largest first where the fields are staged; the 3D kernel that
+      // gathers from global memory keeps the XCD-aware order, whose
+      // neighbouring tiles share an L2 (measured 4.9 against 5.8 ms)
+      T.order = kTileOrder && (DIM == 2 || h->stage) ? h->tile_order : nullptr;
       T.ntiles = h->ntz * h->ntx * h->nty;
       T.ntx = h->ntx;
       T.nty = h->nty;

@@ -799,6 +799,7 @@ __global__ __launch_bounds__(256) void k_gpd_global(StepK<R> P, Fields<R> F, PSo
 // --------------------------------------------------------------------------
 struct TileK {
   const int* start;  // particle range of tile t: [start[t], start[t+1])
+  const int* order;  // dispatch order (largest first), or null: XCD-aware grid order
   int ntiles, ntx, nty;
   int zc0;           // first co-moving z cell of tile row 0
   int* strag;        // straggler slots
@@ -833,7 +834,7 @@ __global__ __launch_bounds__(NT) void k_gpd_tiled(StepK<R> P, Fields<R> F, PSoA<
   R* sF = reinterpret_cast<R*>(smem_raw);
   // 6 LV sizeof(R) is a multiple of 8
   A* sJ = reinterpret_cast<A*>(STAGE ? (unsigned char*)(sF + 6 * LV) : smem_raw);
-  const int t = xcd_remap(blockIdx.x, T.ntiles);
+  const int t = T.order ? T.order[blockIdx.x] : xcd_remap(blockIdx.x, T.ntiles);
   const int ty = DIM == 3 ? t % T.nty : 0;
   const int tx = (t / T.nty) % T.ntx;
   const int tz = t / (T.nty * T.ntx);

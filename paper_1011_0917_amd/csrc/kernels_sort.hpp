@@ -219,4 +219,35 @@ __global__ __launch_bounds__(256) void k_tile_starts(const int* off, int* start,
   }
 }
 
+// Largest-first dispatch order of the tiles (longest-processing-time list
+// scheduling): once the wake bunches the plasma, a few tiles hold several
+// times the mean count and would otherwise finish last.  Tiles are binned by
+// particle count (bin width 2^shift) and listed from the fullest bin down.
+// One workgroup.  The order inside a bin is arbitrary: every tile owns its
+// scratch region, so the order changes no result.
+constexpr int kOrderBins = 256;
+
+__global__ __launch_bounds__(1024) void k_tile_order(const int* start, int ntiles, int shift,
+                                                     int* order) {
+  __shared__ int cnt[kOrderBins];
+  for (int b = threadIdx.x; b < kOrderBins; b += blockDim.x) cnt[b] = 0;
+  __syncthreads();
+  auto bin = [&](int t) {
+    const int b = (start[t + 1] - start[t]) >> shift;
+    return kOrderBins - 1 - (b < kOrderBins - 1 ? b : kOrderBins - 1);
+  };
+  for (int t = threadIdx.x; t < ntiles; t += blockDim.x) atomicAdd(&cnt[bin(t)], 1);
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    int s = 0;
+    for (int b = 0; b < kOrderBins; b++) {
+      const int c = cnt[b];
+      cnt[b] = s;
+      s += c;
+    }
+  }
+  __syncthreads();
+  for (int t = threadIdx.x; t < ntiles; t += blockDim.x) order[atomicAdd(&cnt[bin(t)], 1)] = t;
+}
+
 }  // namespace bfpic
