@@ -1,6 +1,6 @@
 // kernels_sort.hpp -- particle sort by co-moving tile-major cell key, ties by
-// id: count (atomic rank per key), exclusive scan, scatter, per-cell
-// insertion sort by id (makes the order unique), interleave of each tile by
+// id: count (atomic rank per key), exclusive scan, scatter, per-cell sort
+// by id (makes the order unique), interleave of each tile by
 // rank within cell, permute, tile starts.
 #pragma once
 
@@ -118,12 +118,46 @@ __global__ __launch_bounds__(256) void k_sort_scatter(const int* counts, const i
   perm[off[key[p]] + rank[p]] = p;
 }
 
-// Within each key the atomic ranks are arbitrary: order them by id.
+// Within each key the atomic ranks are arbitrary: order them by id.  A cell
+// of up to kCellReg particles is sorted in registers (its slots and ids are
+// loaded in two independent rounds, then an odd-even transposition network
+// orders them); a fuller one by insertion through memory.  Ids are distinct,
+// so both give the same order.
+constexpr int kCellReg = 16;
+
 __global__ __launch_bounds__(256) void k_sort_cells(const int* off, const int* id, int* perm,
                                                     int nkeys) {
   int c = blockIdx.x * blockDim.x + threadIdx.x;
   if (c >= nkeys) return;
   int a = off[c], b = off[c + 1];
+  const int n = b - a;
+  if (n <= 1) return;
+  if (n <= kCellReg) {
+    int pv[kCellReg], iv[kCellReg];
+#pragma unroll
+    for (int m = 0; m < kCellReg; m++) pv[m] = m < n ? perm[a + m] : 0;
+#pragma unroll
+    for (int m = 0; m < kCellReg; m++) iv[m] = m < n ? id[pv[m]] : INT_MAX;
+    // n passes of odd-even transposition sort n entries; the padding
+    // (INT_MAX) stays at the end
+    for (int pass = 0; pass < n; pass++) {
+#pragma unroll
+      for (int m = 0; m + 1 < kCellReg; m += 2) {
+        const int q = m + (pass & 1);
+        if (q + 1 < kCellReg && iv[q] > iv[q + 1]) {
+          const int ti = iv[q], tp = pv[q];
+          iv[q] = iv[q + 1];
+          pv[q] = pv[q + 1];
+          iv[q + 1] = ti;
+          pv[q + 1] = tp;
+        }
+      }
+    }
+#pragma unroll
+    for (int m = 0; m < kCellReg; m++)
+      if (m < n) perm[a + m] = pv[m];
+    return;
+  }
   for (int x = a + 1; x < b; x++) {
     int pv = perm[x];
     int iv = id[pv];
