@@ -123,6 +123,11 @@ WORKLOADS["adjoint_2d_small"] = small("adjoint_2d", nz=128, nx=32, ppc=2, steps=
                                       interval=10, nknots=5, loss_steps=20)
 WORKLOADS["adjoint_2d_tiny"] = small("adjoint_2d", nz=64, nx=16, ppc=2, steps=40,
                                      interval=10, nknots=4, loss_steps=10)
+# On-axis laser history in vacuum at gamma_boost = 5 (one of the boosts of the
+# hyperbolic-rotation comparison), FP64, no window: the boosted-frame record
+# history and its Lorentz transform to the lab frame.
+WORKLOADS["lab_history_2d"] = small("boost13_2d", gamma_b=5.0, nz=256, nx=32, ppc=1, steps=60,
+                                    window=None, precision="fp64")
 
 
 def _resolve(W, beta, boosted_dz, yee_dt, group_beta):
