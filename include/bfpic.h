@@ -207,6 +207,62 @@ int bfpic_window_due(bfpic_ctx* h, int32_t* ncells);
  * mask is reserved (pass 0xffffffff).  Synchronises the stream. */
 int diagnostics(bfpic_ctx* h, uint32_t mask, bfpic_diag* out, double* lineout_dev);
 
+/* ---- lab-frame and spectral diagnostics of the on-axis laser field ---- */
+
+/* Where and when a record was taken: boosted-frame time t' = step dt, the
+ * boosted position of row 0 z0' = window_cells dz (row i lies at
+ * z0' + i dz'), the row spacing, the number of rows n = nz + 1 and the boost. */
+typedef struct bfpic_axis_meta {
+  int64_t step;
+  double t_prime, z0_prime, dz_prime;
+  int32_t n;
+  double gamma_b, beta_b;
+} bfpic_axis_meta;
+
+/* On-axis history of the transverse laser field, the quantity whose
+ * boosted-frame and Lorentz-transformed histories are compared in the
+ * section "Effect of the hyperbolic rotation in Minkowski space" (Fig. 2).
+ * Writes rows i = 0..nz of the axis row (j = nx/2, k = ny/2) into out_dev
+ * (device, nz + 1 doubles):
+ *   frame 0: the boosted-frame E'_y at its nodes;
+ *   frame 1: the lab-frame field at the same events, E_y = gamma_b (E'_y -
+ *            beta_b B'_x) (inverse transform of the transverse fields, c = 1),
+ *            with B'_x, stored at half rows, averaged onto row i.
+ * Fields at integer time (after the last completed step).  *meta (host, may
+ * be NULL) receives the record's place and time.  ERR_ARG for a frame other
+ * than 0 or 1 or a NULL out_dev, ERR_STATE before init.  Asynchronous. */
+int bfpic_axis_record(bfpic_ctx* h, int32_t frame, double* out_dev, bfpic_axis_meta* meta);
+
+/* Lorentz transform of a record history to the lab frame (section "Effect of
+ * the hyperbolic rotation in Minkowski space": boosted data shown in the
+ * laboratory-frame moving window).  rec_dev: nrec records of n doubles
+ * (record r, row i at rec_dev[r n + i]); t_prime_dev, z0_prime_dev: per
+ * record t' (strictly increasing) and z0' (device arrays of nrec doubles);
+ * dz_prime: row spacing.  Output (device, nt x nzeta doubles, row-major in
+ * t): the value at lab time t_m = t0 + m dt and window coordinate
+ * zeta_k = zeta0 + k dzeta, i.e. at z = zeta_k + v_window t_m, read at the
+ * boosted event t' = gamma_b (t - beta_b z), z' = gamma_b (z - beta_b t) by
+ * linear interpolation along z' within the two records that bracket t', then
+ * linearly in t'; NaN where that event lies outside the recorded rows or
+ * times.  FP64.  ERR_ARG for nrec < 2, n < 2, nt < 1, nzeta < 1,
+ * dz_prime <= 0, gamma_b < 1 or a NULL pointer.  Asynchronous. */
+int bfpic_back_transform(bfpic_ctx* h, const double* rec_dev, const double* t_prime_dev,
+                         const double* z0_prime_dev, int64_t nrec, int32_t n,
+                         double dz_prime, double gamma_b, double t0, double dt, int32_t nt,
+                         double zeta0, double dzeta, int32_t nzeta, double v_window,
+                         double* out_dev);
+
+/* Spectral content of each record, as in the spectral content histories of
+ * the section "Mitigation of a numerical instability" (Fig. 3): the power
+ * |X_q|^2 of the discrete Fourier transform X_q = sum_i x_i exp(-2 pi i q i / m)
+ * of record r zero-padded to m points, for q = 0..m/2 (wavenumber
+ * 2 pi q / (m dz')), into out_dev[r (m/2 + 1) + q].  rec_dev as for
+ * bfpic_back_transform; m a power of two, 2 <= m <= 8192, 1 <= n <= m (longer
+ * records: pass a window of them).  FP64, radix-2 in LDS.  ERR_ARG
+ * otherwise.  Asynchronous. */
+int bfpic_axis_spectrum(bfpic_ctx* h, const double* rec_dev, int64_t nrec, int32_t n, int32_t m,
+                        double* out_dev);
+
 /* ---- state access (tests and tools; asynchronous unless stated) ---- */
 
 /* Copies component comp at integer time (domain rows 0..nz; row nz is zero

@@ -73,6 +73,15 @@ class Loss(C.Structure):
                 ("i1", C.c_int32), ("j0", C.c_int32), ("j1", C.c_int32)]
 
 
+class AxisMeta(C.Structure):
+    _fields_ = [("step", C.c_int64), ("t_prime", C.c_double), ("z0_prime", C.c_double),
+                ("dz_prime", C.c_double), ("n", C.c_int32), ("gamma_b", C.c_double),
+                ("beta_b", C.c_double)]
+
+    def as_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_}
+
+
 _lib = None
 
 EXPORTS = ["bfpic_beta", "bfpic_drift_u", "bfpic_group_gamma", "bfpic_boosted_group_beta",
@@ -81,7 +90,8 @@ EXPORTS = ["bfpic_beta", "bfpic_drift_u", "bfpic_group_gamma", "bfpic_boosted_gr
            "moving_window_shift", "bfpic_window_due", "diagnostics", "bfpic_get_field",
            "bfpic_set_field", "bfpic_num_slots", "bfpic_get_particles", "bfpic_sort",
            "bfpic_last_sort", "bfpic_tile_shape", "bfpic_kernel_timing", "bfpic_kernel_time",
-           "bfpic_adjoint_tape_bytes", "bfpic_forward_loss", "pic_step_adjoint"]
+           "bfpic_adjoint_tape_bytes", "bfpic_forward_loss", "pic_step_adjoint",
+           "bfpic_axis_record", "bfpic_back_transform", "bfpic_axis_spectrum"]
 
 
 def lib():
@@ -119,6 +129,10 @@ def lib():
         "bfpic_adjoint_tape_bytes": (C.c_int, [p, i32, i32, C.POINTER(i64)]),
         "bfpic_forward_loss": (C.c_int, [p, i32, i32, C.POINTER(Loss), p, i64, C.POINTER(d)]),
         "pic_step_adjoint": (C.c_int, [p, C.POINTER(d), C.POINTER(d), i32]),
+        "bfpic_axis_record": (C.c_int, [p, i32, p, C.POINTER(AxisMeta)]),
+        "bfpic_back_transform": (C.c_int, [p, p, p, p, i64, i32, d, d, d, d, i32, d, d, i32, d,
+                                           p]),
+        "bfpic_axis_spectrum": (C.c_int, [p, p, i64, i32, i32, p]),
     }
     for name, (res, args) in sig.items():
         f = getattr(L, name)
@@ -241,6 +255,42 @@ class Simulation:
         return out
 
     # ---- state access ----
+    def axis_record(self, frame=1):
+        """On-axis transverse laser field (rows 0..nz): frame 0 boosted E'_y,
+        frame 1 the lab field gamma_b (E'_y - beta_b B'_x).  Returns (device
+        tensor, meta dict)."""
+        import torch
+        m = AxisMeta()
+        out = torch.empty(self.cfg.nz + 1, dtype=torch.float64, device=self.device)
+        _check(lib().bfpic_axis_record(self.h, int(frame), C.c_void_p(out.data_ptr()),
+                                       C.byref(m)), self.h)
+        return out, m.as_dict()
+
+    def back_transform(self, rec, t_prime, z0_prime, dz_prime, gamma_b, t0, dt, nt, zeta0,
+                       dzeta, nzeta, v_window):
+        """Lab-frame values (nt x nzeta) of a record history, see
+        bfpic_back_transform.  rec: (nrec, n) device tensor (FP64)."""
+        import torch
+        rec = torch.as_tensor(rec, dtype=torch.float64, device=self.device).contiguous()
+        tp = torch.as_tensor(t_prime, dtype=torch.float64, device=self.device).contiguous()
+        z0 = torch.as_tensor(z0_prime, dtype=torch.float64, device=self.device).contiguous()
+        out = torch.empty((int(nt), int(nzeta)), dtype=torch.float64, device=self.device)
+        _check(lib().bfpic_back_transform(
+            self.h, C.c_void_p(rec.data_ptr()), C.c_void_p(tp.data_ptr()),
+            C.c_void_p(z0.data_ptr()), rec.shape[0], rec.shape[1], float(dz_prime),
+            float(gamma_b), float(t0), float(dt), int(nt), float(zeta0), float(dzeta),
+            int(nzeta), float(v_window), C.c_void_p(out.data_ptr())), self.h)
+        return out
+
+    def axis_spectrum(self, rec, m):
+        """|DFT|^2 (q = 0..m/2) of each record zero-padded to m points."""
+        import torch
+        rec = torch.as_tensor(rec, dtype=torch.float64, device=self.device).contiguous()
+        out = torch.empty((rec.shape[0], int(m) // 2 + 1), dtype=torch.float64, device=self.device)
+        _check(lib().bfpic_axis_spectrum(self.h, C.c_void_p(rec.data_ptr()), rec.shape[0],
+                                         rec.shape[1], int(m), C.c_void_p(out.data_ptr())), self.h)
+        return out
+
     def get_field(self, comp):
         import torch
         comp = COMP.get(comp, comp)

@@ -19,6 +19,7 @@
 #include "kernels_particles.hpp"
 #include "kernels_sort.hpp"
 #include "kernels_adjoint.hpp"
+#include "kernels_lab.hpp"
 
 using namespace bfpic;
 
@@ -1468,6 +1469,13 @@ struct Impl {
     return BFPIC_OK;
   }
 
+  static int axis_record(bfpic_ctx* h, int frame, double* out) {
+    k_axis_record<R><<<(unsigned)cdiv(h->nz + 1, 256), 256, 0, h->stream>>>(
+        h->g, fields(h), frame, h->gamma_b, h->beta_b, out);
+    HIPCHK(h, hipGetLastError());
+    return BFPIC_OK;
+  }
+
   static int get_field(bfpic_ctx* h, int comp, double* out) {
     const Geo& g = h->g;
     const R* A;
@@ -1646,6 +1654,68 @@ extern "C" int diagnostics(bfpic_ctx* h, uint32_t mask, bfpic_diag* out, double*
   if (!h || !out) return BFPIC_ERR_ARG;
   if (!h->inited) return fail(h, BFPIC_ERR_STATE, "diagnostics before init");
   BFPIC_DISPATCH(h, I::diag(h, out, lineout));
+}
+
+extern "C" int bfpic_axis_record(bfpic_ctx* h, int32_t frame, double* out, bfpic_axis_meta* meta) {
+  if (!h || !out || (frame != 0 && frame != 1)) return BFPIC_ERR_ARG;
+  if (!h->inited) return fail(h, BFPIC_ERR_STATE, "axis record before init");
+  if (meta) {
+    meta->step = h->step;
+    meta->t_prime = (double)h->step * h->dt;
+    meta->z0_prime = (double)h->window_cells * h->dz;
+    meta->dz_prime = h->dz;
+    meta->n = h->nz + 1;
+    meta->gamma_b = h->gamma_b;
+    meta->beta_b = h->beta_b;
+  }
+  BFPIC_DISPATCH(h, I::axis_record(h, frame, out));
+}
+
+extern "C" int bfpic_back_transform(bfpic_ctx* h, const double* rec, const double* tp,
+                                    const double* z0, int64_t nrec, int32_t n, double dz,
+                                    double gamma_b, double t0, double dt, int32_t nt,
+                                    double zeta0, double dzeta, int32_t nzeta, double v_window,
+                                    double* out) {
+  if (!h) return BFPIC_ERR_ARG;
+  if (!rec || !tp || !z0 || !out || nrec < 2 || n < 2 || nt < 1 || nzeta < 1 || !(dz > 0.0) ||
+      !(gamma_b >= 1.0))
+    return fail(h, BFPIC_ERR_ARG, "back transform arguments");
+  BackK K;
+  K.rec = rec;
+  K.tp = tp;
+  K.z0 = z0;
+  K.nrec = nrec;
+  K.n = n;
+  K.dz = dz;
+  K.gamma = gamma_b;
+  K.beta = bfpic_beta(gamma_b);
+  K.t0 = t0;
+  K.dt = dt;
+  K.zeta0 = zeta0;
+  K.dzeta = dzeta;
+  K.vw = v_window;
+  K.nt = nt;
+  K.nzeta = nzeta;
+  const int64_t tot = (int64_t)nt * nzeta;
+  k_back_transform<<<(unsigned)cdiv(tot, 256), 256, 0, h->stream>>>(K, out);
+  HIPCHK(h, hipGetLastError());
+  return BFPIC_OK;
+}
+
+extern "C" int bfpic_axis_spectrum(bfpic_ctx* h, const double* rec, int64_t nrec, int32_t n,
+                                   int32_t m, double* out) {
+  if (!h) return BFPIC_ERR_ARG;
+  if (!rec || !out || nrec < 1 || m < 2 || m > 8192 || (m & (m - 1)) != 0 || n < 1 || n > m ||
+      nrec > 0x7fffffff)
+    return fail(h, BFPIC_ERR_ARG, "spectrum arguments");
+  int logm = 0;
+  while ((1 << logm) < m) logm++;
+  const size_t lds = (size_t)2 * m * sizeof(double);
+  HIPCHK(h, hipFuncSetAttribute((const void*)k_axis_spectrum,
+                                hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
+  k_axis_spectrum<<<(unsigned)nrec, 256, lds, h->stream>>>(rec, n, m, logm, out);
+  HIPCHK(h, hipGetLastError());
+  return BFPIC_OK;
 }
 
 extern "C" int bfpic_get_field(bfpic_ctx* h, int32_t comp, double* out) {

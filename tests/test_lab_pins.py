@@ -124,3 +124,23 @@ def test_boosted_laser_carrier_transform():
     q_carrier = d * 1.0 * m * kw["dz"] / (2 * math.pi)   # k0 = 1 (units of omega0 / c)
     assert abs(q_peak - q_carrier) <= 1.0, (q_peak, q_carrier)
     assert LAMBDA0 == 2 * math.pi
+
+
+def test_vacuum_history_reproduces_lab_pulse():
+    W, kw, init, s = _vacuum_sim()
+    g = kw["gamma_b"]
+    dt = kw["dt"]
+    recs, tps = [LF.record(s, 1, g)], [0.0]
+    for n in range(W["steps"]):
+        s.step(1)
+        recs.append(LF.record(s, 1, g))
+        tps.append((n + 1) * dt)
+    grid = (900.0, 40.0, 100, 0.0, 0.2, 500, 1.0)
+    out = LF.back_transform(np.array(recs), np.array(tps), np.zeros(len(tps)), kw["dz"], g, *grid)
+    fin = np.isfinite(out)
+    assert fin.sum() > 1000
+    t0, dtl, nt, zeta0, dzeta, nzeta, vw = grid
+    lab = np.array([O.laser_eval(init["laser"], 2, 1.0, zeta0 + k * dzeta + vw * (t0 + m * dtl),
+                                 0.0, tp=t0 + m * dtl)[1] for m, k in zip(*np.nonzero(fin))])
+    err = np.linalg.norm(out[fin] - lab) / np.linalg.norm(lab)
+    assert err < 0.06, err

@@ -125,9 +125,12 @@ WORKLOADS["adjoint_2d_tiny"] = small("adjoint_2d", nz=64, nx=16, ppc=2, steps=40
                                      interval=10, nknots=4, loss_steps=10)
 # On-axis laser history in vacuum at gamma_boost = 5 (one of the boosts of the
 # hyperbolic-rotation comparison), FP64, no window: the boosted-frame record
-# history and its Lorentz transform to the lab frame.
-WORKLOADS["lab_history_2d"] = small("boost13_2d", gamma_b=5.0, nz=256, nx=32, ppc=1, steps=60,
-                                    window=None, precision="fp64")
+# history and its Lorentz transform to the lab frame.  The pulse is uniform
+# across the periodic box (waist 1e4 lambda0), so that it propagates as the
+# 1D pulse its analytic lab field describes.
+WORKLOADS["lab_history_2d"] = small(
+    "boost13_2d", gamma_b=5.0, nz=256, nx=32, ppc=1, steps=60, window=None, precision="fp64",
+    laser=dict(WORKLOADS["boost13_2d"]["laser"], place="box_center", w0_lambda0=1.0e4))
 
 
 def _resolve(W, beta, boosted_dz, yee_dt, group_beta):
