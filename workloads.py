@@ -123,6 +123,17 @@ WORKLOADS["adjoint_2d_small"] = small("adjoint_2d", nz=128, nx=32, ppc=2, steps=
                                       interval=10, nknots=5, loss_steps=20)
 WORKLOADS["adjoint_2d_tiny"] = small("adjoint_2d", nz=64, nx=16, ppc=2, steps=40,
                                      interval=10, nknots=4, loss_steps=10)
+# Drifting cold plasma without laser, periodic z: the high-frequency numerical
+# instability of a plasma streaming through the grid at -beta_b, and its
+# mitigation by filtering the current.  An undisturbed pair deposits nothing,
+# so the plasma is seeded with a uniform transverse birth momentum
+# (INSTABILITY_SEED_DU); the random in-cell positions make the seed noisy.
+INSTABILITY_SEED_DU = (1.0e-3, 0.0, 0.0)
+WORKLOADS["drift_instability_2d"] = small("boost130_2d", nz=256, nx=64, ppc=4, steps=2000,
+                                          zbc="periodic", window=None)
+WORKLOADS["drift_instability_2d_small"] = small("boost130_2d", nz=128, nx=32, ppc=2, steps=600,
+                                                zbc="periodic", window=None, precision="fp64")
+
 # On-axis laser history in vacuum at gamma_boost = 5 (one of the boosts of the
 # hyperbolic-rotation comparison), FP64, no window: the boosted-frame record
 # history and its Lorentz transform to the lab frame.  The pulse is uniform
