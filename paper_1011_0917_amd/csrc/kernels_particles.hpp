@@ -589,17 +589,31 @@ __device__ __forceinline__ void deposit3d(const StepK<R>& P, const Snk& snk, con
     place<R, ORDER>(oy == 1, wyi, Iy);
   }
   const R kz = P.kj[0] * w, kx = P.kj[1] * w, ky = P.kj[2] * w;
+  // Columns of the stencil whose values are all zero are skipped: a wave
+  // whose lanes all hold zeros for a column issues none of its LDS adds.  A
+  // pair whose electron keeps its offset from the partner (co-located, moving
+  // with it) gives exact zeros: the partner's term uses the same products as
+  // the electron's (dIz (Ix Iy) against dSz f with f = S0x S0y), and J_x, J_y
+  // vanish without x, y motion.
 #pragma unroll
   for (int b = 0; b < NS; b++)
 #pragma unroll
     for (int c = 0; c < NS; c++) {
-      R f = wmix(S0x[b], dSx[b], S0y[c], dSy[c]);
+      const R f = wmix(S0x[b], dSx[b], S0y[c], dSy[c]);
+      const R fi = comb ? Ix[b] * Iy[c] : (R)0;
+      R v[NS - 1];
       R acc = (R)0;
+      bool any = false;
 #pragma unroll
       for (int a = 0; a < NS - 1; a++) {
-        R Wi = comb ? dIz[a] * Ix[b] * Iy[c] : (R)0;
+        const R Wi = comb ? dIz[a] * fi : (R)0;
         acc += kz * (dSz[a] * f - Wi);
-        snk.add(2, rz + a, rx + b, ry + c, acc);
+        v[a] = acc;
+        any = any || acc != (R)0;
+      }
+      if (any) {
+#pragma unroll
+        for (int a = 0; a < NS - 1; a++) snk.add(2, rz + a, rx + b, ry + c, v[a]);
       }
     }
   if (ion && !comb) {
@@ -617,30 +631,40 @@ __device__ __forceinline__ void deposit3d(const StepK<R>& P, const Snk& snk, con
         }
       }
   }
+  bool mx = false, my = false;  // any motion along x, y
 #pragma unroll
-  for (int a = 0; a < NS; a++)
+  for (int m = 0; m < NS; m++) {
+    mx = mx || dSx[m] != (R)0;
+    my = my || dSy[m] != (R)0;
+  }
+  if (mx) {
 #pragma unroll
-    for (int c = 0; c < NS; c++) {
-      R f = wmix(S0z[a], dSz[a], S0y[c], dSy[c]);
-      R acc = (R)0;
+    for (int a = 0; a < NS; a++)
 #pragma unroll
-      for (int b = 0; b < NS - 1; b++) {
-        acc += kx * dSx[b] * f;
-        snk.add(0, rz + a, rx + b, ry + c, acc);
+      for (int c = 0; c < NS; c++) {
+        R f = wmix(S0z[a], dSz[a], S0y[c], dSy[c]);
+        R acc = (R)0;
+#pragma unroll
+        for (int b = 0; b < NS - 1; b++) {
+          acc += kx * dSx[b] * f;
+          snk.add(0, rz + a, rx + b, ry + c, acc);
+        }
       }
-    }
+  }
+  if (my) {
 #pragma unroll
-  for (int a = 0; a < NS; a++)
+    for (int a = 0; a < NS; a++)
 #pragma unroll
-    for (int b = 0; b < NS; b++) {
-      R f = wmix(S0z[a], dSz[a], S0x[b], dSx[b]);
-      R acc = (R)0;
+      for (int b = 0; b < NS; b++) {
+        R f = wmix(S0z[a], dSz[a], S0x[b], dSx[b]);
+        R acc = (R)0;
 #pragma unroll
-      for (int c = 0; c < NS - 1; c++) {
-        acc += ky * dSy[c] * f;
-        snk.add(1, rz + a, rx + b, ry + c, acc);
+        for (int c = 0; c < NS - 1; c++) {
+          acc += ky * dSy[c] * f;
+          snk.add(1, rz + a, rx + b, ry + c, acc);
+        }
       }
-    }
+  }
 }
 
 // --------------------------------------------------------------------------
