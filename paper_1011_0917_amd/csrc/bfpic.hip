@@ -79,6 +79,11 @@ constexpr bool kTileOrder = BFPIC_TILE_ORDER != 0;
 #define BFPIC_YEE_ROWS 16
 #endif
 constexpr int kYeeRows = BFPIC_YEE_ROWS;
+// Rows per thread of the 3D z sweep (fold + z passes)
+#ifndef BFPIC_FILT3_ROWS
+#define BFPIC_FILT3_ROWS 32
+#endif
+constexpr int kFilt3Rows = BFPIC_FILT3_ROWS;
 constexpr int kF3 = 8;
 constexpr int kNumTimers = 7;
 
@@ -746,7 +751,7 @@ struct Impl {
   // (not state during a step) hold the intermediate grids.
   template <int NP, bool DET>
   static void filt3(bfpic_ctx* h, const FoldK<R>& K, const FiltK& fk, const Fields<R>& Jf) {
-    constexpr int SZ = 16, SX = 16, FY = 64 - 2 * NP;
+    constexpr int SZ = kFilt3Rows, SX = 16, FY = 64 - 2 * NP;
     const Geo& g = h->g;
     Fields<R> T1, T2;
     for (int c = 0; c < 3; c++) {
