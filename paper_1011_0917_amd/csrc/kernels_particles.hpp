@@ -711,13 +711,16 @@ __device__ __forceinline__ bool particle_step(const StepK<R>& P, const F& fetch,
   return eo && io;
 }
 
-// Current of a partner deposited on its own, at absolute nodes: it moves
-// along z only, so its Esirkepov current is Jz alone (the separate-stencil
-// terms of deposit2d / deposit3d, in the same order).
-template <typename R, int DIM, int ORDER, class G>
-__device__ __forceinline__ void partner_far(const StepK<R>& P, const G& glob, const Pos<R>& i0,
+// Current of a partner deposited on its own, at absolute nodes of the
+// overflow grid: it moves along z only, so its Esirkepov current is Jz alone
+// (the separate-stencil terms of deposit2d / deposit3d, in the same order).
+// Its nodes lie within a node of its birth column (and row of y), so one
+// branchless wrap places them; rows outside storage (open z) are dropped.
+template <typename R, int DIM, int ORDER, bool DET>
+__device__ __forceinline__ void partner_far(const StepK<R>& P, const Ovf<R>& O, const Pos<R>& i0,
                                             const Pos<R>& i1, R w) {
   if (!P.ion_moves) return;
+  const Geo& g = P.g;
   constexpr int NS = ORDER + 2;
   constexpr int NY = DIM == 3 ? ORDER + 1 : 1;
   R I0z[NS], dIz[NS], wx[ORDER + 1], wy[ORDER + 1];
@@ -729,12 +732,23 @@ __device__ __forceinline__ void partner_far(const StepK<R>& P, const G& glob, co
   for (int b = 0; b <= ORDER; b++)
 #pragma unroll
     for (int c = 0; c < NY; c++) {
+      const int j = wrap_once(ibx + b, g.nx);
+      const int k = DIM == 3 ? wrap_once(iby + c, g.ny) : 0;
       R acc = (R)0;
 #pragma unroll
       for (int a = 0; a < NS - 1; a++) {
         if (DIM == 3) acc -= kz * dIz[a] * wx[b] * wy[c];
         else acc -= kz * dIz[a] * wx[b];
-        glob.add(2, ibz + a, ibx + b, iby + c, acc);
+        int i = ibz + a;
+        if (g.periodic_z) i = wrapi(i, g.nz);  // absolute rows carry the whole drift
+        else if (i < -kGuard || i > g.nz + kGuard) continue;
+        if (acc == (R)0) continue;
+        const int64_t n = ((int64_t)(i + kGuard) * g.nx + j) * g.ny + k;
+        if constexpr (DET)
+          atomicAdd(reinterpret_cast<unsigned long long*>(&O.Jq[2][n]),
+                    (unsigned long long)to_fixed((double)acc));
+        else
+          atomicAdd(&O.J[2][n], acc);
       }
     }
 }
@@ -991,8 +1005,7 @@ __global__ __launch_bounds__(NT) void k_gpd_tiled(StepK<R> P, Fields<R> F, PSoA<
     if (!near) {
       atomicMin(&far_rows[0], min(e0.c[0], i0.c[0]) - ORDER - 1);
       atomicMax(&far_rows[1], max(e0.c[0], i0.c[0]) + ORDER + 2);
-      typename std::conditional<DET, GlobalSinkFx<R>, GlobalSink<R>>::type glob{O, g};
-      partner_far<R, DIM, ORDER>(P, glob, i0, i1, w);
+      partner_far<R, DIM, ORDER, DET>(P, O, i0, i1, w);
     }
     store_state<R, DIM>(S, p, xi, du, dead);
   }
