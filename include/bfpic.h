@@ -263,6 +263,34 @@ int bfpic_back_transform(bfpic_ctx* h, const double* rec_dev, const double* t_pr
 int bfpic_axis_spectrum(bfpic_ctx* h, const double* rec_dev, int64_t nrec, int32_t n, int32_t m,
                         double* out_dev);
 
+/* ---- witness electrons (section "Modeling of up to 1 TeV stages", Fig. 4:
+ * energy gain of the accelerated beam against laboratory position) ---- */
+
+/* Binds n witness electrons: test particles that feel the run's fields and
+ * deposit no current.  state_dev: caller-owned device array of n rows of six
+ * FP64 values (z, x, y, u_z, u_x, u_y), position in grid cells relative to
+ * the window, momentum of the calculation frame; it must stay valid while
+ * bound.  Each pic_step then, before the plasma moves, gathers E and B at
+ * every witness from the start-of-step fields with the deposit's shape (the
+ * working-precision grid read as FP64; no field beyond rows 0..nz in open
+ * z), applies the relativistic Boris rotation in FP64 with charge -1 and
+ * moves it by v dt (x, y periodic; z wraps in a periodic box); a window
+ * shift lowers every z by the shift.  Witnesses leave no mark on the
+ * fields or the plasma.  n = 0 unbinds; init_boosted_plasma unbinds.  The
+ * taped adjoint run refuses to run with witnesses bound (ERR_STATE).
+ * ERR_ARG for n < 0 or a null array with n > 0, ERR_STATE before init.
+ * Calls on one context are ordered on its stream. */
+int bfpic_witness_bind(bfpic_ctx* h, int32_t n, double* state_dev);
+
+/* Laboratory view of the bound witnesses into out_dev (n rows of four FP64
+ * values): lab time, lab position, gamma and u_z of the event (t', z') with
+ * t' = step dt, z' = (z + window cells) dz, the momentum boosted back from
+ * the frame moving at +beta_b along z: t = gamma_b (t' + beta_b z'),
+ * z = gamma_b (z' + beta_b t'), gamma = gamma_b (gamma' + beta_b u'_z),
+ * u_z = gamma_b (u'_z + beta_b gamma').  ERR_STATE with none bound.
+ * Asynchronous. */
+int bfpic_witness_lab(bfpic_ctx* h, double* out_dev);
+
 /* ---- state access (tests and tools; asynchronous unless stated) ---- */
 
 /* Copies component comp at integer time (domain rows 0..nz; row nz is zero

@@ -91,7 +91,8 @@ EXPORTS = ["bfpic_beta", "bfpic_drift_u", "bfpic_group_gamma", "bfpic_boosted_gr
            "bfpic_set_field", "bfpic_num_slots", "bfpic_get_particles", "bfpic_sort",
            "bfpic_last_sort", "bfpic_tile_shape", "bfpic_kernel_timing", "bfpic_kernel_time",
            "bfpic_adjoint_tape_bytes", "bfpic_forward_loss", "pic_step_adjoint",
-           "bfpic_axis_record", "bfpic_back_transform", "bfpic_axis_spectrum"]
+           "bfpic_axis_record", "bfpic_back_transform", "bfpic_axis_spectrum",
+           "bfpic_witness_bind", "bfpic_witness_lab"]
 
 
 def lib():
@@ -133,6 +134,8 @@ def lib():
         "bfpic_back_transform": (C.c_int, [p, p, p, p, i64, i32, d, d, d, d, i32, d, d, i32, d,
                                            p]),
         "bfpic_axis_spectrum": (C.c_int, [p, p, i64, i32, i32, p]),
+        "bfpic_witness_bind": (C.c_int, [p, i32, p]),
+        "bfpic_witness_lab": (C.c_int, [p, p]),
     }
     for name, (res, args) in sig.items():
         f = getattr(L, name)
@@ -231,6 +234,7 @@ class Simulation:
         _check(lib().init_boosted_plasma(self.h, float(gamma_boost),
                                          C.byref(dens) if dens is not None else None,
                                          C.byref(laser) if laser is not None else None), self.h)
+        self._wit = None  # init unbinds the witnesses
 
     def pic_step(self, nsteps=1):
         _check(lib().pic_step(self.h, int(nsteps)), self.h)
@@ -290,6 +294,29 @@ class Simulation:
         _check(lib().bfpic_axis_spectrum(self.h, C.c_void_p(rec.data_ptr()), rec.shape[0],
                                          rec.shape[1], int(m), C.c_void_p(out.data_ptr())), self.h)
         return out
+
+    def witness_bind(self, state):
+        """Binds a (n, 6) FP64 device tensor of witness electrons (z, x, y,
+        u_z, u_x, u_y), advanced in place by every pic_step; None unbinds."""
+        if state is None:
+            _check(lib().bfpic_witness_bind(self.h, 0, None), self.h)
+            self._wit = None
+            return
+        import torch
+        if (state.dtype != torch.float64 or state.device.type != "cuda" or state.dim() != 2
+                or state.shape[1] != 6 or not state.is_contiguous()):
+            raise BfpicError("witness state: contiguous (n, 6) float64 device tensor")
+        _check(lib().bfpic_witness_bind(self.h, state.shape[0], C.c_void_p(state.data_ptr())),
+               self.h)
+        self._wit = state
+
+    def witness_lab(self):
+        """(n, 4) device tensor: lab t, z, gamma, u_z of the bound witnesses."""
+        import torch
+        n = 0 if getattr(self, "_wit", None) is None else self._wit.shape[0]
+        out = torch.empty((max(n, 1), 4), dtype=torch.float64, device=self.device)
+        _check(lib().bfpic_witness_lab(self.h, C.c_void_p(out.data_ptr())), self.h)
+        return out[:n]
 
     def get_field(self, comp):
         import torch

@@ -20,6 +20,7 @@
 #include "kernels_sort.hpp"
 #include "kernels_adjoint.hpp"
 #include "kernels_lab.hpp"
+#include "kernels_witness.hpp"
 
 using namespace bfpic;
 
@@ -146,6 +147,8 @@ struct bfpic_ctx {
   double* dout = nullptr;
   int* nanflag = nullptr;
   void* mur_save = nullptr;
+  double* wit = nullptr;  // caller's witness state (n x 6), or null
+  int nwit = 0;
   int64_t last_sort_nkeys = 0;
   int last_sort_tzmin = 0, last_sort_ntz = 0;
   const int* final_perm = nullptr;  // destination -> source slot of the last sort
@@ -964,6 +967,10 @@ struct Impl {
     }
     const Geo& g = h->g;
     StepK<R> P = step_consts(h);
+    if (h->nwit > 0) {
+      rc = witness_push(h);
+      if (rc) return rc;
+    }
     rc = h->det ? particles_and_currents<true>(h, P) : particles_and_currents<false>(h, P);
     if (rc) return rc;
     rc = yee(h);
@@ -1303,8 +1310,19 @@ struct Impl {
       k_shift<R><<<nb, 256, 0, h->stream>>>(h->g, (const R*)h->F[c], (R*)h->Fs[c], n, half);
       std::swap(h->F[c], h->Fs[c]);
     }
+    if (h->nwit > 0)
+      k_witness_shift<<<(unsigned)cdiv(h->nwit, 256), 256, 0, h->stream>>>(h->wit, h->nwit, n);
     HIPCHK(h, hipGetLastError());
     h->window_cells += n;
+    return BFPIC_OK;
+  }
+
+  // Witness electrons through the start-of-step fields (FP64).
+  static int witness_push(bfpic_ctx* h) {
+    WitK W{h->wit, h->nwit, {h->dt / h->dz, h->dt / h->dx, h->dt / h->dy}, -0.5 * h->dt};
+    k_witness_push<R, DIM, ORDER><<<(unsigned)cdiv(h->nwit, 256), 256, 0, h->stream>>>(
+        h->g, fields(h), W);
+    HIPCHK(h, hipGetLastError());
     return BFPIC_OK;
   }
 
@@ -1322,6 +1340,8 @@ struct Impl {
     h->laser_a0 = laser ? laser->a0 : 0.0;
     h->adj_ready = false;
     h->no_sort = false;
+    h->wit = nullptr;
+    h->nwit = 0;
     h->slots_bound = 0;
     h->tail_bound = 0;
     h->have_sort = false;
@@ -1676,6 +1696,24 @@ extern "C" int bfpic_axis_record(bfpic_ctx* h, int32_t frame, double* out, bfpic
   BFPIC_DISPATCH(h, I::axis_record(h, frame, out));
 }
 
+extern "C" int bfpic_witness_bind(bfpic_ctx* h, int32_t n, double* state_dev) {
+  if (!h || n < 0 || (n > 0 && !state_dev)) return BFPIC_ERR_ARG;
+  if (!h->inited) return fail(h, BFPIC_ERR_STATE, "witness bind before init");
+  h->wit = n > 0 ? state_dev : nullptr;
+  h->nwit = n;
+  return BFPIC_OK;
+}
+
+extern "C" int bfpic_witness_lab(bfpic_ctx* h, double* out_dev) {
+  if (!h || !out_dev) return BFPIC_ERR_ARG;
+  if (h->nwit == 0) return fail(h, BFPIC_ERR_STATE, "no witnesses bound");
+  k_witness_lab<<<(unsigned)cdiv(h->nwit, 256), 256, 0, h->stream>>>(
+      h->wit, h->nwit, (double)h->step * h->dt, (double)h->window_cells * h->dz, h->dz,
+      h->gamma_b, h->beta_b, out_dev);
+  if (hipGetLastError() != hipSuccess) return fail(h, BFPIC_ERR_HIP, "witness lab launch");
+  return BFPIC_OK;
+}
+
 extern "C" int bfpic_back_transform(bfpic_ctx* h, const double* rec, const double* tp,
                                     const double* z0, int64_t nrec, int32_t n, double dz,
                                     double gamma_b, double t0, double dt, int32_t nt,
@@ -1829,6 +1867,7 @@ extern "C" int bfpic_forward_loss(bfpic_ctx* h, int32_t nsteps, int32_t interval
                                   const bfpic_loss* loss, void* tape, int64_t tape_bytes,
                                   double* loss_out) {
   if (!h || !loss || !loss_out) return BFPIC_ERR_ARG;
+  if (h->nwit > 0) return fail(h, BFPIC_ERR_STATE, "taped runs do not carry witnesses");
   BFPIC_DISPATCH(h, I::forward_loss(h, nsteps, interval, loss, tape, tape_bytes, loss_out));
 }
 

@@ -207,3 +207,23 @@ def resolve_oracle(W):
               auto_window=1 if W.get("window") else 0, ions=1, load=W.get("load", 0))
     init = dict(n_lab=W["n_lab"], laser=O.make_laser(**r["laser"]))
     return kw, init
+
+
+# Witness beam: n test electrons in the wake behind the laser (the accelerated
+# beam whose energy gain against lab position is tracked), seeded: z uniform
+# over [0.15, 0.40] of the box, x (and y) uniform within nx/8 (ny/8) of the
+# axis, calculation-frame momentum u'_z uniform in [0.5, 3.0] and transverse
+# momenta normal with standard deviation 0.02.  Rows (z, x, y, u_z, u_x, u_y).
+def witness_beam(W, n, seed=None):
+    import numpy as np
+    rng = np.random.default_rng(W["seed"] + 7 if seed is None else seed)
+    nz, nx, ny = W["nz"], W["nx"], W.get("ny", 1)
+    out = np.zeros((n, 6))
+    out[:, 0] = rng.uniform(0.15 * nz, 0.40 * nz, n)
+    out[:, 1] = nx / 2 + rng.uniform(-nx / 8, nx / 8, n)
+    if W["dim"] == 3:
+        out[:, 2] = ny / 2 + rng.uniform(-ny / 8, ny / 8, n)
+    out[:, 3] = rng.uniform(0.5, 3.0, n)
+    out[:, 4] = rng.normal(0.0, 0.02, n)
+    out[:, 5] = rng.normal(0.0, 0.02, n)
+    return out
