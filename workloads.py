@@ -227,3 +227,40 @@ def witness_beam(W, n, seed=None):
     out[:, 4] = rng.normal(0.0, 0.02, n)
     out[:, 5] = rng.normal(0.0, 0.02, n)
     return out
+
+
+# Energy-gain scaling of the accelerated beam (the rescaled gain-versus-lab-
+# position curves of Fig. 4), downscaled to four lab densities n = 2e-3, 1e-3,
+# 5e-4, 2.5e-4 n_c, each in the frame gamma_b = gamma_g / 2 (gamma_g = n^-1/2):
+#   * a resonant plane-wave pulse: a0 = 1, Gaussian length L = sqrt(2) / k_p,
+#     uniform across a periodic slab of 16 transverse cells (no diffraction,
+#     as no guiding channel is modelled), its centre 4.5 boosted lengths
+#     (72 L / lambda0 cells) behind the front of the box;
+#   * 16 cells per boosted laser wavelength along z, transverse cells of
+#     16 lambda0 and Courant number 0.99 (c dt / dz' = 0.96 to 0.99), 4 pairs
+#     per cell, FP32 split, window at the boosted group velocity;
+#   * current filter: 8 binomial passes with compensation up to gamma_b = 16,
+#     16 passes above (wider filtering at the higher boosts);
+#   * box: the pulse's front gap plus 2.5 boosted wake periods (wake_cells);
+#     run: 2.4 dephasing lengths lambda_p^3 / lambda0^2 of lab travel;
+#   * witnesses: 256 on axis, evenly over 1.5 wake periods behind the pulse,
+#     at lab gamma 2 gamma_g.
+GAIN_DENSITIES = (2e-3, 1e-3, 5e-4, 2.5e-4)
+_GAIN_BOX = {2e-3: (1280, 1100, 286.5), 1e-3: (1536, 1550, 405.0),
+             5e-4: (2304, 2210, 572.6), 2.5e-4: (3072, 3160, 809.7)}  # nz, steps, wake_cells
+
+
+def gain_scaling(n):
+    nz, steps, wake = _GAIN_BOX[n]
+    kp = math.sqrt(n)
+    L_l0 = math.sqrt(2.0) / kp / LAMBDA0
+    gb = 0.5 / kp
+    W = small("boost13_2d", nz=nz, nx=16, ppc=4, gamma_b=gb, n_lab=n, dx_lambda0=16.0,
+              cfl=0.99, filter_passes=8 if gb <= 16.0 else 16, precision="fp32",
+              window="group", steps=steps,
+              laser=dict(a0=1.0, w0_lambda0=1.0e4, L_lambda0=L_l0, place="front",
+                         front_gap=4.5, collimated=1))
+    W["witness"] = dict(n=256, z_centre=nz - 72.0 * L_l0, wake_cells=wake,
+                        gamma_lab=2.0 / kp,
+                        dephasing=(2 * math.pi / kp) ** 3 / LAMBDA0 ** 2)
+    return W
