@@ -109,14 +109,17 @@ typedef struct bfpic_laser {
   int32_t images_z, images_x, images_y;
 } bfpic_laser;
 
-/* Field loss for the adjoint: L = (1 / nwin) sum over n = step_first ..
- * step_last of the mean of Ez^n over the node box i0..i1 (z rows of Ez,
- * inclusive) by j0..j1 (x columns, inclusive), where Ez^n is the field after
- * step n (steps counted from 1 after init) and nwin = step_last -
- * step_first + 1. */
+/* Loss for the adjoint: L = (1 / nwin) sum over n = step_first .. step_last
+ * of the mean of Ez^n over the node box i0..i1 (z rows of Ez, inclusive) by
+ * j0..j1 (x columns, inclusive), where Ez^n is the field after step n (steps
+ * counted from 1 after init) and nwin = step_last - step_first + 1; plus
+ * witness_weight times the mean lab-frame energy gamma_b (gamma' + beta_b
+ * u'_z) of the bound witness electrons after the last step (the
+ * witness-beam energy; witness_weight = 0: no such term). */
 typedef struct bfpic_loss {
   int32_t step_first, step_last;
   int32_t i0, i1, j0, j1;
+  double witness_weight;
 } bfpic_loss;
 
 typedef struct bfpic_sizes {
@@ -276,8 +279,9 @@ int bfpic_axis_spectrum(bfpic_ctx* h, const double* rec_dev, int64_t nrec, int32
  * z), applies the relativistic Boris rotation in FP64 with charge -1 and
  * moves it by v dt (x, y periodic; z wraps in a periodic box); a window
  * shift lowers every z by the shift.  Witnesses leave no mark on the
- * fields or the plasma.  n = 0 unbinds; init_boosted_plasma unbinds.  The
- * taped adjoint run refuses to run with witnesses bound (ERR_STATE).
+ * fields or the plasma.  n = 0 unbinds; init_boosted_plasma unbinds.  A
+ * taped adjoint run carries the bound witnesses (bind them before sizing
+ * its tape), and its loss may weigh their final lab energy.
  * ERR_ARG for n < 0 or a null array with n > 0, ERR_STATE before init.
  * Calls on one context are ordered on its stream. */
 int bfpic_witness_bind(bfpic_ctx* h, int32_t n, double* state_dev);
@@ -344,7 +348,10 @@ int bfpic_kernel_time(bfpic_ctx* h, int32_t cls, double* total_ms, int64_t* laun
  * stage's wake.  The reverse sweep runs the transposes of the Yee update, the
  * Mur boundary and the filter, and per particle the vector-Jacobian product of
  * gather, push, move and deposit, backwards over the steps, recomputing each
- * segment of `interval` steps from its checkpoint.  Runs without a moving
+ * segment of `interval` steps from its checkpoint.  Bound witness electrons
+ * are carried: their states are taped, and with a witness term in the loss
+ * their vector-Jacobian product (gather, push, move) is run backwards too,
+ * its gathered-field part added to the field adjoint.  Runs without a moving
  * window only (beta_window = 0, auto_window = 0); particles are not re-sorted
  * during a taped run.
  *
@@ -358,7 +365,9 @@ int bfpic_kernel_time(bfpic_ctx* h, int32_t cls, double* total_ms, int64_t* laun
  * pic_step_adjoint: reverse sweep of the last bfpic_forward_loss run:
  *   *dL_da0 (host) and dL_dn[m] (host array of nn >= number of knots, or >= 1
  *   for a uniform density).  Leaves the simulation state unspecified
- *   (re-initialise before stepping on).  Synchronises. */
+ *   (re-initialise before stepping on), witness states included.
+ *   ERR_STATE if the bound witnesses changed since the taped run.
+ *   Synchronises. */
 int bfpic_adjoint_tape_bytes(bfpic_ctx* h, int32_t nsteps, int32_t interval, int64_t* bytes);
 int bfpic_forward_loss(bfpic_ctx* h, int32_t nsteps, int32_t interval, const bfpic_loss* loss,
                        void* tape, int64_t tape_bytes, double* loss_out);

@@ -164,6 +164,7 @@ struct bfpic_ctx {
   bool adj_recompute = false;
   int adj_nsteps = 0, adj_interval = 0;
   int64_t adj_slots = 0;     // slots created by the taped run
+  int adj_nwit = 0;          // witnesses bound during the taped run
   bfpic_loss adj_loss{};
   std::vector<HostCkpt> ckpt;
   uint8_t* tape = nullptr;
@@ -1008,6 +1009,8 @@ struct Impl {
     R* lxi[2] = {};
     R* ldu[3] = {};
     double* lw = nullptr;
+    double* wl = nullptr;    // witness adjoints (n x 6)
+    double* wfin = nullptr;  // witness states after the last taped step
     int* idb = nullptr;     // birth id of every slot
     double* acc = nullptr;  // [0] loss, [1] <lambda_F, F(0)>, [2..] density gradient
     int64_t total = 0;
@@ -1017,8 +1020,9 @@ struct Impl {
     Tape T;
     const int64_t fb = align256(gbytes(h)), ib = align256(h->cap * 4),
                   rb = align256(h->cap * (int64_t)sizeof(R));
-    T.ckb = 6 * fb + ib + 6 * rb + 256;
-    T.sgb = 6 * fb + ib + 5 * rb + 256;
+    const int64_t wb = align256(h->nwit * 48);
+    T.ckb = 6 * fb + ib + 6 * rb + 256 + wb;
+    T.sgb = 6 * fb + ib + 5 * rb + 256 + wb;
     const int64_t ncp = cdiv(nsteps, interval);
     int64_t o = 0;
     auto take = [&](int64_t bytes) {
@@ -1036,6 +1040,8 @@ struct Impl {
     for (int a = 0; a < 2; a++) T.lxi[a] = (R*)take(rb);
     for (int a = 0; a < 3; a++) T.ldu[a] = (R*)take(rb);
     T.lw = (double*)take(h->cap * 8);
+    T.wl = (double*)take(h->nwit * 48);
+    T.wfin = (double*)take(h->nwit * 48);
     T.idb = (int*)take(ib);
     T.acc = (double*)take(8 * (2 + kMaxKnots));
     T.total = o;
@@ -1048,6 +1054,7 @@ struct Impl {
     return off_id(h) + align256(h->cap * 4) + k * align256(h->cap * (int64_t)sizeof(R));
   }
   static int64_t off_tail(bfpic_ctx* h, bool ck) { return off_r(h, ck ? 6 : 5); }
+  static int64_t off_wit(bfpic_ctx* h, bool ck) { return off_tail(h, ck) + 256; }
 
   static int copy(bfpic_ctx* h, void* dst, const void* src, int64_t bytes) {
     if (bytes > 0)
@@ -1081,6 +1088,9 @@ struct Impl {
     if (!rc)
       rc = save ? copy(h, b + off_tail(h, true), h->counts, 16 * 4)
                 : copy(h, h->counts, b + off_tail(h, true), 16 * 4);
+    if (!rc && h->nwit > 0)
+      rc = save ? copy(h, b + off_wit(h, true), h->wit, h->nwit * 48)
+                : copy(h, h->wit, b + off_wit(h, true), h->nwit * 48);
     if (rc) return rc;
     if (save) h->ckpt[k] = {h->step, h->window_cells, h->next_col, h->slots_bound, h->tail_bound,
                             h->cur};
@@ -1106,9 +1116,14 @@ struct Impl {
         rc = copy(h, b + (q == 0 ? off_id(h) : off_r(h, q - 1)), parts[q],
                   n * (q == 0 ? 4 : (int64_t)sizeof(R)));
       if (!rc) rc = copy(h, b + off_tail(h, false), h->counts, 4);
+      if (!rc && h->nwit > 0) rc = copy(h, b + off_wit(h, false), h->wit, h->nwit * 48);
       if (rc) return rc;
     }
     StepK<R> P = step_consts(h);
+    if (h->nwit > 0) {
+      rc = witness_push(h);
+      if (rc) return rc;
+    }
     rc = h->det ? particles_and_currents<true>(h, P) : particles_and_currents<false>(h, P);
     if (rc) return rc;
     rc = yee(h);
@@ -1146,6 +1161,8 @@ struct Impl {
     if (L->step_first < 1 || L->step_last > nsteps || L->step_first > L->step_last ||
         L->i0 < 0 || L->i1 > rz || L->i0 > L->i1 || L->j0 < 0 || L->j1 >= h->nx || L->j0 > L->j1)
       return fail(h, BFPIC_ERR_ARG, "loss window or box out of range");
+    if (!std::isfinite(L->witness_weight) || (L->witness_weight != 0.0 && h->nwit == 0))
+      return fail(h, BFPIC_ERR_ARG, "witness weight needs bound witnesses");
     Tape T = tape_map(h, (uint8_t*)tape, nsteps, interval);
     if (!tape || tape_bytes < T.total || ((uintptr_t)tape & 255))
       return fail(h, BFPIC_ERR_ARG, "tape too small or misaligned");
@@ -1169,6 +1186,16 @@ struct Impl {
       if (rc) return rc;
     }
     h->adj_slots = h->slots_bound;
+    h->adj_nwit = h->nwit;
+    if (h->nwit > 0) {
+      rc = copy(h, T.wfin, h->wit, h->nwit * 48);
+      if (rc) return rc;
+      if (L->witness_weight != 0.0) {
+        k_witness_energy<<<(unsigned)cdiv(h->nwit, 256), 256, 0, h->stream>>>(
+            h->wit, h->nwit, L->witness_weight / h->nwit, h->gamma_b, h->beta_b, T.acc);
+        HIPCHK(h, hipGetLastError());
+      }
+    }
     double v = 0.0;
     HIPCHK(h, hipMemcpyAsync(&v, T.acc, 8, hipMemcpyDeviceToHost, h->stream));
     HIPCHK(h, hipStreamSynchronize(h->stream));
@@ -1182,6 +1209,8 @@ struct Impl {
       return fail(h, BFPIC_ERR_UNSUPPORTED, "the adjoint is built for 2D runs");
     } else {
       if (!h->adj_ready) return fail(h, BFPIC_ERR_STATE, "no taped forward run");
+      if (h->nwit != h->adj_nwit)
+        return fail(h, BFPIC_ERR_STATE, "witnesses rebound since the taped run");
       const int nk = h->dens.nknots >= 2 ? h->dens.nknots : 1;
       if (nn < nk) return fail(h, BFPIC_ERR_ARG, "density gradient needs one value per knot");
       const int nsteps = h->adj_nsteps, interval = h->adj_interval;
@@ -1227,6 +1256,13 @@ struct Impl {
       for (int a = 0; a < 2; a++) A.lxi[a] = T.lxi[a];
       for (int a = 0; a < 3; a++) A.ldu[a] = T.ldu[a];
       A.lw = T.lw;
+      const bool wit_adj = h->nwit > 0 && L.witness_weight != 0.0;
+      const unsigned nbw = (unsigned)cdiv(std::max(h->nwit, 1), 256);
+      if (wit_adj) {
+        k_witness_energy_seed<<<nbw, 256, 0, h->stream>>>(
+            T.wfin, h->nwit, L.witness_weight / h->nwit, h->gamma_b, h->beta_b, T.wl);
+        HIPCHK(h, hipGetLastError());
+      }
       const int ncp = (int)cdiv(nsteps, interval);
       for (int k = ncp - 1; k >= 0; k--) {
         const int s0 = k * interval, s1 = std::min(nsteps, s0 + interval);
@@ -1269,6 +1305,11 @@ struct Impl {
           const unsigned nbq = (unsigned)std::max<int64_t>(1, std::min<int64_t>(
                                    cdiv(std::max<int64_t>(h->slots_bound, 1), 256), 4096));
           k_adj_particles<R, ORDER><<<nbq, 256, 0, h->stream>>>(P, F, TP, LJ, LF, A);
+          if (wit_adj) {
+            WitK W{(double*)(b + off_wit(h, false)), h->nwit,
+                   {h->dt / h->dz, h->dt / h->dx, h->dt / h->dy}, -0.5 * h->dt};
+            k_adj_witness<R, ORDER><<<nbw, 256, 0, h->stream>>>(g, F, W, T.wl, LF);
+          }
           HIPCHK(h, hipGetLastError());
         }
       }
@@ -1867,7 +1908,6 @@ extern "C" int bfpic_forward_loss(bfpic_ctx* h, int32_t nsteps, int32_t interval
                                   const bfpic_loss* loss, void* tape, int64_t tape_bytes,
                                   double* loss_out) {
   if (!h || !loss || !loss_out) return BFPIC_ERR_ARG;
-  if (h->nwit > 0) return fail(h, BFPIC_ERR_STATE, "taped runs do not carry witnesses");
   BFPIC_DISPATCH(h, I::forward_loss(h, nsteps, interval, loss, tape, tape_bytes, loss_out));
 }
 

@@ -22,6 +22,7 @@
 #include "device_common.hpp"
 #include "kernels_fields.hpp"
 #include "kernels_particles.hpp"
+#include "kernels_witness.hpp"
 
 namespace bfpic {
 
@@ -498,6 +499,80 @@ __global__ __launch_bounds__(256) void k_note_ids(const int* id, const int* coun
   if (p >= counts[0]) return;
   const int v = id[p];
   if (v >= 0) id_birth[p] = v;
+}
+
+// --------------------------------------------------------------------------
+// Witness electrons in the adjoint.  Loss term: sc times the sum over the
+// witnesses of the lab-frame energy after the last step,
+// gamma_lab = gb (gamma' + bb u'_z) (sc = weight / number of witnesses).
+// --------------------------------------------------------------------------
+__global__ __launch_bounds__(256) void k_witness_energy(const double* s, int n, double sc,
+                                                        double gb, double bb, double* acc) {
+  const int r = blockIdx.x * blockDim.x + threadIdx.x;
+  if (r >= n) return;
+  const double* w = s + (int64_t)r * 6;
+  const double gp = sqrt(1.0 + w[3] * w[3] + w[4] * w[4] + w[5] * w[5]);
+  atomicAdd(acc, sc * gb * (gp + bb * w[3]));
+}
+
+// Gradient of that term with respect to the final witness state (the
+// positions take none).
+__global__ __launch_bounds__(256) void k_witness_energy_seed(const double* s, int n, double sc,
+                                                             double gb, double bb, double* lam) {
+  const int r = blockIdx.x * blockDim.x + threadIdx.x;
+  if (r >= n) return;
+  const double* w = s + (int64_t)r * 6;
+  double* l = lam + (int64_t)r * 6;
+  const double ig = 1.0 / sqrt(1.0 + w[3] * w[3] + w[4] * w[4] + w[5] * w[5]);
+  l[0] = 0.0;
+  l[1] = 0.0;
+  l[2] = 0.0;
+  l[3] = sc * gb * (w[3] * ig + bb);
+  l[4] = sc * gb * w[4] * ig;
+  l[5] = sc * gb * w[5] * ig;
+}
+
+// One reverse witness step (2D): the vector-Jacobian product of
+// (state, E_p, B_p) -> state' with the adjoint of state' (lam, overwritten
+// with that of state), formed with dual numbers over the 12 input
+// directions; the E_p, B_p directions go to the field adjoint lf through the
+// gather's transpose.  W.s holds the taped start-of-step states.
+template <typename R, int ORDER>
+__global__ __launch_bounds__(256) void k_adj_witness(Geo g, Fields<R> F, WitK W, double* lam,
+                                                     Fields<R> LF) {
+  using D = Dual<double>;
+  const int r = blockIdx.x * blockDim.x + threadIdx.x;
+  if (r >= W.n) return;
+  const double* s0 = W.s + (int64_t)r * 6;
+  double* l = lam + (int64_t)r * 6;
+  double lo[6], gdir[12];
+#pragma unroll
+  for (int a = 0; a < 6; a++) lo[a] = l[a];
+  const WideFetch<R, D> f{(const R* const*)F.F, g};
+#pragma unroll 1
+  for (int dir = 0; dir < 12; dir++) {
+    D v[6];
+#pragma unroll
+    for (int a = 0; a < 6; a++) v[a] = D(s0[a]);
+    if (dir < 6) v[dir].d = 1.0;
+    witness_advance<D, 2, ORDER>(f, g, W, v, SeedFields<double>{dir});
+    double acc = 0.0;
+#pragma unroll
+    for (int a = 0; a < 6; a++) acc += lo[a] * v[a].d;
+    gdir[dir] = acc;
+  }
+#pragma unroll
+  for (int a = 0; a < 6; a++) l[a] = gdir[a];
+  Pos<R> p;
+  p.c[0] = (int)floor(s0[0]);
+  p.o[0] = (R)(s0[0] - (double)p.c[0]);
+  p.c[1] = (int)floor(s0[1]);
+  p.o[1] = (R)(s0[1] - (double)p.c[1]);
+  p.c[2] = 0;
+  p.o[2] = (R)0;
+  const R gE[3] = {(R)gdir[6], (R)gdir[7], (R)gdir[8]};
+  const R gB[3] = {(R)gdir[9], (R)gdir[10], (R)gdir[11]};
+  gather_transpose<R, ORDER>(LF.F, g, p, gE, gB);
 }
 
 }  // namespace bfpic

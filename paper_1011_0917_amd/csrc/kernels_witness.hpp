@@ -12,19 +12,20 @@
 
 namespace bfpic {
 
-// Field fetch for the witness gather: the working-precision grid read as FP64.
-// Nodes exist on rows 0..row_hi of each component (open z); periodic z wraps.
-template <typename R>
+// Field fetch for the witness gather: the working-precision grid read as FP64
+// (O = double, or a dual number of it).  Nodes exist on rows 0..row_hi of
+// each component (open z); periodic z wraps.
+template <typename R, typename O = double>
 struct WideFetch {
   const R* const* F;
   Geo g;
-  __device__ __forceinline__ double operator()(int comp, int i, int j, int k) const {
+  __device__ __forceinline__ O operator()(int comp, int i, int j, int k) const {
     const int half_z = comp == 2 || comp == 3 || comp == 4;
     if (g.periodic_z) i = wrapi(i, g.nz);
-    else if (i < 0 || i > row_hi(g, half_z)) return 0.0;
+    else if (i < 0 || i > row_hi(g, half_z)) return O(0.0);
     j = wrapi(j, g.nx);
     k = g.ny > 1 ? wrapi(k, g.ny) : 0;
-    return (double)F[comp][((int64_t)(i + kGuard) * g.nx + j) * g.ny + k];
+    return O((double)F[comp][((int64_t)(i + kGuard) * g.nx + j) * g.ny + k]);
   }
 };
 
@@ -37,50 +38,55 @@ struct WitK {
   double qdt2;    // q dt / 2, q = -1
 };
 
-// One step: gather E, B at the start-of-step position with the deposit's
-// shape, relativistic Boris rotation (Boris 1970) of the full momentum, move
-// by v dt.  x and y are periodic; z wraps in a periodic box.
-template <typename R, int DIM, int ORDER>
-__global__ __launch_bounds__(256) void k_witness_push(Geo g, Fields<R> F, WitK W) {
-  const int r = blockIdx.x * blockDim.x + threadIdx.x;
-  if (r >= W.n) return;
-  double* s = W.s + (int64_t)r * 6;
-  double z = s[0], x = s[1], y = s[2];
+struct NoSeed {
+  template <typename T>
+  __device__ __forceinline__ void operator()(T*, T*) const {}
+};
+
+// One step of one witness, state s updated in place: gather E, B at the
+// start-of-step position with the deposit's shape, relativistic Boris
+// rotation (Boris 1970) of the full momentum, move by v dt.  x and y are
+// periodic; z wraps in a periodic box.  T is double, or a dual number for the
+// adjoint, whose `seed` marks one gathered component as the direction.
+template <typename T, int DIM, int ORDER, class Fch, class Seed>
+__device__ __forceinline__ void witness_advance(const Fch& f, const Geo& g, const WitK& W, T s[6],
+                                                const Seed& seed) {
+  T z = s[0], x = s[1], y = s[2];
   // vectors in (x, y, z) order
-  double u[3] = {s[4], s[5], s[3]};
-  Pos<double> p;
+  T u[3] = {s[4], s[5], s[3]};
+  Pos<T> p;
   p.c[0] = (int)floor(z);
-  p.o[0] = z - (double)p.c[0];
+  p.o[0] = z - T((double)p.c[0]);
   p.c[1] = (int)floor(x);
-  p.o[1] = x - (double)p.c[1];
+  p.o[1] = x - T((double)p.c[1]);
   p.c[2] = DIM == 3 ? (int)floor(y) : 0;
-  p.o[2] = DIM == 3 ? y - (double)p.c[2] : 0.0;
+  p.o[2] = DIM == 3 ? y - T((double)p.c[2]) : T(0.0);
   const int bc[3] = {p.c[0], p.c[1], p.c[2]};
-  double E[3], B[3];
-  WideFetch<R> f{(const R* const*)F.F, g};
-  gather_nodes<double, DIM, ORDER>(f, bc, p, E, B);
-  const double h = W.qdt2;
-  double m[3], t[3];
+  T E[3], B[3];
+  gather_nodes<T, DIM, ORDER>(f, bc, p, E, B);
+  seed(E, B);
+  const T h = T(W.qdt2);
+  T m[3], t[3];
 #pragma unroll
   for (int a = 0; a < 3; a++) m[a] = u[a] + h * E[a];
-  const double gm = sqrt(1.0 + m[0] * m[0] + m[1] * m[1] + m[2] * m[2]);
+  const T gm = sqrt(T(1.0) + m[0] * m[0] + m[1] * m[1] + m[2] * m[2]);
 #pragma unroll
   for (int a = 0; a < 3; a++) t[a] = h * B[a] / gm;
-  const double sf = 2.0 / (1.0 + t[0] * t[0] + t[1] * t[1] + t[2] * t[2]);
-  const double q0 = m[0] + (m[1] * t[2] - m[2] * t[1]);
-  const double q1 = m[1] + (m[2] * t[0] - m[0] * t[2]);
-  const double q2 = m[2] + (m[0] * t[1] - m[1] * t[0]);
+  const T sf = T(2.0) / (T(1.0) + t[0] * t[0] + t[1] * t[1] + t[2] * t[2]);
+  const T q0 = m[0] + (m[1] * t[2] - m[2] * t[1]);
+  const T q1 = m[1] + (m[2] * t[0] - m[0] * t[2]);
+  const T q2 = m[2] + (m[0] * t[1] - m[1] * t[0]);
   u[0] = m[0] + sf * (q1 * t[2] - q2 * t[1]) + h * E[0];
   u[1] = m[1] + sf * (q2 * t[0] - q0 * t[2]) + h * E[1];
   u[2] = m[2] + sf * (q0 * t[1] - q1 * t[0]) + h * E[2];
-  const double ig = 1.0 / sqrt(1.0 + u[0] * u[0] + u[1] * u[1] + u[2] * u[2]);
-  z += u[2] * ig * W.dtd[0];
-  if (g.periodic_z) z -= (double)g.nz * floor(z / (double)g.nz);
-  x += u[0] * ig * W.dtd[1];
-  x -= (double)g.nx * floor(x / (double)g.nx);
+  const T ig = T(1.0) / sqrt(T(1.0) + u[0] * u[0] + u[1] * u[1] + u[2] * u[2]);
+  z += u[2] * ig * T(W.dtd[0]);
+  if (g.periodic_z) z -= T((double)g.nz) * floor(z / T((double)g.nz));
+  x += u[0] * ig * T(W.dtd[1]);
+  x -= T((double)g.nx) * floor(x / T((double)g.nx));
   if (DIM == 3) {
-    y += u[1] * ig * W.dtd[2];
-    y -= (double)g.ny * floor(y / (double)g.ny);
+    y += u[1] * ig * T(W.dtd[2]);
+    y -= T((double)g.ny) * floor(y / T((double)g.ny));
   }
   s[0] = z;
   s[1] = x;
@@ -88,6 +94,19 @@ __global__ __launch_bounds__(256) void k_witness_push(Geo g, Fields<R> F, WitK W
   s[3] = u[2];
   s[4] = u[0];
   s[5] = u[1];
+}
+
+template <typename R, int DIM, int ORDER>
+__global__ __launch_bounds__(256) void k_witness_push(Geo g, Fields<R> F, WitK W) {
+  const int r = blockIdx.x * blockDim.x + threadIdx.x;
+  if (r >= W.n) return;
+  double* s = W.s + (int64_t)r * 6;
+  double v[6];
+#pragma unroll
+  for (int a = 0; a < 6; a++) v[a] = s[a];
+  witness_advance<double, DIM, ORDER>(WideFetch<R>{(const R* const*)F.F, g}, g, W, v, NoSeed{});
+#pragma unroll
+  for (int a = 0; a < 6; a++) s[a] = v[a];
 }
 
 // The window moved forward by n cells: positions relative to it drop by n.

@@ -188,8 +188,8 @@ def test_witness_error_paths(P):
     Wg = torch.zeros((2, 6), dtype=torch.float64, device=sim.device)
     Wg[:, 0] = 20.0
     sim.witness_bind(Wg)
-    with pytest.raises(P.BfpicError):                         # taped runs refuse witnesses
-        sim.forward_loss(2, 1, 1, 2, (0, 4, 0, 4))
+    with pytest.raises(P.BfpicError):                         # a weight that is not finite
+        sim.forward_loss(2, 1, 1, 2, (0, 4, 0, 4), witness_weight=float("nan"))
     sim.witness_bind(None)
     assert L.bfpic_witness_lab(sim.h, dummy) != 0
     sim.close()
