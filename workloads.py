@@ -264,3 +264,29 @@ def gain_scaling(n):
                         gamma_lab=2.0 / kp,
                         dephasing=(2 * math.pi / kp) ** 3 / LAMBDA0 ** 2)
     return W
+
+
+# Laser entering a plasma in boosted frames approaching the group-velocity
+# frame (the hyperbolic rotation of the laser's phase fronts, Fig. 2): lab
+# density 1e-3 n_c starting 4 cells ahead of the box (knots: zero up to the
+# lab position gamma_b dz (nz + 4), rising to n over 8 cells), gamma_b = 0.5,
+# 0.7, 0.85 gamma_g; a plane-wave pulse (a0 = 0.1, L = 10 lambda0, uniform
+# across a periodic 16-cell slab) at the box centre, in vacuum at t' = 0;
+# 8192 cells along z at 16 per boosted vacuum wavelength, transverse cells of
+# 16 lambda0, Courant number 0.99, current filter as in the energy-gain
+# recipe (8 passes with compensation up to gamma_b = 16, 16 above), no
+# window; the run lasts until the plasma has covered the pulse (0.37 box
+# lengths of light travel).
+BEATING_RATIOS = (0.5, 0.7, 0.85)
+
+
+def time_beating(ratio, n=1e-3):
+    gb = ratio / math.sqrt(n)
+    W = small("boost13_2d", nz=8192, nx=16, ppc=4, gamma_b=gb, n_lab=n, dx_lambda0=16.0,
+              cfl=0.99, filter_passes=8 if gb <= 16.0 else 16, precision="fp32", window=None,
+              laser=dict(a0=0.1, w0_lambda0=1.0e4, L_lambda0=10.0, place="box_center",
+                         collimated=1))
+    W["plasma_start_cells"] = 4
+    W["ramp_cells"] = 8
+    W["travel_boxes"] = 0.37
+    return W
