@@ -47,7 +47,8 @@ class Config(C.Structure):
 class Density(C.Structure):
     _fields_ = [("n_uniform", C.c_double), ("nknots", C.c_int32),
                 ("z_lab", C.POINTER(C.c_double)), ("n", C.POINTER(C.c_double)),
-                ("du", C.c_double * 3)]
+                ("du", C.c_double * 3), ("channel_depth", C.c_double),
+                ("channel_radius", C.c_double)]
 
 
 class Laser(C.Structure):
@@ -187,13 +188,15 @@ class Sim:
             self.h = None
 
     def init(self, n_uniform=None, knots_z=None, knots_n=None, laser: Laser | None = None,
-             fill=True, du=(0.0, 0.0, 0.0)):
+             fill=True, du=(0.0, 0.0, 0.0), channel=None):
         dens = None
         self._keep = []
         if n_uniform is not None or knots_z is not None:
             dens = Density()
             dens.n_uniform = 0.0 if n_uniform is None else float(n_uniform)
             dens.du[:] = [float(v) for v in du]
+            if channel is not None:
+                dens.channel_depth, dens.channel_radius = (float(v) for v in channel)
             if knots_z is not None:
                 kz = np.ascontiguousarray(knots_z, dtype=np.float64)
                 kn = np.ascontiguousarray(knots_n, dtype=np.float64)

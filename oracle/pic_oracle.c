@@ -62,6 +62,7 @@ struct orc_sim {
   double* kz;
   double* kn;
   double du0[3];
+  double ch_depth, ch_radius;
 };
 
 /* ------------------------------------------------------------------------ */
@@ -685,6 +686,19 @@ static double lab_density(const orc_sim* s, double zl) {
   return s->kn[s->nknots - 1];
 }
 
+/* Plasma channel: the lab density times 1 + depth r^2 / radius^2, r the
+ * distance of the birth position from the laser axis (the box centre, x in
+ * 2D, x and y in 3D).  A parabolic channel of depth dn / n at r = w0 guides a
+ * Gaussian beam of waist w0 when dn / n_c = 4 / (k0 w0)^2 (paraxial mode of a
+ * parabolic index profile, applied per transverse axis). */
+static double channel_factor(const orc_sim* s, double x, double y) {
+  const orc_config* c = &s->c;
+  if (s->ch_depth == 0.0) return 1.0;
+  double dxa = x * c->dx - 0.5 * c->nx * c->dx;
+  double dya = c->dim == 3 ? y * c->dy - 0.5 * c->ny * c->dy : 0.0;
+  return 1.0 + s->ch_depth * (dxa * dxa + dya * dya) / (s->ch_radius * s->ch_radius);
+}
+
 static void grow(orc_sim* s, int64_t need) {
   if (need <= s->cap) return;
   int64_t nc = s->cap ? s->cap : 1024;
@@ -729,8 +743,8 @@ static void add_column(orc_sim* s, int64_t k, double D) {
           ry = d3 ? orc_cell_offset(c->seed, k, l, j, q, 2, c->nx, s->nyy, c->ppc) : 0.0;
         }
         double zl = c->gamma_b * ((double)k + rz) * c->dz;
-        double w = c->gamma_b * lab_density(s, zl) * dV / (double)c->ppc;
         double z = ((double)k + rz) - D, x = (double)j + rx, y = (double)l + ry;
+        double w = c->gamma_b * lab_density(s, zl) * channel_factor(s, x, y) * dV / (double)c->ppc;
         int64_t id = ((k * s->nyy + l) * c->nx + j) * c->ppc + q;
         orc_add_pair(s, z, x, y, ub + s->du0[2], s->du0[0], s->du0[1], z, x, y, w, id);
       }
@@ -787,7 +801,13 @@ int orc_init(orc_sim* s, const orc_density* dens, const orc_laser* laser, int32_
   s->kz = s->kn = NULL;
   s->nknots = 0;
   s->du0[0] = s->du0[1] = s->du0[2] = 0.0;
+  s->ch_depth = 0.0;
+  s->ch_radius = 1.0;
   if (dens) {
+    if (!(dens->channel_depth >= 0.0) || (dens->channel_depth > 0.0 && !(dens->channel_radius > 0.0)))
+      return -1;
+    s->ch_depth = dens->channel_depth;
+    if (dens->channel_depth > 0.0) s->ch_radius = dens->channel_radius;
     for (int a = 0; a < 3; a++) s->du0[a] = dens->du[a];
     s->n_uniform = dens->n_uniform;
     s->nknots = dens->nknots;

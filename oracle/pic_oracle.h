@@ -67,6 +67,8 @@ typedef struct orc_density {
   const double* z_lab;       /* knot positions, lab frame [c/omega0], increasing */
   const double* n;           /* knot densities [n_crit] */
   double du[3];              /* momentum added to every electron at birth (x, y, z) */
+  double channel_depth;      /* transverse profile 1 + depth r^2 / radius^2 about the */
+  double channel_radius;     /* laser axis (a plasma channel); depth 0: none          */
 } orc_density;
 
 typedef struct orc_laser {
