@@ -87,13 +87,21 @@ typedef struct bfpic_config {
 /* Lab-frame plasma density.  nknots == 0: n_uniform everywhere.  nknots >= 2:
  * piecewise linear through (z_lab[m], n[m]) (host arrays, increasing z_lab),
  * zero outside.  du is a uniform momentum added to every electron at birth
- * (x, y, z order; zero for a cold plasma). */
+ * (x, y, z order; zero for a cold plasma).  Plasma channel (the guiding
+ * channel of the 10 GeV stage in the paper's last figure): the density is
+ * multiplied by 1 + channel_depth r^2 / channel_radius^2, r the transverse
+ * distance of the birth position from the laser axis (the box centre; x in
+ * 2D, x and y in 3D).  channel_depth = 0: no channel; a Gaussian beam of
+ * waist w0 is guided when the density rise at r = w0 is 4 / (k0 w0)^2 n_c.
+ * ERR_ARG for channel_depth < 0, or > 0 with channel_radius <= 0. */
 typedef struct bfpic_density {
   double n_uniform;
   int32_t nknots;
   const double* z_lab;
   const double* n;
   double du[3];
+  double channel_depth;
+  double channel_radius;
 } bfpic_density;
 
 /* Lab-frame laser: y-polarised paraxial Gaussian pulse along +z, given by its

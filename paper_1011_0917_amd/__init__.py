@@ -42,7 +42,8 @@ class Config(C.Structure):
 class Density(C.Structure):
     _fields_ = [("n_uniform", C.c_double), ("nknots", C.c_int32),
                 ("z_lab", C.POINTER(C.c_double)), ("n", C.POINTER(C.c_double)),
-                ("du", C.c_double * 3)]
+                ("du", C.c_double * 3), ("channel_depth", C.c_double),
+                ("channel_radius", C.c_double)]
 
 
 class Laser(C.Structure):
@@ -218,12 +219,14 @@ class Simulation:
 
     # ---- the four entry points of the method ----
     def init_boosted_plasma(self, gamma_boost, n_uniform=None, knots_z=None, knots_n=None,
-                            du=(0.0, 0.0, 0.0), laser: Laser | None = None):
+                            du=(0.0, 0.0, 0.0), laser: Laser | None = None, channel=None):
         dens = None
         if n_uniform is not None or knots_z is not None:
             dens = Density()
             dens.n_uniform = 0.0 if n_uniform is None else float(n_uniform)
             dens.du[:] = [float(v) for v in du]
+            if channel is not None:  # (depth, radius): n (1 + depth r^2 / radius^2)
+                dens.channel_depth, dens.channel_radius = (float(v) for v in channel)
             self._knots = None
             if knots_z is not None:
                 kz = (C.c_double * len(knots_z))(*knots_z)

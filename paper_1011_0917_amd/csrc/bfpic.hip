@@ -630,7 +630,9 @@ struct Impl {
     const DensityK& D = h->dens;
     double nmax = std::fabs(D.n_uniform);
     for (int m = 0; m < D.nknots; m++) nmax = std::max(nmax, std::fabs(D.kn[m]));
-    const double wmax = D.gamma_b * nmax * D.dV_over_ppc;
+    // the channel's largest factor: the box corner, half a box from the axis
+    const double rmax2 = D.xa * D.xa + D.ya * D.ya;
+    const double wmax = D.gamma_b * nmax * (1.0 + D.ch_k * rmax2) * D.dV_over_ppc;
     double k;
     if (DIM == 2)
       k = std::max({1.0 / (h->dx * h->dt), 1.0 / (h->dz * h->dt), 1.0 / (h->dz * h->dx)});
@@ -1451,6 +1453,16 @@ struct Impl {
       D.dz = h->dz;
       D.dV_over_ppc = h->dz * h->dx * (DIM == 3 ? h->dy : 1.0) / h->cfg.ppc;
       for (int a = 0; a < 3; a++) D.du0[a] = d->du[a];
+      if (!(d->channel_depth >= 0.0) || !std::isfinite(d->channel_depth) ||
+          (d->channel_depth > 0.0 && !(d->channel_radius > 0.0)))
+        return fail(h, BFPIC_ERR_ARG, "channel: depth >= 0, radius > 0");
+      D.ch_k = d->channel_depth > 0.0
+                   ? d->channel_depth / (d->channel_radius * d->channel_radius) : 0.0;
+      D.dx = h->dx;
+      D.dy = h->dy;
+      D.xa = 0.5 * h->nx * h->dx;
+      D.ya = DIM == 3 ? 0.5 * h->ny * h->dy : 0.0;
+      D.dim3 = DIM == 3;
       set_fixed_scale(h);
       int64_t count = (int64_t)h->nz * h->nx * h->ny * h->cfg.ppc;
       if (count > h->cap)

@@ -470,12 +470,12 @@ __global__ __launch_bounds__(256) void k_knot_grad(const int* id_birth, const do
        p += (int64_t)gridDim.x * blockDim.x) {
     const int id = id_birth[p];
     if (id < 0) continue;
-    const double c = lw[p] * d.gamma_b * d.dV_over_ppc;
+    const Birth b = decode_id(L, id);
+    const double c = lw[p] * d.gamma_b * d.dV_over_ppc * birth_channel(d, L, id, b);
     if (d.nknots < 2) {
       atomicAdd(&sh[0], c);
       continue;
     }
-    const Birth b = decode_id(L, id);
     const double rz = (double)birth_offset<double>(L, id, 0);
     const double zl = d.gamma_b * ((double)b.k + rz) * d.dz;
     if (zl < d.kz[0] || zl > d.kz[d.nknots - 1]) continue;

@@ -1026,7 +1026,8 @@ __global__ __launch_bounds__(NT) void k_gpd_tiled(StepK<R> P, Fields<R> F, PSoA<
 // --------------------------------------------------------------------------
 // Plasma creation: lattice columns [k0, k0 + ncols) -> slots starting at
 // counts[0] (the current slot count); each slot gets id, xi = 0, du = du0
-// and the weight gamma_b n_lab(z_lab) dV / ppc at z_lab = gamma_b (k + r_z) dz.
+// and the weight gamma_b n_lab(z_lab) c(x, y) dV / ppc at z_lab = gamma_b (k + r_z) dz,
+// with c the plasma channel's transverse factor.
 // --------------------------------------------------------------------------
 struct DensityK {
   double n_uniform;
@@ -1034,7 +1035,27 @@ struct DensityK {
   double kz[32], kn[32];
   double gamma_b, dz, dV_over_ppc;
   double du0[3];
+  // channel: 1 + ch_k ((x dx - xa)^2 + (y dy - ya)^2), ch_k = depth / radius^2
+  double ch_k, dx, dy, xa, ya;
+  int dim3;
 };
+
+// Transverse factor of the plasma channel at the birth position (cells).
+__device__ __forceinline__ double channel_factor(const DensityK& d, double x, double y) {
+  if (d.ch_k == 0.0) return 1.0;
+  const double a = x * d.dx - d.xa;
+  const double b = d.dim3 ? y * d.dy - d.ya : 0.0;
+  return 1.0 + d.ch_k * (a * a + b * b);
+}
+
+// Channel factor of a lattice birth.
+__device__ __forceinline__ double birth_channel(const DensityK& d, const LatticeP& L, int id,
+                                                const Birth& b) {
+  if (d.ch_k == 0.0) return 1.0;
+  const double x = (double)b.j + (double)birth_offset<double>(L, id, 1);
+  const double y = d.dim3 ? (double)b.l + (double)birth_offset<double>(L, id, 2) : 0.0;
+  return channel_factor(d, x, y);
+}
 
 __device__ __forceinline__ double lab_density(const DensityK& d, double zl) {
   if (d.nknots < 2) return d.n_uniform;
@@ -1059,7 +1080,7 @@ __global__ __launch_bounds__(256) void k_create(PSoA<R> S, LatticeP L, DensityK 
   Birth b = decode_id(L, id);
   double rz = (double)birth_offset<double>(L, id, 0);
   double zl = d.gamma_b * ((double)b.k + rz) * d.dz;
-  double w = d.gamma_b * lab_density(d, zl) * d.dV_over_ppc;
+  double w = d.gamma_b * lab_density(d, zl) * birth_channel(d, L, id, b) * d.dV_over_ppc;
   S.id[p] = id;
   S.xi[0][p] = (R)0;
   S.xi[1][p] = (R)0;

@@ -290,3 +290,24 @@ def time_beating(ratio, n=1e-3):
     W["ramp_cells"] = 8
     W["travel_boxes"] = 0.37
     return W
+
+
+# Laser guiding in a plasma channel, lab frame: a0 = 0.1 (linear), waist
+# w0 = 8 lambda0 at the pulse centre, L = 4 lambda0, on-axis density 1e-3 n_c;
+# 512 x 256 cells of lambda0/16 x lambda0/4 (32 x 64 lambda0, eight waists
+# across), 2 pairs per cell, FP32, window at the group velocity, 1.5 Rayleigh
+# lengths (pi w0^2 / lambda0) of propagation.  The matched channel's depth is
+# the density rise 4 / (k0 w0)^2 n_c at r = w0, relative to the axis density.
+def channel_guiding(matched=True):
+    w0 = 8.0 * LAMBDA0
+    n0 = 1e-3
+    W = dict(
+        dim=2, nz=512, nx=256, ny=1, gamma_b=1.0, dz_lambda0=1 / 16, dx_lambda0=0.25,
+        cfl=0.95, n_lab=n0, ppc=2, order=1, filter_passes=1, filter_compensate=0, zbc="mur",
+        precision="fp32", steps=None, seed=1017, window="group",
+        laser=dict(a0=0.1, w0_lambda0=8.0, L_lambda0=4.0, place="front", front_gap=4.5,
+                   collimated=1))
+    W["channel"] = (4.0 / w0 ** 2 / n0, w0) if matched else None
+    W["rayleigh"] = math.pi * w0 ** 2 / LAMBDA0
+    W["propagation_rayleigh"] = 1.5
+    return W
