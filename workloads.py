@@ -280,12 +280,15 @@ def gain_scaling(n):
 BEATING_RATIOS = (0.5, 0.7, 0.85)
 
 
-def time_beating(ratio, n=1e-3):
+def time_beating(ratio, n=1e-3, passes=None, compensate=1):
     gb = ratio / math.sqrt(n)
     W = small("boost13_2d", nz=8192, nx=16, ppc=4, gamma_b=gb, n_lab=n, dx_lambda0=16.0,
               cfl=0.99, filter_passes=8 if gb <= 16.0 else 16, precision="fp32", window=None,
               laser=dict(a0=0.1, w0_lambda0=1.0e4, L_lambda0=10.0, place="box_center",
                          collimated=1))
+    if passes is not None:
+        W["filter_passes"] = passes
+        W["filter_compensate"] = compensate
     W["plasma_start_cells"] = 4
     W["ramp_cells"] = 8
     W["travel_boxes"] = 0.37
