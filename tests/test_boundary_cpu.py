@@ -93,3 +93,42 @@ def test_workloads_resolve_identically_on_both_sides(P):
         assert cfg.beta_window == pytest.approx(kw["beta_window"], rel=1e-13, abs=1e-16)
         assert P.yee_dt(cfg.dim, cfg.dz, cfg.dx, cfg.dy, cfg.cfl) == pytest.approx(kw["dt"], rel=1e-15)
         assert init["laser"].z_center == pytest.approx(oinit["laser"].z_center, rel=1e-14)
+
+
+STRUCTS = {"Config": "bfpic_config", "Density": "bfpic_density", "Laser": "bfpic_laser",
+           "Loss": "bfpic_loss", "Sizes": "bfpic_sizes", "Diag": "bfpic_diag",
+           "AxisMeta": "bfpic_axis_meta"}
+
+
+def _check_layouts(mod, structs, header_dir, header, tmp_path):
+    """Size and field offsets of each ctypes structure of `mod` against its C
+    struct, read from a program that gcc compiles against the header."""
+    import subprocess
+    lines = ['#include <stdio.h>', '#include <stddef.h>', f'#include "{header}"',
+             "int main(void) {"]
+    for py, c in structs.items():
+        lines.append(f'  printf("{py} size %zu\\n", sizeof({c}));')
+        for f, _ in getattr(mod, py)._fields_:
+            lines.append(f'  printf("{py} {f} %zu\\n", offsetof({c}, {f}));')
+    lines += ["  return 0;", "}"]
+    src = tmp_path / "layout.c"
+    src.write_text("\n".join(lines) + "\n")
+    exe = tmp_path / "layout"
+    subprocess.run(["gcc", "-std=c11", "-I", header_dir, "-o", str(exe), str(src)], check=True)
+    out = subprocess.run([str(exe)], check=True, capture_output=True, text=True).stdout
+    assert out
+    for line in out.splitlines():
+        py, field, value = line.split()
+        cls = getattr(mod, py)
+        want = ctypes.sizeof(cls) if field == "size" else getattr(cls, field).offset
+        assert int(value) == want, (py, field, value, want)
+
+
+def test_binding_structs_match_the_header(P, tmp_path):
+    _check_layouts(P, STRUCTS, os.path.join(ROOT, "include"), "bfpic.h", tmp_path)
+
+
+def test_oracle_structs_match_its_header(tmp_path):
+    structs = {"Config": "orc_config", "Density": "orc_density", "Laser": "orc_laser",
+               "Diag": "orc_diag"}
+    _check_layouts(O, structs, os.path.join(ROOT, "oracle"), "pic_oracle.h", tmp_path)
