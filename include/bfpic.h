@@ -303,6 +303,34 @@ int bfpic_witness_bind(bfpic_ctx* h, int32_t n, double* state_dev);
  * Asynchronous. */
 int bfpic_witness_lab(bfpic_ctx* h, double* out_dev);
 
+/* ---- checkpoint and resume ---- */
+
+/* Device bytes of a state blob of the present state (call right before
+ * pic_save: the size follows the number of particle slots in use).
+ * ERR_STATE before init. */
+int bfpic_state_bytes(bfpic_ctx* h, int64_t* bytes);
+
+/* Writes the simulation state into blob_dev, a caller-owned device buffer of
+ * at least bfpic_state_bytes bytes, 256-byte aligned: a header (the
+ * configuration, the step and window schedule, the injection cursor, the
+ * boost and density parameters, the fixed-point scale), then E and B with
+ * their guard rows, the particle slots in use and the device counters.
+ * Currents and scratch are rebuilt within each step and are not saved, nor
+ * are bound witnesses (caller state).  The blob may be copied to the host
+ * and back unchanged.  ERR_ARG for a short or misaligned blob, ERR_STATE
+ * before init.  Synchronises. */
+int pic_save(bfpic_ctx* h, void* blob_dev, int64_t blob_bytes);
+
+/* Restores a state written by pic_save into a context created with the same
+ * configuration (grid, spacings, CFL, shapes, filter, precision,
+ * deterministic mode, boundaries, loading, seed and window; capacity and
+ * sort interval may differ), then re-sorts the particles into tiles.  The
+ * run continues from the saved step; in deterministic mode it continues
+ * bitwise as the uninterrupted run would.  ERR_ARG for a blob that is not a
+ * state, comes from another configuration or is shorter than its header
+ * says, ERR_CAPACITY if its slots exceed the capacity.  Synchronises. */
+int pic_load(bfpic_ctx* h, const void* blob_dev, int64_t blob_bytes);
+
 /* ---- state access (tests and tools; asynchronous unless stated) ---- */
 
 /* Copies component comp at integer time (domain rows 0..nz; row nz is zero

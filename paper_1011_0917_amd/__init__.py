@@ -94,7 +94,8 @@ EXPORTS = ["bfpic_beta", "bfpic_drift_u", "bfpic_group_gamma", "bfpic_boosted_gr
            "bfpic_last_sort", "bfpic_tile_shape", "bfpic_kernel_timing", "bfpic_kernel_time",
            "bfpic_adjoint_tape_bytes", "bfpic_forward_loss", "pic_step_adjoint",
            "bfpic_axis_record", "bfpic_back_transform", "bfpic_axis_spectrum",
-           "bfpic_witness_bind", "bfpic_witness_lab"]
+           "bfpic_witness_bind", "bfpic_witness_lab", "bfpic_state_bytes", "pic_save",
+           "pic_load"]
 
 
 def lib():
@@ -138,6 +139,8 @@ def lib():
         "bfpic_axis_spectrum": (C.c_int, [p, p, i64, i32, i32, p]),
         "bfpic_witness_bind": (C.c_int, [p, i32, p]),
         "bfpic_witness_lab": (C.c_int, [p, p]),
+        "bfpic_state_bytes": (C.c_int, [p, C.POINTER(i64)]),
+        "pic_save": (C.c_int, [p, p, i64]), "pic_load": (C.c_int, [p, p, i64]),
     }
     for name, (res, args) in sig.items():
         f = getattr(L, name)
@@ -321,6 +324,21 @@ class Simulation:
         out = torch.empty((max(n, 1), 4), dtype=torch.float64, device=self.device)
         _check(lib().bfpic_witness_lab(self.h, C.c_void_p(out.data_ptr())), self.h)
         return out[:n]
+
+    def save(self):
+        """The simulation state as a uint8 device tensor (see pic_save)."""
+        import torch
+        nb = C.c_int64()
+        _check(lib().bfpic_state_bytes(self.h, C.byref(nb)), self.h)
+        blob = torch.empty(nb.value, dtype=torch.uint8, device=self.device)
+        _check(lib().pic_save(self.h, C.c_void_p(blob.data_ptr()), nb.value), self.h)
+        return blob
+
+    def load(self, blob):
+        """Resumes from a state saved by `save` (same configuration)."""
+        import torch
+        blob = torch.as_tensor(blob, dtype=torch.uint8).to(self.device).contiguous()
+        _check(lib().pic_load(self.h, C.c_void_p(blob.data_ptr()), blob.numel()), self.h)
 
     def get_field(self, comp):
         import torch

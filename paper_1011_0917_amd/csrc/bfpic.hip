@@ -1369,6 +1369,33 @@ struct Impl {
     return BFPIC_OK;
   }
 
+  // Zeroes every device buffer a step expects to find zeroed or reset: the
+  // fields and the shift buffers, the filtered current, the whole overflow
+  // grid, the counters, the row of zero tiles the fold reads past the last
+  // tile, and the overflow row range.
+  static int reset_device(bfpic_ctx* h) {
+    const Geo& g = h->g;
+    const int64_t rs = h->fp64 ? 8 : 4;
+    const int64_t grid = g.rows * g.plane;
+    for (int c = 0; c < 6; c++) {
+      HIPCHK(h, hipMemsetAsync(h->F[c], 0, grid * rs, h->stream));
+      HIPCHK(h, hipMemsetAsync(h->Fs[c], 0, grid * rs, h->stream));
+    }
+    for (int c = 0; c < 3; c++) {
+      HIPCHK(h, hipMemsetAsync(h->Jf[c], 0, grid * rs, h->stream));
+      HIPCHK(h, hipMemsetAsync(h->Jo[c], 0, grid * (int64_t)ovf_bytes(h), h->stream));
+    }
+    HIPCHK(h, hipMemsetAsync(h->counts, 0, 16 * 4, h->stream));
+    if (h->tiled) {
+      const int64_t tile_bytes = 3 * (int64_t)h->LV * (int64_t)ovf_bytes(h);
+      HIPCHK(h, hipMemsetAsync((char*)h->scratch + h->maxtiles * tile_bytes, 0,
+                               (int64_t)h->ntx * h->nty * tile_bytes, h->stream));
+    }
+    k_ovf_reset<<<1, 1, 0, h->stream>>>(h->ovf_rows, h->counts + 4);
+    HIPCHK(h, hipGetLastError());
+    return BFPIC_OK;
+  }
+
   static int init(bfpic_ctx* h, double gamma_boost, const bfpic_density* d,
                   const bfpic_laser* laser) {
     const Geo& g = h->g;
@@ -1388,23 +1415,9 @@ struct Impl {
     h->slots_bound = 0;
     h->tail_bound = 0;
     h->have_sort = false;
-    const int64_t rs = h->fp64 ? 8 : 4;
+    int rc0 = reset_device(h);
+    if (rc0) return rc0;
     const int64_t grid = g.rows * g.plane;
-    for (int c = 0; c < 6; c++) {
-      HIPCHK(h, hipMemsetAsync(h->F[c], 0, grid * rs, h->stream));
-      HIPCHK(h, hipMemsetAsync(h->Fs[c], 0, grid * rs, h->stream));
-    }
-    for (int c = 0; c < 3; c++) {
-      HIPCHK(h, hipMemsetAsync(h->Jf[c], 0, grid * rs, h->stream));
-      HIPCHK(h, hipMemsetAsync(h->Jo[c], 0, grid * (int64_t)ovf_bytes(h), h->stream));
-    }
-    HIPCHK(h, hipMemsetAsync(h->counts, 0, 16 * 4, h->stream));
-    if (h->tiled) {
-      const int64_t tile_bytes = 3 * (int64_t)h->LV * (int64_t)ovf_bytes(h);
-      HIPCHK(h, hipMemsetAsync((char*)h->scratch + h->maxtiles * tile_bytes, 0,
-                               (int64_t)h->ntx * h->nty * tile_bytes, h->stream));
-    }
-    k_ovf_reset<<<1, 1, 0, h->stream>>>(h->ovf_rows, h->counts + 4);
     if (laser) {
       LaserK K;
       K.a0 = laser->a0;
@@ -1843,6 +1856,183 @@ extern "C" int bfpic_sort(bfpic_ctx* h) {
   if (!h) return BFPIC_ERR_ARG;
   if (!h->inited) return fail(h, BFPIC_ERR_STATE, "sort before init");
   BFPIC_DISPATCH(h, I::sort(h));
+}
+
+// ---------------------------------------------------------------------------
+// Checkpoint / resume.  A state blob is one caller-owned device buffer: a
+// header (identity of the configuration, the host schedule, the boost and
+// density parameters, the fixed-point scale), then E and B with their guard
+// rows, the live particle slots and the device counters.  Currents, the
+// overflow grid and the Mur and shift buffers are rebuilt within each step
+// and are not state; neither are bound witnesses (the caller's).
+// ---------------------------------------------------------------------------
+namespace {
+constexpr uint64_t kStateMagic = 0x3153544349504642ull;  // "BFPICTS1"
+constexpr int64_t kStateHead = 4096;
+
+struct StateHeader {
+  uint64_t magic;
+  int64_t total;
+  bfpic_config cfg;
+  int64_t cap, slots;
+  int64_t step, window_cells, next_col, slots_bound, tail_bound;
+  double gamma_b, beta_b, u_b, sb, laser_a0, fx_scale, fx_inv;
+  int32_t has_plasma, ndisp;
+  DensityK dens;
+};
+static_assert(sizeof(StateHeader) <= kStateHead, "state header");
+
+struct StateMap {
+  int64_t field, id, comp, counts, total;
+};
+
+StateMap state_map(const bfpic_ctx* h, int64_t slots) {
+  const int64_t es = h->fp64 ? 8 : 4;
+  StateMap m;
+  m.field = align256(h->g.rows * h->g.plane * es);
+  m.id = align256(std::max<int64_t>(slots, 1) * 4);
+  m.comp = align256(std::max<int64_t>(slots, 1) * es);
+  const int ndisp = h->dim == 3 ? 3 : 2;
+  m.counts = 256;
+  m.total = kStateHead + 6 * m.field + m.id + (int64_t)(ndisp + 4) * m.comp + m.counts;
+  return m;
+}
+
+bool same_physics(const bfpic_config& a, const bfpic_config& b) {
+  return a.dim == b.dim && a.nz == b.nz && a.nx == b.nx && a.ny == b.ny && a.dz == b.dz &&
+         a.dx == b.dx && a.dy == b.dy && a.cfl == b.cfl && a.shape_order == b.shape_order &&
+         a.filter_passes == b.filter_passes && a.filter_compensate == b.filter_compensate &&
+         a.precision == b.precision && a.deterministic == b.deterministic &&
+         a.z_boundary == b.z_boundary && a.ppc == b.ppc && a.load == b.load &&
+         a.seed == b.seed && a.beta_window == b.beta_window && a.auto_window == b.auto_window;
+}
+
+// Device arrays of the state in blob order: E, B, id, displacements,
+// momenta, weight.
+int state_arrays(bfpic_ctx* h, int64_t slots, void* ptr[16], int64_t bytes[16]) {
+  const int64_t es = h->fp64 ? 8 : 4;
+  int n = 0;
+  for (int c = 0; c < 6; c++) {
+    ptr[n] = h->F[c];
+    bytes[n++] = h->g.rows * h->g.plane * es;
+  }
+  ptr[n] = h->pid[h->cur];
+  bytes[n++] = slots * 4;
+  const int ndisp = h->dim == 3 ? 3 : 2;
+  for (int a = 0; a < ndisp; a++) {
+    ptr[n] = h->pxi[h->cur][a];
+    bytes[n++] = slots * es;
+  }
+  for (int a = 0; a < 3; a++) {
+    ptr[n] = h->pdu[h->cur][a];
+    bytes[n++] = slots * es;
+  }
+  ptr[n] = h->pw[h->cur];
+  bytes[n++] = slots * es;
+  return n;
+}
+}  // namespace
+
+static int reset_device_of(bfpic_ctx* h) { BFPIC_DISPATCH(h, I::reset_device(h)); }
+
+extern "C" int bfpic_state_bytes(bfpic_ctx* h, int64_t* bytes) {
+  if (!h || !bytes) return BFPIC_ERR_ARG;
+  if (!h->inited) return fail(h, BFPIC_ERR_STATE, "state size before init");
+  *bytes = state_map(h, h->slots_bound).total;
+  return BFPIC_OK;
+}
+
+extern "C" int pic_save(bfpic_ctx* h, void* blob_dev, int64_t blob_bytes) {
+  if (!h || !blob_dev) return BFPIC_ERR_ARG;
+  if (!h->inited) return fail(h, BFPIC_ERR_STATE, "save before init");
+  const StateMap m = state_map(h, h->slots_bound);
+  if (blob_bytes < m.total || ((uintptr_t)blob_dev & 255))
+    return fail(h, BFPIC_ERR_ARG, "state blob too small or misaligned");
+  StateHeader hd{};
+  hd.magic = kStateMagic;
+  hd.total = m.total;
+  hd.cfg = h->cfg;
+  hd.cap = h->cap;
+  hd.slots = h->slots_bound;
+  hd.step = h->step;
+  hd.window_cells = h->window_cells;
+  hd.next_col = h->next_col;
+  hd.slots_bound = h->slots_bound;
+  hd.tail_bound = h->tail_bound;
+  hd.gamma_b = h->gamma_b;
+  hd.beta_b = h->beta_b;
+  hd.u_b = h->u_b;
+  hd.sb = h->sb;
+  hd.laser_a0 = h->laser_a0;
+  hd.fx_scale = h->fx_scale;
+  hd.fx_inv = h->fx_inv;
+  hd.has_plasma = h->has_plasma ? 1 : 0;
+  hd.ndisp = h->dim == 3 ? 3 : 2;
+  hd.dens = h->dens;
+  uint8_t* b = (uint8_t*)blob_dev;
+  HIPCHK(h, hipMemcpyAsync(b, &hd, sizeof(hd), hipMemcpyHostToDevice, h->stream));
+  void* ptr[16];
+  int64_t bytes[16];
+  const int n = state_arrays(h, h->slots_bound, ptr, bytes);
+  int64_t o = kStateHead;
+  for (int q = 0; q < n; q++) {
+    if (bytes[q] > 0)
+      HIPCHK(h, hipMemcpyAsync(b + o, ptr[q], (size_t)bytes[q], hipMemcpyDeviceToDevice, h->stream));
+    o += q < 6 ? m.field : (q == 6 ? m.id : m.comp);
+  }
+  HIPCHK(h, hipMemcpyAsync(b + o, h->counts, 16 * 4, hipMemcpyDeviceToDevice, h->stream));
+  HIPCHK(h, hipStreamSynchronize(h->stream));  // the header's host copy
+  return BFPIC_OK;
+}
+
+extern "C" int pic_load(bfpic_ctx* h, const void* blob_dev, int64_t blob_bytes) {
+  if (!h || !blob_dev) return BFPIC_ERR_ARG;
+  if (blob_bytes < kStateHead || ((uintptr_t)blob_dev & 255))
+    return fail(h, BFPIC_ERR_ARG, "state blob too small or misaligned");
+  StateHeader hd{};
+  HIPCHK(h, hipMemcpyAsync(&hd, blob_dev, sizeof(hd), hipMemcpyDeviceToHost, h->stream));
+  HIPCHK(h, hipStreamSynchronize(h->stream));
+  if (hd.magic != kStateMagic) return fail(h, BFPIC_ERR_ARG, "not a state blob");
+  if (!same_physics(hd.cfg, h->cfg))
+    return fail(h, BFPIC_ERR_ARG, "state blob of another configuration");
+  if (hd.slots < 0 || hd.slots > h->cap)
+    return fail(h, BFPIC_ERR_CAPACITY, "state blob holds more slots than the capacity");
+  const StateMap m = state_map(h, hd.slots);
+  if (hd.total != m.total || blob_bytes < m.total)
+    return fail(h, BFPIC_ERR_ARG, "state blob size does not match its header");
+  h->step = hd.step;
+  h->window_cells = hd.window_cells;
+  h->next_col = hd.next_col;
+  h->slots_bound = hd.slots_bound;
+  h->tail_bound = hd.tail_bound;
+  h->gamma_b = hd.gamma_b;
+  h->beta_b = hd.beta_b;
+  h->u_b = hd.u_b;
+  h->sb = hd.sb;
+  h->laser_a0 = hd.laser_a0;
+  h->fx_scale = hd.fx_scale;
+  h->fx_inv = hd.fx_inv;
+  h->has_plasma = hd.has_plasma != 0;
+  h->dens = hd.dens;
+  h->adj_ready = false;
+  h->no_sort = false;
+  h->have_sort = false;
+  const int rz = reset_device_of(h);
+  if (rz) return rz;
+  const uint8_t* b = (const uint8_t*)blob_dev;
+  void* ptr[16];
+  int64_t bytes[16];
+  const int n = state_arrays(h, hd.slots, ptr, bytes);
+  int64_t o = kStateHead;
+  for (int q = 0; q < n; q++) {
+    if (bytes[q] > 0)
+      HIPCHK(h, hipMemcpyAsync(ptr[q], b + o, (size_t)bytes[q], hipMemcpyDeviceToDevice, h->stream));
+    o += q < 6 ? m.field : (q == 6 ? m.id : m.comp);
+  }
+  HIPCHK(h, hipMemcpyAsync(h->counts, b + o, 16 * 4, hipMemcpyDeviceToDevice, h->stream));
+  h->inited = true;
+  // the tile structures follow the particle order: rebuild them
+  return bfpic_sort(h);
 }
 
 extern "C" int bfpic_last_sort(bfpic_ctx* h, int32_t* key_dev, int32_t* id_dev, int32_t* perm_dev,
