@@ -16,6 +16,13 @@ The tests check the orders of magnitude: unfiltered growth by more than 1e8
 by step 2000, and filtering that keeps the energy more than 1e6 below the
 unfiltered one there, with one pass in between.
 
+Boost and filter survey (gamma_b = 13, 130, 1300 on the same slab; N = 0,
+1, 4 + comp., 8 + comp.): at every boost the energy at step 2000 falls with N
+(observed 1.3e4 > 8.5e2 > 3.7 > 7e-6 at 13; 1.5e7 > 18 > 0.10 > 4e-4 at 130;
+8.9e9 > 77 > 36 > 1.7 at 1300), and unfiltered and with eight passes it grows
+with the boost.  Checked: each step in N lowers the energy at least 1.5x, and
+the boost ordering for N = 0 and N = 8.
+
 Parity: the FP64 energy history of a smaller slab (128 x 32, 2 pairs per
 cell, 600 steps, in the growing phase) against the oracle, unfiltered and
 filtered.  The growth rate itself has no closed form here (parity unpinned
@@ -88,3 +95,30 @@ def test_instability_history_matches_oracle(P, npass, comp):
     assert np.all(np.abs(ug - uo) <= 1e-5 * np.abs(uo))
     if npass == 0:
         assert uo[-1] > 10 * uo[0]           # the window covers growth
+
+
+def survey_energy(P, gb, npass, comp):
+    W = small("boost130_2d", nz=256, nx=64, ppc=4, steps=2000, zbc="periodic", window=None,
+              gamma_b=gb, filter_passes=npass, filter_compensate=comp)
+    cfg, init, nst = resolve_gpu(W)
+    sim = P.Simulation(cfg, capacity=init["capacity"])
+    sim.init_boosted_plasma(init["gamma_b"], n_uniform=init["n_lab"], du=INSTABILITY_SEED_DU)
+    sim.pic_step(nst)
+    d = sim.diagnostics()
+    sim.close()
+    assert not d["nan_flag"]
+    return d["ue"] + d["ub"]
+
+
+def test_growth_against_boost_and_filtering(P):
+    filters = ((0, 0), (1, 0), (4, 1), (8, 1))
+    u = {}
+    for gb in (13.0, 130.0, 1300.0):
+        print("case instability survey, gamma_b =", gb, flush=True)
+        u[gb] = [survey_energy(P, gb, n, c) for n, c in filters]
+        print(f"gamma_b {gb}: U_E + U_B at step 2000 for N = 0, 1, 4c, 8c: "
+              + ", ".join(f"{v:.3e}" for v in u[gb]), flush=True)
+        for k in range(len(filters) - 1):
+            assert u[gb][k + 1] * 1.5 < u[gb][k], (gb, k)
+    for k in (0, 3):  # unfiltered and eight passes: stronger growth at higher boost
+        assert u[13.0][k] < u[130.0][k] < u[1300.0][k], k
