@@ -328,7 +328,9 @@ int pic_save(bfpic_ctx* h, void* blob_dev, int64_t blob_bytes);
  * run continues from the saved step; in deterministic mode it continues
  * bitwise as the uninterrupted run would.  ERR_ARG for a blob that is not a
  * state, comes from another configuration or is shorter than its header
- * says, ERR_CAPACITY if its slots exceed the capacity.  Synchronises. */
+ * says, ERR_CAPACITY if its slots exceed the capacity; these leave the
+ * context untouched.  After ERR_HIP the context's state is undefined
+ * (re-initialise or load again).  Synchronises. */
 int pic_load(bfpic_ctx* h, const void* blob_dev, int64_t blob_bytes);
 
 /* ---- state access (tests and tools; asynchronous unless stated) ---- */

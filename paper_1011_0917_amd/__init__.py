@@ -337,7 +337,9 @@ class Simulation:
     def load(self, blob):
         """Resumes from a state saved by `save` (same configuration)."""
         import torch
-        blob = torch.as_tensor(blob, dtype=torch.uint8).to(self.device).contiguous()
+        if not isinstance(blob, torch.Tensor) or blob.dtype != torch.uint8 or blob.dim() != 1:
+            raise BfpicError("state blob: a 1-D uint8 tensor written by save()")
+        blob = blob.to(self.device).contiguous()
         _check(lib().pic_load(self.h, C.c_void_p(blob.data_ptr()), blob.numel()), self.h)
 
     def get_field(self, comp):

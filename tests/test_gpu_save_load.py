@@ -116,6 +116,8 @@ def test_save_load_error_paths(P):
     with pytest.raises(P.BfpicError):                                 # another configuration
         other.load(blob)
     other.close()
+    with pytest.raises(P.BfpicError):                                 # not a uint8 blob
+        a.load(blob.float())
     a.load(blob)                                                      # the round trip itself
     assert a.diagnostics()["step"] == 3
     a.close()
