@@ -9,8 +9,8 @@
  * introduction; first paragraph of "Mitigation of a numerical instability"),
  * so the step is the standard explicit electromagnetic PIC cycle the method
  * runs in the boosted frame: gather -> Boris push -> move -> Esirkepov
- * deposit -> binomial current filter -> Yee update.  Readings of what the
- * paper leaves open are listed in the design doc of the repository.
+ * deposit -> binomial current filter -> Yee update.  Where the paper leaves
+ * a choice open, the function that makes it states the reading it takes.
  *
  * Conventions
  *   positions: absolute FP64, in cells, relative to the current grid origin

@@ -16,7 +16,7 @@ The tests check the orders of magnitude: unfiltered growth by more than 1e8
 by step 2000, and filtering that keeps the energy more than 1e6 below the
 unfiltered one there, with one pass in between.
 
-Boost and filter survey (gamma_b = 13, 130, 1300 on the same slab; N = 0,
+Boost and filter sweep (gamma_b = 13, 130, 1300 on the same slab; N = 0,
 1, 4 + comp., 8 + comp.): at every boost the energy at step 2000 falls with N
 (observed 1.3e4 > 8.5e2 > 3.7 > 7e-6 at 13; 1.5e7 > 18 > 0.10 > 4e-4 at 130;
 8.9e9 > 77 > 36 > 1.7 at 1300), and unfiltered and with eight passes it grows
@@ -97,7 +97,7 @@ def test_instability_history_matches_oracle(P, npass, comp):
         assert uo[-1] > 10 * uo[0]           # the window covers growth
 
 
-def survey_energy(P, gb, npass, comp):
+def sweep_energy(P, gb, npass, comp):
     W = small("boost130_2d", nz=256, nx=64, ppc=4, steps=2000, zbc="periodic", window=None,
               gamma_b=gb, filter_passes=npass, filter_compensate=comp)
     cfg, init, nst = resolve_gpu(W)
@@ -114,8 +114,8 @@ def test_growth_against_boost_and_filtering(P):
     filters = ((0, 0), (1, 0), (4, 1), (8, 1))
     u = {}
     for gb in (13.0, 130.0, 1300.0):
-        print("case instability survey, gamma_b =", gb, flush=True)
-        u[gb] = [survey_energy(P, gb, n, c) for n, c in filters]
+        print("case instability sweep, gamma_b =", gb, flush=True)
+        u[gb] = [sweep_energy(P, gb, n, c) for n, c in filters]
         print(f"gamma_b {gb}: U_E + U_B at step 2000 for N = 0, 1, 4c, 8c: "
               + ", ".join(f"{v:.3e}" for v in u[gb]), flush=True)
         for k in range(len(filters) - 1):
