@@ -214,6 +214,10 @@ def main():
                    "parallelism": "1 GPU"},
         "cell_updates_per_s": cups,
         "step_roofline_frac": step_bytes / (ms_step * 1e-3) / 1e9 / HBM_PEAK_GBS,
+        # the whole step's algorithmic bytes at the HBM peak bound both rates
+        "step_roofline_rates": {
+            "particle_steps_per_s": r32["particles"] * HBM_PEAK_GBS * 1e9 / step_bytes,
+            "cell_updates_per_s": r32["cells"] * HBM_PEAK_GBS * 1e9 / step_bytes},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS,
                      "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
                      "traffic": measured_traffic("k_gpd_tiled", args.workload, "fp32"),
