@@ -102,6 +102,7 @@ def lib():
             "orc_sort_keys": (C.c_int, [p, i32, i32, i32, i64, i32, p, p]),
             "orc_laser_eval": (None, [C.POINTER(Laser), i32, d, d, d, d, d, dp, dp]),
             "orc_filter_field": (C.c_int, [p, i32]),
+            "orc_lab_density": (d, [p, d]), "orc_channel_factor": (d, [p, d, d]),
         }
         for name, (res, args) in sig.items():
             f = getattr(L, name)
@@ -256,6 +257,12 @@ class Sim:
 
     def clear_particles(self):
         lib().orc_clear_particles(self.h)
+
+    def lab_density(self, z_lab: float) -> float:
+        return lib().orc_lab_density(self.h, float(z_lab))
+
+    def channel_factor(self, x: float, y: float = 0.0) -> float:
+        return lib().orc_channel_factor(self.h, float(x), float(y))
 
     def sort_keys(self, tz, tx, ty, tz_min, ntz):
         n = self.num_pairs()

@@ -674,29 +674,44 @@ static void init_laser(orc_sim* s, const orc_laser* L) {
 /* a lattice rigid in the calculation frame; column k occupies co-moving     */
 /* cells [k, k+1).  Lab birth coordinate z_lab = gamma_b (k + r_z) dz.       */
 /* ------------------------------------------------------------------------ */
+/* Piecewise-linear lab density through the knots (z_m, n_m), zero outside
+ * [z_0, z_last].  The bracketing segment [z_m, z_m+1] is found by bisection
+ * on the increasing knot positions; the value is the barycentric mix
+ * n_m (z_m+1 - z) / h + n_m+1 (z - z_m) / h with h = z_m+1 - z_m. */
 static double lab_density(const orc_sim* s, double zl) {
   if (s->nknots < 2) return s->n_uniform;
-  if (zl < s->kz[0] || zl > s->kz[s->nknots - 1]) return 0.0;
-  for (int m = 0; m + 1 < s->nknots; m++) {
-    if (zl <= s->kz[m + 1]) {
-      double f = (zl - s->kz[m]) / (s->kz[m + 1] - s->kz[m]);
-      return s->kn[m] + f * (s->kn[m + 1] - s->kn[m]);
-    }
+  const double* kz = s->kz;
+  int last = s->nknots - 1;
+  if (!(zl >= kz[0] && zl <= kz[last])) return 0.0;
+  int lo = 0, hi = last; /* invariant: kz[lo] <= zl <= kz[hi] */
+  while (hi - lo > 1) {
+    int mid = (lo + hi) / 2;
+    if (kz[mid] <= zl) lo = mid;
+    else hi = mid;
   }
-  return s->kn[s->nknots - 1];
+  double h = kz[hi] - kz[lo];
+  double a = (kz[hi] - zl) / h, b = (zl - kz[lo]) / h;
+  return s->kn[lo] * a + s->kn[hi] * b;
 }
 
 /* Plasma channel: the lab density times 1 + depth r^2 / radius^2, r the
  * distance of the birth position from the laser axis (the box centre, x in
  * 2D, x and y in 3D).  A parabolic channel of depth dn / n at r = w0 guides a
  * Gaussian beam of waist w0 when dn / n_c = 4 / (k0 w0)^2 (paraxial mode of a
- * parabolic index profile, applied per transverse axis). */
+ * parabolic index profile, applied per transverse axis).  x, y in cells. */
 static double channel_factor(const orc_sim* s, double x, double y) {
   const orc_config* c = &s->c;
   if (s->ch_depth == 0.0) return 1.0;
-  double dxa = x * c->dx - 0.5 * c->nx * c->dx;
-  double dya = c->dim == 3 ? y * c->dy - 0.5 * c->ny * c->dy : 0.0;
-  return 1.0 + s->ch_depth * (dxa * dxa + dya * dya) / (s->ch_radius * s->ch_radius);
+  double rx = (x - 0.5 * (double)c->nx) * c->dx;
+  double ry = c->dim == 3 ? (y - 0.5 * (double)c->ny) * c->dy : 0.0;
+  double r2 = rx * rx + ry * ry;
+  return 1.0 + s->ch_depth * (r2 / (s->ch_radius * s->ch_radius));
+}
+
+double orc_lab_density(const orc_sim* s, double z_lab) { return lab_density(s, z_lab); }
+
+double orc_channel_factor(const orc_sim* s, double x, double y) {
+  return channel_factor(s, x, y);
 }
 
 static void grow(orc_sim* s, int64_t need) {

@@ -144,6 +144,10 @@ int orc_sort_keys(const orc_sim* s, int32_t tz, int32_t tx, int32_t ty,
 /* the laser vector potential and Ey' at one calculation-frame event (t', z', x, y) */
 void orc_laser_eval(const orc_laser* L, int32_t dim, double gamma_b, double tp, double zp,
                     double x, double y, double* A, double* Ey);
+/* the lab density profile set by orc_init at lab position z_lab, and the
+ * channel factor at a transverse position (cells) */
+double orc_lab_density(const orc_sim* s, double z_lab);
+double orc_channel_factor(const orc_sim* s, double x, double y);
 /* apply the configured current filter to one stored component in place */
 int orc_filter_field(orc_sim* s, int32_t comp);
 
