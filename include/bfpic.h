@@ -170,7 +170,8 @@ double bfpic_yee_dt(int32_t dim, double dz, double dx, double dy, double cfl);
 /* ---- lifecycle ---- */
 
 /* Pure host.  Sizes of the device workspace for cfg and a particle capacity
- * (number of electrons; partners are implicit).  ERR_ARG on a bad config. */
+ * (number of electrons; partners are implicit).  ERR_ARG on a bad config or
+ * a capacity outside 1 .. 2^31 - 1 (the bound bfpic_create applies). */
 int bfpic_query_sizes(const bfpic_config* cfg, int64_t particle_capacity, bfpic_sizes* out);
 
 /* Creates a context on the current HIP device.  workspace: device pointer of
@@ -181,8 +182,14 @@ int bfpic_create(const bfpic_config* cfg, int64_t particle_capacity, void* works
 void bfpic_destroy(bfpic_ctx* h);
 const char* bfpic_last_error(const bfpic_ctx* h);
 
-/* Sets the fields and particles at t' = 0 in the frame boosted by gamma_boost
- * along +z (gamma_boost = 1: lab frame).  Laser: the lab potential above is
+/* The boosted-frame initialisation.  The paper changes frame by a Lorentz
+ * boost, which it describes as a hyperbolic rotation of space-time (section
+ * "Effect of the hyperbolic rotation in Minkowski space"), and notes that
+ * laser and plasma initialisation in the boosted frame need care (section
+ * "Mitigation of a numerical instability"; the procedure itself is in its
+ * companion papers).  This call sets the fields and particles at t' = 0 in
+ * the frame boosted by gamma_boost along +z (gamma_boost = 1: lab frame).
+ * Laser: the lab potential above is
  * evaluated on the t' = 0 hyperplane, i.e. at lab (t, z) = (gamma beta z',
  * gamma z'); Ey' = -dA/dt' there, B' = curl_h A' on the grid, and in 3D Ez'
  * from discrete div E' = 0 integrated from the low z end.  Plasma: every
@@ -190,21 +197,44 @@ const char* bfpic_last_error(const bfpic_ctx* h);
  * u = (0, 0, -gamma_b beta_b) + du, weight gamma_b n_lab(z_lab) dV / ppc at
  * the lab birth coordinate z_lab = gamma_b z'.  n_e may be NULL (vacuum),
  * laser may be NULL (no laser).  Resets step, window and injection counters.
- * ERR_CAPACITY if the initial particles do not fit. */
+ * Particle ids: the lattice slot ((k ny + l) nx + j) ppc + s of column k,
+ * transverse cell (j, l) and slot s, an int32; the columns a run may create
+ * (the box plus every injected column) are bounded by
+ * columns nx ny ppc <= 2^31.
+ * ERR_ARG for more than 32 knots, knots that do not increase, a null knot
+ * array or a bad channel; ERR_CAPACITY if the initial particles exceed the
+ * capacity or the id space.  These checks run before anything is changed:
+ * on them the context keeps its previous state.  A later failure (ERR_HIP)
+ * leaves the context uninitialised. */
 int init_boosted_plasma(bfpic_ctx* h, double gamma_boost, const bfpic_density* n_e,
                         const bfpic_laser* laser);
 
-/* Advances nsteps full steps.  Each step: inject the lattice columns whose low
+/* One explicit electromagnetic PIC step in the boosted frame, the step whose
+ * cost the boosted frame reduces (introduction; section "Effect of the
+ * hyperbolic rotation in Minkowski space": the speedup of the boosted-frame
+ * run over the lab run), with the current filtering that keeps the
+ * short-wavelength instability of the drifting plasma in check (section
+ * "Mitigation of a numerical instability").  The steps are the textbook
+ * methods: momentum-conserving gather with the deposit's shape, relativistic
+ * Boris push (Boris 1970), Esirkepov's charge-conserving deposit (2001),
+ * binomial filtering with compensation, Yee's FDTD update (1966) with
+ * first-order Mur boundaries (1981).
+ * Advances nsteps full steps.  Each step: inject the lattice columns whose low
  * edge has entered the box (k - D < nz), re-sort the particles if the sort
  * interval is due, then gather -> Boris (split drift form) -> move ->
  * Esirkepov deposit of each electron and its drifting partner -> filter J ->
  * B half step, E full step (+ Mur), B half step; then drop pairs more than
  * order+1 cells outside [0, nz] along z.  With auto_window the window shifts
  * after a step by floor(beta_window t / dz) - window_cells.  Asynchronous.
- * ERR_CAPACITY (before any launch) if the injections would not fit. */
+ * ERR_CAPACITY (before that step's launches) if its injections would not fit
+ * the capacity or the id space; the steps before it have run. */
 int pic_step(bfpic_ctx* h, int32_t nsteps);
 
-/* Shifts the window by ncells (either sign): field rows move by ncells,
+/* The moving window that follows the laser (section "Effect of the
+ * hyperbolic rotation in Minkowski space": the lab-frame simulation window
+ * moves with the laser; in the boosted frame it moves at the boosted group
+ * velocity, and near the laser's frame it stands still).
+ * Shifts the window by ncells (either sign): field rows move by ncells,
  * the rows that enter are zero, particles keep their lab positions (their
  * grid coordinates drop by ncells).  Columns that become due are injected by
  * the next pic_step.  ERR_ARG on a periodic z boundary.  Asynchronous. */
@@ -213,7 +243,13 @@ int moving_window_shift(bfpic_ctx* h, int32_t ncells);
 /* Host FP64 schedule: floor(beta_window t / dz) - window_cells. */
 int bfpic_window_due(bfpic_ctx* h, int32_t* ncells);
 
-/* Fills *out (host) with FP64 diagnostics.  lineout_dev (may be NULL): device
+/* Diagnostics of the run: the field and kinetic energies and the on-axis
+ * wake field Ez whose amplitude sets a stage's energy gain (section
+ * "Modeling of up to 1 TeV stages", Fig. 4), and the Gauss-law residual and
+ * non-finite flag that show a run is sound.  U_E = 1/2 sum E^2 dV,
+ * U_B = 1/2 sum B^2 dV over the domain nodes of each component,
+ * U_kin = sum w (gamma - 1) over electrons; all sums in FP64.
+ * Fills *out (host) with FP64 diagnostics.  lineout_dev (may be NULL): device
  * buffer of nz doubles that receives Ez on the axis row (j = nx/2, k = ny/2).
  * mask is reserved (pass 0xffffffff).  Synchronises the stream. */
 int diagnostics(bfpic_ctx* h, uint32_t mask, bfpic_diag* out, double* lineout_dev);
@@ -365,6 +401,13 @@ int bfpic_sort(bfpic_ctx* h);
  * *ntz (host) the co-moving tile rows used for the keys.  Synchronises. */
 int bfpic_last_sort(bfpic_ctx* h, int32_t* key_dev, int32_t* id_dev, int32_t* perm_dev,
                     int64_t* n, int64_t* n_live, int64_t* tz_min, int32_t* ntz);
+
+/* The sort probe: perm[d] = source slot of destination d of the last sort
+ * (the permutation bfpic_last_sort also returns), for live particles only;
+ * *n_live (host) receives their number.  perm_dev: device array of at least
+ * bfpic_num_slots entries before that sort.  ERR_STATE before any sort.
+ * Synchronises. */
+int bfpic_sort_permutation(bfpic_ctx* h, int32_t* perm_dev, int64_t* n_live);
 
 /* Tile geometry used by the sort key: tile sizes along z, x, y in cells. */
 int bfpic_tile_shape(const bfpic_ctx* h, int32_t* tz, int32_t* tx, int32_t* ty);

@@ -91,7 +91,7 @@ EXPORTS = ["bfpic_beta", "bfpic_drift_u", "bfpic_group_gamma", "bfpic_boosted_gr
            "bfpic_destroy", "bfpic_last_error", "init_boosted_plasma", "pic_step",
            "moving_window_shift", "bfpic_window_due", "diagnostics", "bfpic_get_field",
            "bfpic_set_field", "bfpic_num_slots", "bfpic_get_particles", "bfpic_sort",
-           "bfpic_last_sort", "bfpic_tile_shape", "bfpic_kernel_timing", "bfpic_kernel_time",
+           "bfpic_last_sort", "bfpic_sort_permutation", "bfpic_tile_shape", "bfpic_kernel_timing", "bfpic_kernel_time",
            "bfpic_adjoint_tape_bytes", "bfpic_forward_loss", "pic_step_adjoint",
            "bfpic_axis_record", "bfpic_back_transform", "bfpic_axis_spectrum",
            "bfpic_witness_bind", "bfpic_witness_lab", "bfpic_state_bytes", "pic_save",
@@ -127,6 +127,7 @@ def lib():
         "bfpic_sort": (C.c_int, [p]),
         "bfpic_last_sort": (C.c_int, [p, p, p, p, C.POINTER(i64), C.POINTER(i64),
                                       C.POINTER(i64), C.POINTER(i32)]),
+        "bfpic_sort_permutation": (C.c_int, [p, p, C.POINTER(i64)]),
         "bfpic_tile_shape": (C.c_int, [p, C.POINTER(i32), C.POINTER(i32), C.POINTER(i32)]),
         "bfpic_kernel_timing": (C.c_int, [p, i32]),
         "bfpic_kernel_time": (C.c_int, [p, i32, C.POINTER(d), C.POINTER(i64)]),
@@ -387,6 +388,15 @@ class Simulation:
                                      C.byref(tzmin), C.byref(ntz)), self.h)
         return {"key": key[: n.value].cpu().numpy(), "id": pid[: n.value].cpu().numpy(),
                 "perm": perm[: nl.value].cpu().numpy(), "tz_min": tzmin.value, "ntz": ntz.value}
+
+    def sort_permutation(self):
+        """perm[d] = source slot of destination d of the last sort (live only)."""
+        import torch
+        perm = torch.empty(max(self.capacity, 1), dtype=torch.int32, device=self.device)
+        nl = C.c_int64()
+        _check(lib().bfpic_sort_permutation(self.h, C.c_void_p(perm.data_ptr()), C.byref(nl)),
+               self.h)
+        return perm[: nl.value].cpu().numpy()
 
     def tile_shape(self):
         a, b, c = C.c_int32(), C.c_int32(), C.c_int32()

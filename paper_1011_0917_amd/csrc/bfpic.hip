@@ -410,6 +410,14 @@ static int64_t plan(bfpic_ctx* h, int64_t cap, bfpic_ctx* fill, bfpic_sizes* sz)
   return L.total;
 }
 
+// A particle's id is its lattice slot ((k ny + l) nx + j) ppc + s, an int32
+// (negative marks a removed slot); columns below kcols fit when
+// kcols nx ny ppc <= 2^31.
+static bool id_space_fits(const bfpic_ctx* h, int64_t kcols) {
+  const int64_t per_col = (int64_t)h->nx * h->ny * h->cfg.ppc;
+  return kcols >= 0 && kcols <= (int64_t(1) << 31) / per_col;
+}
+
 // ---------------------------------------------------------------------------
 // Typed implementation
 // ---------------------------------------------------------------------------
@@ -500,6 +508,9 @@ struct Impl {
   static int create_columns(bfpic_ctx* h, int64_t k0, int64_t ncols) {
     int64_t count = ncols * h->nx * h->ny * h->cfg.ppc;
     if (count <= 0) return BFPIC_OK;
+    if (!id_space_fits(h, k0 + ncols))
+      return fail(h, BFPIC_ERR_CAPACITY, "lattice ids of column " + std::to_string(k0 + ncols) +
+                                             " exceed the int32 id space");
     {
       Timer t(h, 5);
       k_create<R><<<(unsigned)cdiv(count, 256), 256, 0, h->stream>>>(
@@ -534,6 +545,9 @@ struct Impl {
     int64_t m = due_columns(h);
     if (m == 0) return BFPIC_OK;
     int64_t count = m * h->nx * h->ny * h->cfg.ppc;
+    if (!id_space_fits(h, h->next_col + m))
+      return fail(h, BFPIC_ERR_CAPACITY, "lattice ids of column " + std::to_string(h->next_col + m) +
+                                             " exceed the int32 id space");
     if (h->slots_bound + count > h->cap) {
       int rc = refresh_bound(h);
       if (rc) return rc;
@@ -1396,9 +1410,35 @@ struct Impl {
     return BFPIC_OK;
   }
 
+  // Every check init makes, before it changes any host or device state.
+  static int init_args(bfpic_ctx* h, const bfpic_density* d) {
+    if (!d) return BFPIC_OK;
+    if (d->nknots >= 2) {
+      if (d->nknots > kMaxKnots) return fail(h, BFPIC_ERR_ARG, "at most 32 density knots");
+      if (!d->z_lab || !d->n) return fail(h, BFPIC_ERR_ARG, "density knots: null array");
+      for (int m = 0; m + 1 < d->nknots; m++)
+        if (!(d->z_lab[m + 1] > d->z_lab[m]))
+          return fail(h, BFPIC_ERR_ARG, "density knots: z_lab must increase");
+    }
+    if (!(d->channel_depth >= 0.0) || !std::isfinite(d->channel_depth) ||
+        (d->channel_depth > 0.0 && !(d->channel_radius > 0.0)))
+      return fail(h, BFPIC_ERR_ARG, "channel: depth >= 0, radius > 0");
+    const int64_t count = (int64_t)h->nz * h->nx * h->ny * h->cfg.ppc;
+    if (count > h->cap)
+      return fail(h, BFPIC_ERR_CAPACITY, "initial particles " + std::to_string(count) +
+                                             " exceed capacity " + std::to_string(h->cap));
+    if (!id_space_fits(h, h->nz))
+      return fail(h, BFPIC_ERR_CAPACITY, "initial lattice ids exceed the int32 id space");
+    return BFPIC_OK;
+  }
+
   static int init(bfpic_ctx* h, double gamma_boost, const bfpic_density* d,
                   const bfpic_laser* laser) {
     const Geo& g = h->g;
+    int rca = init_args(h, d);
+    if (rca) return rca;
+    // from here on a failure leaves the context needing a new init
+    h->inited = false;
     h->gamma_b = gamma_boost;
     h->beta_b = bfpic_beta(gamma_boost);
     h->u_b = bfpic_drift_u(gamma_boost);
@@ -1457,7 +1497,6 @@ struct Impl {
       DensityK& D = h->dens;
       D.n_uniform = d->n_uniform;
       D.nknots = d->nknots >= 2 ? d->nknots : 0;
-      if (D.nknots > 32) return fail(h, BFPIC_ERR_ARG, "at most 32 density knots");
       for (int m = 0; m < D.nknots; m++) {
         D.kz[m] = d->z_lab[m];
         D.kn[m] = d->n[m];
@@ -1466,9 +1505,6 @@ struct Impl {
       D.dz = h->dz;
       D.dV_over_ppc = h->dz * h->dx * (DIM == 3 ? h->dy : 1.0) / h->cfg.ppc;
       for (int a = 0; a < 3; a++) D.du0[a] = d->du[a];
-      if (!(d->channel_depth >= 0.0) || !std::isfinite(d->channel_depth) ||
-          (d->channel_depth > 0.0 && !(d->channel_radius > 0.0)))
-        return fail(h, BFPIC_ERR_ARG, "channel: depth >= 0, radius > 0");
       D.ch_k = d->channel_depth > 0.0
                    ? d->channel_depth / (d->channel_radius * d->channel_radius) : 0.0;
       D.dx = h->dx;
@@ -1477,10 +1513,6 @@ struct Impl {
       D.ya = DIM == 3 ? 0.5 * h->ny * h->dy : 0.0;
       D.dim3 = DIM == 3;
       set_fixed_scale(h);
-      int64_t count = (int64_t)h->nz * h->nx * h->ny * h->cfg.ppc;
-      if (count > h->cap)
-        return fail(h, BFPIC_ERR_CAPACITY, "initial particles " + std::to_string(count) +
-                                               " exceed capacity " + std::to_string(h->cap));
       int rc = create_columns(h, 0, h->nz);
       if (rc) return rc;
       h->next_col = h->nz;
@@ -1636,7 +1668,7 @@ static int tape_bytes_of(bfpic_ctx* h, int nsteps, int interval, int64_t* out) {
 // ---------------------------------------------------------------------------
 extern "C" int bfpic_query_sizes(const bfpic_config* cfg, int64_t cap, bfpic_sizes* out) {
   std::string why;
-  if (!out || cap < 1 || !check_cfg(cfg, why)) return BFPIC_ERR_ARG;
+  if (!out || cap < 1 || cap > 0x7fffffffLL || !check_cfg(cfg, why)) return BFPIC_ERR_ARG;
   bfpic_ctx tmp;
   derive(&tmp, cfg);
   plan(&tmp, cap, nullptr, out);
@@ -2057,6 +2089,19 @@ extern "C" int bfpic_last_sort(bfpic_ctx* h, int32_t* key_dev, int32_t* id_dev, 
   *n_live = nl;
   *tz_min = h->last_sort_tzmin;
   *ntz = h->last_sort_ntz;
+  return BFPIC_OK;
+}
+
+extern "C" int bfpic_sort_permutation(bfpic_ctx* h, int32_t* perm_dev, int64_t* n_live) {
+  if (!h || !perm_dev || !n_live) return BFPIC_ERR_ARG;
+  if (!h->have_sort) return fail(h, BFPIC_ERR_STATE, "no sort yet");
+  int nl = 0;
+  HIPCHK(h, hipMemcpyAsync(&nl, h->off + h->last_sort_nkeys, 4, hipMemcpyDeviceToHost, h->stream));
+  HIPCHK(h, hipStreamSynchronize(h->stream));
+  HIPCHK(h, hipMemcpyAsync(perm_dev, h->final_perm, (size_t)nl * 4, hipMemcpyDeviceToDevice,
+                           h->stream));
+  HIPCHK(h, hipStreamSynchronize(h->stream));
+  *n_live = nl;
   return BFPIC_OK;
 }
 

@@ -132,3 +132,77 @@ def test_oracle_structs_match_its_header(tmp_path):
     structs = {"Config": "orc_config", "Density": "orc_density", "Laser": "orc_laser",
                "Diag": "orc_diag"}
     _check_layouts(O, structs, os.path.join(ROOT, "oracle"), "pic_oracle.h", tmp_path)
+
+
+def test_query_and_create_share_the_capacity_bound(P):
+    c = P.make_config()
+    s = P.Sizes()
+    assert P.lib().bfpic_query_sizes(ctypes.byref(c), 2 ** 31 - 1, ctypes.byref(s)) == 0
+    assert P.lib().bfpic_query_sizes(ctypes.byref(c), 2 ** 31, ctypes.byref(s)) == -1
+    h = ctypes.c_void_p()
+    rc = P.lib().bfpic_create(ctypes.byref(c), 2 ** 31, ctypes.c_void_p(256), 1 << 40, None,
+                              ctypes.byref(h))
+    assert rc == -1 and not h.value
+
+
+def _host_ctx(P, buf_keep, **kw):
+    """A context over a host buffer standing in for the workspace.  Only calls
+    that fail their argument checks, which run before any device work, may be
+    made on it."""
+    c = P.make_config(**kw)
+    s = P.Sizes()
+    cap = kw.get("nz", 64) * kw.get("nx", 32) * kw.get("ppc", 1)
+    assert P.lib().bfpic_query_sizes(ctypes.byref(c), cap, ctypes.byref(s)) == 0
+    buf = ctypes.create_string_buffer(s.workspace_bytes + 256)
+    buf_keep.append(buf)
+    base = (ctypes.addressof(buf) + 255) & ~255
+    h = ctypes.c_void_p()
+    rc = P.lib().bfpic_create(ctypes.byref(c), cap, ctypes.c_void_p(base), s.workspace_bytes,
+                              None, ctypes.byref(h))
+    if rc != 0:
+        pytest.skip("context creation needs the HIP runtime here")
+    return h, cap
+
+
+def test_init_rejects_bad_density_before_any_device_work(P):
+    keep = []
+    h, cap = _host_ctx(P, keep, nz=16, nx=8, ppc=2, z_boundary=P.BC_MUR)
+    L = P.lib()
+    try:
+        d = P.Density()
+        kz = (ctypes.c_double * 33)(*[float(i) for i in range(33)])
+        kn = (ctypes.c_double * 33)(*([1e-3] * 33))
+        d.nknots, d.z_lab, d.n = 33, ctypes.cast(kz, ctypes.POINTER(ctypes.c_double)), \
+            ctypes.cast(kn, ctypes.POINTER(ctypes.c_double))
+        assert L.init_boosted_plasma(h, 13.0, ctypes.byref(d), None) == -1
+        d.nknots = 3
+        kz[1] = kz[0]  # not increasing
+        assert L.init_boosted_plasma(h, 13.0, ctypes.byref(d), None) == -1
+        kz[1] = 1.0
+        d.channel_depth, d.channel_radius = 0.5, 0.0
+        assert L.init_boosted_plasma(h, 13.0, ctypes.byref(d), None) == -1
+        # nothing was initialised: stepping is still out of order
+        assert L.pic_step(h, 1) == -4
+    finally:
+        L.bfpic_destroy(h)
+
+
+def test_init_rejects_capacity_before_any_device_work(P):
+    L = P.lib()
+    # a capacity below the box's particles
+    c = P.make_config(nz=16, nx=8, ppc=2, z_boundary=P.BC_MUR)
+    s = P.Sizes()
+    assert L.bfpic_query_sizes(ctypes.byref(c), 100, ctypes.byref(s)) == 0
+    buf = ctypes.create_string_buffer(s.workspace_bytes + 256)
+    base = (ctypes.addressof(buf) + 255) & ~255
+    h = ctypes.c_void_p()
+    if L.bfpic_create(ctypes.byref(c), 100, ctypes.c_void_p(base), s.workspace_bytes, None,
+                      ctypes.byref(h)) != 0:
+        pytest.skip("context creation needs the HIP runtime here")
+    try:
+        d = P.Density()
+        d.n_uniform = 1e-3
+        assert L.init_boosted_plasma(h, 13.0, ctypes.byref(d), None) == -2
+        assert b"capacity" in L.bfpic_last_error(h)
+    finally:
+        L.bfpic_destroy(h)
