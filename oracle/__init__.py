@@ -29,7 +29,7 @@ def build(force: bool = True) -> str:
     """Compile the oracle with gcc (-O2, no FP contraction)."""
     if force or not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
         cmd = ["gcc", "-std=c99", "-D_DEFAULT_SOURCE", "-O2", "-fPIC", "-shared",
-               "-ffp-contract=off", "-o", _LIB + ".tmp", _SRC, "-lm"]
+               "-ffp-contract=off", "-fopenmp", "-o", _LIB + ".tmp", _SRC, "-lm"]
         subprocess.check_call(cmd)
         os.replace(_LIB + ".tmp", _LIB)
     return _LIB
@@ -103,6 +103,7 @@ def lib():
             "orc_laser_eval": (None, [C.POINTER(Laser), i32, d, d, d, d, d, dp, dp]),
             "orc_filter_field": (C.c_int, [p, i32]),
             "orc_lab_density": (d, [p, d]), "orc_channel_factor": (d, [p, d, d]),
+            "orc_set_threads": (C.c_int, [p, i32]), "orc_max_threads": (i32, []),
         }
         for name, (res, args) in sig.items():
             f = getattr(L, name)
@@ -128,6 +129,7 @@ def yee_dt(dim, dz, dx, dy, cfl): return lib().orc_yee_dt(dim, dz, dx, dy, cfl)
 def depletion_length(n): return lib().orc_depletion_length(n)
 def splitmix64(seed, n): return lib().orc_splitmix64(seed, n)
 def shape(order, d): return lib().orc_shape(order, d)
+def max_threads(): return lib().orc_max_threads()
 
 
 def cell_offset(seed, k, l, j, s, axis, nx, nyy, ppc):
@@ -257,6 +259,10 @@ class Sim:
 
     def clear_particles(self):
         lib().orc_clear_particles(self.h)
+
+    def set_threads(self, n: int):
+        """Threads of the particle loop (per-thread current buffers)."""
+        assert lib().orc_set_threads(self.h, int(n)) == 0
 
     def lab_density(self, z_lab: float) -> float:
         return lib().orc_lab_density(self.h, float(z_lab))

@@ -22,6 +22,9 @@
 #include "pic_oracle.h"
 
 #include <complex.h>
+#ifdef _OPENMP
+#include <omp.h>
+#endif
 #include <math.h>
 #include <stdlib.h>
 #include <string.h>
@@ -63,6 +66,10 @@ struct orc_sim {
   double* kn;
   double du0[3];
   double ch_depth, ch_radius;
+  /* per-thread current buffers of the parallel particle loop (thread t > 0
+   * deposits into tJ[t-1][comp]; thread 0 into the grid's own J) */
+  int nthreads;
+  double** tJ;
 };
 
 /* ------------------------------------------------------------------------ */
@@ -307,8 +314,8 @@ static void shape_row(int order, double p0, double p1, int64_t* lo, int* n, doub
   }
 }
 
-static void deposit_2d(orc_sim* s, double q, double w, double vy, double z0, double x0,
-                       double z1, double x1) {
+static void deposit_2d(const orc_sim* s, double* const* J, double q, double w, double vy,
+                       double z0, double x0, double z1, double x1) {
   const orc_config* c = &s->c;
   int64_t lz, lx;
   int nz_, nx_;
@@ -324,7 +331,7 @@ static void deposit_2d(orc_sim* s, double q, double w, double vy, double z0, dou
     for (int a = 0; a < nz_; a++) {
       double dSz = S1z[a] - S0z[a];
       acc += cz * dSz * (S0x[b] + 0.5 * dSx);
-      if (acc != 0.0) add_at(s, s->F[ORC_JZ], lz + a, lx + b, 0, acc);
+      if (acc != 0.0) add_at(s, J[2], lz + a, lx + b, 0, acc);
     }
   }
   /* Jx: prefix along x for every z node */
@@ -333,7 +340,7 @@ static void deposit_2d(orc_sim* s, double q, double w, double vy, double z0, dou
     for (int b = 0; b < nx_; b++) {
       double dSx = S1x[b] - S0x[b];
       acc += cx * dSx * (S0z[a] + 0.5 * dSz);
-      if (acc != 0.0) add_at(s, s->F[ORC_JX], lz + a, lx + b, 0, acc);
+      if (acc != 0.0) add_at(s, J[0], lz + a, lx + b, 0, acc);
     }
   }
   /* Jy: out-of-plane, the time-averaged shape */
@@ -344,7 +351,7 @@ static void deposit_2d(orc_sim* s, double q, double w, double vy, double z0, dou
         double dSx = S1x[b] - S0x[b];
         double wy = S0z[a] * S0x[b] + 0.5 * dSz * S0x[b] + 0.5 * S0z[a] * dSx +
                     dSz * dSx / 3.0;
-        if (wy != 0.0) add_at(s, s->F[ORC_JY], lz + a, lx + b, 0, cy * wy);
+        if (wy != 0.0) add_at(s, J[1], lz + a, lx + b, 0, cy * wy);
       }
     }
   }
@@ -354,8 +361,8 @@ static double wmix(double S0a, double dSa, double S0b, double dSb) {
   return S0a * S0b + 0.5 * dSa * S0b + 0.5 * S0a * dSb + dSa * dSb / 3.0;
 }
 
-static void deposit_3d(orc_sim* s, double q, double w, double z0, double x0, double y0,
-                       double z1, double x1, double y1) {
+static void deposit_3d(const orc_sim* s, double* const* J, double q, double w, double z0,
+                       double x0, double y0, double z1, double x1, double y1) {
   const orc_config* c = &s->c;
   int64_t lz, lx, ly;
   int nz_, nx_, ny_;
@@ -371,7 +378,7 @@ static void deposit_3d(orc_sim* s, double q, double w, double z0, double x0, dou
       double acc = 0.0;
       for (int a = 0; a < nz_; a++) {
         acc += cz * (S1z[a] - S0z[a]) * wmix(S0x[b], S1x[b] - S0x[b], S0y[d], S1y[d] - S0y[d]);
-        if (acc != 0.0) add_at(s, s->F[ORC_JZ], lz + a, lx + b, ly + d, acc);
+        if (acc != 0.0) add_at(s, J[2], lz + a, lx + b, ly + d, acc);
       }
     }
   for (int a = 0; a < nz_; a++)
@@ -379,7 +386,7 @@ static void deposit_3d(orc_sim* s, double q, double w, double z0, double x0, dou
       double acc = 0.0;
       for (int b = 0; b < nx_; b++) {
         acc += cx * (S1x[b] - S0x[b]) * wmix(S0z[a], S1z[a] - S0z[a], S0y[d], S1y[d] - S0y[d]);
-        if (acc != 0.0) add_at(s, s->F[ORC_JX], lz + a, lx + b, ly + d, acc);
+        if (acc != 0.0) add_at(s, J[0], lz + a, lx + b, ly + d, acc);
       }
     }
   for (int a = 0; a < nz_; a++)
@@ -387,7 +394,7 @@ static void deposit_3d(orc_sim* s, double q, double w, double z0, double x0, dou
       double acc = 0.0;
       for (int d = 0; d < ny_; d++) {
         acc += cy * (S1y[d] - S0y[d]) * wmix(S0z[a], S1z[a] - S0z[a], S0x[b], S1x[b] - S0x[b]);
-        if (acc != 0.0) add_at(s, s->F[ORC_JY], lz + a, lx + b, ly + d, acc);
+        if (acc != 0.0) add_at(s, J[1], lz + a, lx + b, ly + d, acc);
       }
     }
 }
@@ -799,6 +806,7 @@ void orc_destroy(orc_sim* s) {
   free(s->id);
   free(s->kz);
   free(s->kn);
+  orc_set_threads(s, 1);
   free(s);
 }
 
@@ -866,6 +874,45 @@ int orc_window_shift(orc_sim* s, int32_t n) {
   return 0;
 }
 
+/* Threads of the particle loop: the count set by orc_set_threads (1 by
+ * default), but no more than one per 4096 pairs; the per-thread current
+ * buffers are allocated on first use and kept. */
+static int orc_threads_for(orc_sim* s) {
+  int nt = s->nthreads > 1 ? s->nthreads : 1;
+  int64_t lim = s->np / 4096;
+  if (lim < 1) lim = 1;
+  if (nt > lim) nt = (int)lim;
+  if (nt > 1 && !s->tJ) {
+    int64_t total = (int64_t)s->nzs * s->plane;
+    s->tJ = (double**)calloc((size_t)(3 * (s->nthreads - 1)), sizeof(double*));
+    for (int t = 0; t < 3 * (s->nthreads - 1); t++)
+      s->tJ[t] = (double*)malloc(sizeof(double) * (size_t)total);
+  }
+  return nt;
+}
+
+int orc_set_threads(orc_sim* s, int32_t n) {
+  if (n < 1) return -1;
+#ifndef _OPENMP
+  if (n > 1) return -1;
+#endif
+  if (s->tJ) {
+    for (int t = 0; t < 3 * (s->nthreads - 1); t++) free(s->tJ[t]);
+    free(s->tJ);
+    s->tJ = NULL;
+  }
+  s->nthreads = n;
+  return 0;
+}
+
+int32_t orc_max_threads(void) {
+#ifdef _OPENMP
+  return (int32_t)omp_get_max_threads();
+#else
+  return 1;
+#endif
+}
+
 /* One full step: inject -> (gather, Boris, move, deposit) per electron,
  * rigid drift + deposit per ion partner -> filter J -> Yee -> removal. */
 int orc_step(orc_sim* s, int32_t nsteps) {
@@ -877,7 +924,24 @@ int orc_step(orc_sim* s, int32_t nsteps) {
   for (int32_t it = 0; it < nsteps; it++) {
     inject_due(s);
     for (int a = ORC_JX; a <= ORC_JZ; a++) memset(s->F[a], 0, sizeof(double) * (size_t)total);
+    /* Particles are independent within a step: each thread pushes a share of
+     * them and deposits into its own current buffer; the buffers are summed
+     * into J afterwards (same sums, another order of addition). */
+    int nt = orc_threads_for(s);
+    for (int t = 1; t < nt; t++)
+      for (int a = 0; a < 3; a++) memset(s->tJ[3 * (t - 1) + a], 0, sizeof(double) * (size_t)total);
+#ifdef _OPENMP
+#pragma omp parallel for num_threads(nt) schedule(static)
+#endif
     for (int64_t p = 0; p < s->np; p++) {
+#ifdef _OPENMP
+      int th = omp_get_thread_num();
+#else
+      int th = 0;
+#endif
+      double* const Jt[3] = {th ? s->tJ[3 * (th - 1) + 0] : s->F[ORC_JX],
+                             th ? s->tJ[3 * (th - 1) + 1] : s->F[ORC_JY],
+                             th ? s->tJ[3 * (th - 1) + 2] : s->F[ORC_JZ]};
       double z0 = s->ze[p], x0 = s->xe[p], y0 = s->ye[p];
       double E[3], B[3];
       E[0] = gather(s, ORC_EX, z0, x0, y0);
@@ -893,8 +957,8 @@ int orc_step(orc_sim* s, int32_t nsteps) {
       double z1 = z0 + vz * c->dt / c->dz;
       double x1 = x0 + vx * c->dt / c->dx;
       double y1 = d3 ? y0 + vy * c->dt / c->dy : y0;
-      if (d3) deposit_3d(s, -1.0, s->w[p], z0, x0, y0, z1, x1, y1);
-      else deposit_2d(s, -1.0, s->w[p], vy, z0, x0, z1, x1);
+      if (d3) deposit_3d(s, Jt, -1.0, s->w[p], z0, x0, y0, z1, x1, y1);
+      else deposit_2d(s, Jt, -1.0, s->w[p], vy, z0, x0, z1, x1);
       s->ux[p] = u[0];
       s->uy[p] = u[1];
       s->uz[p] = u[2];
@@ -903,11 +967,17 @@ int orc_step(orc_sim* s, int32_t nsteps) {
       s->ye[p] = d3 ? y1 - c->ny * floor(y1 / c->ny) : y1;
       if (c->ions && sb != 0.0) {
         double zi0 = s->zi[p], zi1 = zi0 - sb;
-        if (d3) deposit_3d(s, 1.0, s->w[p], zi0, s->xi[p], s->yi[p], zi1, s->xi[p], s->yi[p]);
-        else deposit_2d(s, 1.0, s->w[p], 0.0, zi0, s->xi[p], zi1, s->xi[p]);
+        if (d3) deposit_3d(s, Jt, 1.0, s->w[p], zi0, s->xi[p], s->yi[p], zi1, s->xi[p], s->yi[p]);
+        else deposit_2d(s, Jt, 1.0, s->w[p], 0.0, zi0, s->xi[p], zi1, s->xi[p]);
         s->zi[p] = c->zbc == 0 ? zi1 - c->nz * floor(zi1 / c->nz) : zi1;
       }
     }
+    for (int t = 1; t < nt; t++)
+      for (int a = 0; a < 3; a++) {
+        const double* src = s->tJ[3 * (t - 1) + a];
+        double* dst = s->F[ORC_JX + a];
+        for (int64_t q = 0; q < total; q++) dst[q] += src[q];
+      }
     apply_filter(s, s->F[ORC_JX], SIG[ORC_JX][0]);
     apply_filter(s, s->F[ORC_JY], SIG[ORC_JY][0]);
     apply_filter(s, s->F[ORC_JZ], SIG[ORC_JZ][0]);

@@ -125,6 +125,11 @@ int orc_init(orc_sim* s, const orc_density* dens, const orc_laser* laser, int32_
 int orc_step(orc_sim* s, int32_t nsteps);
 int orc_window_shift(orc_sim* s, int32_t ncells);
 int orc_diagnostics(orc_sim* s, orc_diag* out, double* lineout /* nz or NULL */);
+/* Threads of the particle loop (OpenMP, per-thread current buffers summed
+ * after the loop); 1 by default.  -1 for n < 1, or n > 1 in a build without
+ * OpenMP.  orc_max_threads: the OpenMP default thread count (1 without). */
+int orc_set_threads(orc_sim* s, int32_t n);
+int32_t orc_max_threads(void);
 
 /* state access (domain rows i = 0..nz; layout [i][j][k], k = y fastest) */
 int64_t orc_field_size(const orc_sim* s);

@@ -220,3 +220,34 @@ def test_sort_keys_hand_table_3d_periodic():
            (0.0, 7.9, 3.2)]   # tile 0, local (0, 7, 3) -> 59
     key, _ = _keyed(3, 0, pts, (8, 8, 8), 0, 2, nz=16, nx=8, ny=8)
     assert key == [599, 960, 59]
+
+
+# --------------------------------------------------------------------------
+# The parallel particle loop sums the same currents in another order
+# --------------------------------------------------------------------------
+@pytest.mark.skipif(O.max_threads() < 2, reason="oracle built without OpenMP")
+@pytest.mark.parametrize("dim", [2, 3])
+def test_threaded_particle_loop_matches_serial(dim):
+    from workloads import WORKLOADS, resolve_oracle, small
+    if dim == 2:
+        W = small("boost13_2d", nz=48, nx=64, steps=6)
+    else:
+        W = small("boost100_3d", nz=24, nx=16, ny=16, steps=6)
+    out = []
+    for nt in (1, 4):
+        kw, init = resolve_oracle(W)
+        s = O.Sim(**kw)
+        s.set_threads(nt)
+        s.init(n_uniform=init["n_lab"], laser=init["laser"])
+        s.step(6)
+        # one particle's current at a node is of order w / (cell area dt): the
+        # electron and partner terms of a pair cancel to far below that, so
+        # round-off of the order of addition is measured against it
+        unit = s.particles()["w"].max() / (kw["dx"] * kw["dt"] * (kw["dy"] if dim == 3 else 1.0))
+        out.append((s.diagnostics(lineout=True), s.get_field("Jz"), s.get_field("Ey"), unit))
+    (d1, j1, e1, unit), (d4, j4, e4, _) = out
+    for k in ("ue", "ub", "ukin"):
+        assert d4[k] == pytest.approx(d1[k], rel=1e-12)
+    assert d4["live"] == d1["live"]
+    assert np.abs(j4 - j1).max() <= 1e-14 * unit
+    assert np.abs(e4 - e1).max() <= 1e-12 * np.abs(e1).max()
