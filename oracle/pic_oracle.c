@@ -13,7 +13,13 @@
  * a choice open, the function that makes it states the reading it takes.
  *
  * Conventions
- *   positions: absolute FP64, in cells, relative to the current grid origin
+ *   positions: absolute, in cells, relative to the current grid origin, held
+ *   in x87 extended precision (long double, 64-bit significand): at 8192
+ *   cells an FP64 coordinate resolves 1.8e-12 cell, about 1e-4 of the
+ *   distance a boosted pair's electron moves away from its partner in one
+ *   step at gamma_b = 130, while the extended one resolves 9e-16 cell.  Every
+ *   shape factor is evaluated in FP64 on the offset from its stencil base,
+ *   formed in extended precision.
  *   grid node (i, j, k) of a component sits at ((i+sz)dz, (j+sx)dx, (k+sy)dy)
  *   with the Yee offsets of the table SIG below; y is absent in 2D.
  *   Fields are stored for rows i = -G .. nz+G; rows outside the physical
@@ -44,6 +50,8 @@ static const double SIG[ORC_NCOMP][3] = {
     {0.5, 0.0, 0.0}, /* Jz */
 };
 
+typedef long double xpos; /* particle coordinates (see the conventions above) */
+
 struct orc_sim {
   orc_config c;
   int nyy;        /* ny in 3D, 1 in 2D */
@@ -53,7 +61,8 @@ struct orc_sim {
   double* rho;    /* diagnostics scratch, same shape as one component */
   /* particle pairs: electron (e) and its ion partner (i) */
   int64_t np, cap;
-  double *ze, *xe, *ye, *uz, *ux, *uy, *zi, *xi, *yi, *w;
+  xpos *ze, *xe, *ye, *zi, *xi, *yi;
+  double *uz, *ux, *uy, *w;
   int64_t* id;
   int64_t step;
   double window_cells;
@@ -262,23 +271,25 @@ static int in_domain(const orc_sim* s, double sz, int64_t i) {
 /* Gather: F_p = sum_nodes F(node) S(z - i - sz) S(x - j - sx) [S(y - k - sy)]*/
 /* with the deposit's shape order (momentum-conserving gather).               */
 /* ------------------------------------------------------------------------ */
-static double gather(const orc_sim* s, int comp, double z, double x, double y) {
+static double gather(const orc_sim* s, int comp, xpos z, xpos x, xpos y) {
   const orc_config* c = &s->c;
-  double pz = z - SIG[comp][0], px = x - SIG[comp][1], py = y - SIG[comp][2];
-  int64_t i0 = (int64_t)floor(pz) - 2, j0 = (int64_t)floor(px) - 2;
-  int64_t k0 = (int64_t)floor(py) - 2;
+  xpos pz = z - SIG[comp][0], px = x - SIG[comp][1], py = y - SIG[comp][2];
+  int64_t i0 = (int64_t)floorl(pz) - 2, j0 = (int64_t)floorl(px) - 2;
+  int64_t k0 = (int64_t)floorl(py) - 2;
+  /* offsets from the stencil base, small enough for FP64 */
+  double lz = (double)(pz - (xpos)i0), lx = (double)(px - (xpos)j0), ly = (double)(py - (xpos)k0);
   double sum = 0.0;
   for (int a = 0; a < 6; a++) {
-    double wz = orc_shape(c->order, pz - (double)(i0 + a));
+    double wz = orc_shape(c->order, lz - (double)a);
     if (wz == 0.0) continue;
     for (int b = 0; b < 6; b++) {
-      double wx = orc_shape(c->order, px - (double)(j0 + b));
+      double wx = orc_shape(c->order, lx - (double)b);
       if (wx == 0.0) continue;
       if (c->dim == 2) {
         sum += fget(s, comp, i0 + a, j0 + b, 0) * wz * wx;
       } else {
         for (int d = 0; d < 6; d++) {
-          double wy = orc_shape(c->order, py - (double)(k0 + d));
+          double wy = orc_shape(c->order, ly - (double)d);
           if (wy == 0.0) continue;
           sum += fget(s, comp, i0 + a, j0 + b, k0 + d) * wz * wx * wy;
         }
@@ -301,21 +312,22 @@ static double gather(const orc_sim* s, int comp, double z, double x, double y) {
 /* ------------------------------------------------------------------------ */
 #define STN 12
 
-static void shape_row(int order, double p0, double p1, int64_t* lo, int* n, double* S0,
+static void shape_row(int order, xpos p0, xpos p1, int64_t* lo, int* n, double* S0,
                       double* S1) {
-  int64_t a = (int64_t)floor(p0 < p1 ? p0 : p1) - 2;
-  int64_t b = (int64_t)floor(p0 > p1 ? p0 : p1) + 3;
+  int64_t a = (int64_t)floorl(p0 < p1 ? p0 : p1) - 2;
+  int64_t b = (int64_t)floorl(p0 > p1 ? p0 : p1) + 3;
   *lo = a;
   *n = (int)(b - a + 1);
   if (*n > STN) *n = STN; /* displacements are below one cell per step */
+  double l0 = (double)(p0 - (xpos)a), l1 = (double)(p1 - (xpos)a);
   for (int m = 0; m < *n; m++) {
-    S0[m] = orc_shape(order, p0 - (double)(a + m));
-    S1[m] = orc_shape(order, p1 - (double)(a + m));
+    S0[m] = orc_shape(order, l0 - (double)m);
+    S1[m] = orc_shape(order, l1 - (double)m);
   }
 }
 
 static void deposit_2d(const orc_sim* s, double* const* J, double q, double w, double vy,
-                       double z0, double x0, double z1, double x1) {
+                       xpos z0, xpos x0, xpos z1, xpos x1) {
   const orc_config* c = &s->c;
   int64_t lz, lx;
   int nz_, nx_;
@@ -361,8 +373,8 @@ static double wmix(double S0a, double dSa, double S0b, double dSb) {
   return S0a * S0b + 0.5 * dSa * S0b + 0.5 * S0a * dSb + dSa * dSb / 3.0;
 }
 
-static void deposit_3d(const orc_sim* s, double* const* J, double q, double w, double z0,
-                       double x0, double y0, double z1, double x1, double y1) {
+static void deposit_3d(const orc_sim* s, double* const* J, double q, double w, xpos z0,
+                       xpos x0, xpos y0, xpos z1, xpos x1, xpos y1) {
   const orc_config* c = &s->c;
   int64_t lz, lx, ly;
   int nz_, nx_, ny_;
@@ -400,22 +412,22 @@ static void deposit_3d(const orc_sim* s, double* const* J, double q, double w, d
 }
 
 /* Charge density on the integer lattice (diagnostics): rho += q w S S [S] / dV */
-static void deposit_rho(orc_sim* s, double* R, double q, double w, double z, double x,
-                        double y) {
+static void deposit_rho(orc_sim* s, double* R, double q, double w, xpos z, xpos x, xpos y) {
   const orc_config* c = &s->c;
   double dV = c->dz * c->dx * (c->dim == 3 ? c->dy : 1.0);
-  int64_t i0 = (int64_t)floor(z) - 2, j0 = (int64_t)floor(x) - 2, k0 = (int64_t)floor(y) - 2;
+  int64_t i0 = (int64_t)floorl(z) - 2, j0 = (int64_t)floorl(x) - 2, k0 = (int64_t)floorl(y) - 2;
+  double lz = (double)(z - (xpos)i0), lx = (double)(x - (xpos)j0), ly = (double)(y - (xpos)k0);
   for (int a = 0; a < 6; a++) {
-    double wz = orc_shape(c->order, z - (double)(i0 + a));
+    double wz = orc_shape(c->order, lz - (double)a);
     if (wz == 0.0) continue;
     for (int b = 0; b < 6; b++) {
-      double wx = orc_shape(c->order, x - (double)(j0 + b));
+      double wx = orc_shape(c->order, lx - (double)b);
       if (wx == 0.0) continue;
       if (c->dim == 2) {
         add_at(s, R, i0 + a, j0 + b, 0, q * w * wz * wx / dV);
       } else {
         for (int d = 0; d < 6; d++) {
-          double wy = orc_shape(c->order, y - (double)(k0 + d));
+          double wy = orc_shape(c->order, ly - (double)d);
           if (wy != 0.0) add_at(s, R, i0 + a, j0 + b, k0 + d, q * w * wz * wx * wy / dV);
         }
       }
@@ -444,6 +456,11 @@ static void filter_pass(orc_sim* s, double* A, double sz, int axis, double a, do
   double* T = (double*)malloc(sizeof(double) * (size_t)total);
   memcpy(T, A, sizeof(double) * (size_t)total);
   int ny = s->nyy;
+  int nt = s->nthreads > 1 ? s->nthreads : 1;
+  (void)nt;
+#ifdef _OPENMP
+#pragma omp parallel for num_threads(nt) schedule(static)
+#endif
   for (int64_t i = row_lo(s, sz); i <= row_hi(s, sz); i++)
     for (int64_t j = 0; j < c->nx; j++)
       for (int64_t k = 0; k < ny; k++) {
@@ -484,6 +501,11 @@ static void yee_b(orc_sim* s, double h) {
   const orc_config* c = &s->c;
   int d3 = c->dim == 3;
   double idz = 1.0 / c->dz, idx = 1.0 / c->dx, idy = d3 ? 1.0 / c->dy : 0.0;
+  int nt = s->nthreads > 1 ? s->nthreads : 1;
+  (void)nt;
+#ifdef _OPENMP
+#pragma omp parallel for num_threads(nt) schedule(static)
+#endif
   for (int64_t j = 0; j < c->nx; j++)
     for (int64_t k = 0; k < s->nyy; k++) {
       for (int64_t i = 0; i <= row_hi(s, 0.5); i++) {
@@ -522,6 +544,11 @@ static void yee_e(orc_sim* s, double h) {
     }
   }
   int64_t tlo = mur ? 1 : 0, thi = mur ? nz - 1 : nz - 1;
+  int nt = s->nthreads > 1 ? s->nthreads : 1;
+  (void)nt;
+#ifdef _OPENMP
+#pragma omp parallel for num_threads(nt) schedule(static)
+#endif
   for (int64_t j = 0; j < c->nx; j++)
     for (int64_t k = 0; k < s->nyy; k++) {
       for (int64_t i = tlo; i <= thi; i++) {
@@ -630,6 +657,11 @@ static void init_laser(orc_sim* s, const orc_laser* L) {
   int64_t total = (int64_t)s->nzs * s->plane;
   double* A = (double*)calloc((size_t)total, sizeof(double));
   int my = d3 ? L->images_y : 0;
+  int nt = s->nthreads > 1 ? s->nthreads : 1;
+  (void)nt;
+#ifdef _OPENMP
+#pragma omp parallel for num_threads(nt) schedule(dynamic, 4)
+#endif
   for (int64_t i = 0; i <= ihi; i++)
     for (int64_t j = 0; j < c->nx; j++)
       for (int64_t k = 0; k < s->nyy; k++) {
@@ -725,32 +757,43 @@ static void grow(orc_sim* s, int64_t need) {
   if (need <= s->cap) return;
   int64_t nc = s->cap ? s->cap : 1024;
   while (nc < need) nc *= 2;
-  double** arrs[10] = {&s->ze, &s->xe, &s->ye, &s->uz, &s->ux, &s->uy, &s->zi, &s->xi, &s->yi, &s->w};
-  for (int a = 0; a < 10; a++) *arrs[a] = (double*)realloc(*arrs[a], sizeof(double) * (size_t)nc);
+  xpos** pos[6] = {&s->ze, &s->xe, &s->ye, &s->zi, &s->xi, &s->yi};
+  for (int a = 0; a < 6; a++) *pos[a] = (xpos*)realloc(*pos[a], sizeof(xpos) * (size_t)nc);
+  double** arrs[4] = {&s->uz, &s->ux, &s->uy, &s->w};
+  for (int a = 0; a < 4; a++) *arrs[a] = (double*)realloc(*arrs[a], sizeof(double) * (size_t)nc);
   s->id = (int64_t*)realloc(s->id, sizeof(int64_t) * (size_t)nc);
   s->cap = nc;
 }
 
-int orc_add_pair(orc_sim* s, double ze, double xe, double ye, double uz, double ux, double uy,
-                 double zi, double xi, double yi, double w, int64_t id) {
+static void store_pair(orc_sim* s, xpos ze, xpos xe, xpos ye, double uz, double ux, double uy,
+                       xpos zi, xpos xi, xpos yi, double w, int64_t id) {
   grow(s, s->np + 1);
   int64_t p = s->np++;
   s->ze[p] = ze; s->xe[p] = xe; s->ye[p] = ye;
   s->uz[p] = uz; s->ux[p] = ux; s->uy[p] = uy;
   s->zi[p] = zi; s->xi[p] = xi; s->yi[p] = yi;
   s->w[p] = w; s->id[p] = id;
+}
+
+int orc_add_pair(orc_sim* s, double ze, double xe, double ye, double uz, double ux, double uy,
+                 double zi, double xi, double yi, double w, int64_t id) {
+  store_pair(s, ze, xe, ye, uz, ux, uy, zi, xi, yi, w, id);
   return 0;
 }
 
 void orc_clear_particles(orc_sim* s) { s->np = 0; }
 
-static double drift_cells(const orc_sim* s) {
+/* D = step * s_b + window cells, with s_b = beta_b dt / dz rounded once to
+ * FP64 (the step the partners take) and the product formed in extended
+ * precision, as the partners' positions accumulate it. */
+static xpos drift_cells_x(const orc_sim* s) {
   double bb = orc_beta_of_gamma(s->c.gamma_b);
   double sb = (bb * s->c.dt) / s->c.dz;
-  return (double)s->step * sb + s->window_cells;
+  return (xpos)s->step * (xpos)sb + (xpos)s->window_cells;
 }
+static double drift_cells(const orc_sim* s) { return (double)drift_cells_x(s); }
 
-static void add_column(orc_sim* s, int64_t k, double D) {
+static void add_column(orc_sim* s, int64_t k, xpos D) {
   const orc_config* c = &s->c;
   int d3 = c->dim == 3;
   double ub = orc_drift_u(c->gamma_b);
@@ -765,18 +808,19 @@ static void add_column(orc_sim* s, int64_t k, double D) {
           ry = d3 ? orc_cell_offset(c->seed, k, l, j, q, 2, c->nx, s->nyy, c->ppc) : 0.0;
         }
         double zl = c->gamma_b * ((double)k + rz) * c->dz;
-        double z = ((double)k + rz) - D, x = (double)j + rx, y = (double)l + ry;
+        xpos z = ((xpos)k + (xpos)rz) - D;
+        double x = (double)j + rx, y = (double)l + ry;
         double w = c->gamma_b * lab_density(s, zl) * channel_factor(s, x, y) * dV / (double)c->ppc;
         int64_t id = ((k * s->nyy + l) * c->nx + j) * c->ppc + q;
-        orc_add_pair(s, z, x, y, ub + s->du0[2], s->du0[0], s->du0[1], z, x, y, w, id);
+        store_pair(s, z, x, y, ub + s->du0[2], s->du0[0], s->du0[1], z, x, y, w, id);
       }
 }
 
 /* Continuous injection: column k enters once its low edge k - D is below nz. */
 static void inject_due(orc_sim* s) {
   if (!s->has_plasma || s->c.zbc == 0) return;
-  double D = drift_cells(s);
-  while ((double)s->next_col - D < (double)s->c.nz) {
+  xpos D = drift_cells_x(s);
+  while ((xpos)s->next_col - D < (xpos)s->c.nz) {
     add_column(s, s->next_col, D);
     s->next_col++;
   }
@@ -801,8 +845,10 @@ void orc_destroy(orc_sim* s) {
   if (!s) return;
   for (int a = 0; a < ORC_NCOMP; a++) free(s->F[a]);
   free(s->rho);
-  double* arrs[10] = {s->ze, s->xe, s->ye, s->uz, s->ux, s->uy, s->zi, s->xi, s->yi, s->w};
-  for (int a = 0; a < 10; a++) free(arrs[a]);
+  xpos* pos[6] = {s->ze, s->xe, s->ye, s->zi, s->xi, s->yi};
+  for (int a = 0; a < 6; a++) free(pos[a]);
+  double* arrs[4] = {s->uz, s->ux, s->uy, s->w};
+  for (int a = 0; a < 4; a++) free(arrs[a]);
   free(s->id);
   free(s->kz);
   free(s->kn);
@@ -942,7 +988,7 @@ int orc_step(orc_sim* s, int32_t nsteps) {
       double* const Jt[3] = {th ? s->tJ[3 * (th - 1) + 0] : s->F[ORC_JX],
                              th ? s->tJ[3 * (th - 1) + 1] : s->F[ORC_JY],
                              th ? s->tJ[3 * (th - 1) + 2] : s->F[ORC_JZ]};
-      double z0 = s->ze[p], x0 = s->xe[p], y0 = s->ye[p];
+      xpos z0 = s->ze[p], x0 = s->xe[p], y0 = s->ye[p];
       double E[3], B[3];
       E[0] = gather(s, ORC_EX, z0, x0, y0);
       E[1] = gather(s, ORC_EY, z0, x0, y0);
@@ -954,22 +1000,22 @@ int orc_step(orc_sim* s, int32_t nsteps) {
       orc_boris(-1.0, c->dt, E, B, u);
       double g = sqrt(1.0 + u[0] * u[0] + u[1] * u[1] + u[2] * u[2]);
       double vx = u[0] / g, vy = u[1] / g, vz = u[2] / g;
-      double z1 = z0 + vz * c->dt / c->dz;
-      double x1 = x0 + vx * c->dt / c->dx;
-      double y1 = d3 ? y0 + vy * c->dt / c->dy : y0;
+      xpos z1 = z0 + (xpos)(vz * c->dt / c->dz);
+      xpos x1 = x0 + (xpos)(vx * c->dt / c->dx);
+      xpos y1 = d3 ? y0 + (xpos)(vy * c->dt / c->dy) : y0;
       if (d3) deposit_3d(s, Jt, -1.0, s->w[p], z0, x0, y0, z1, x1, y1);
       else deposit_2d(s, Jt, -1.0, s->w[p], vy, z0, x0, z1, x1);
       s->ux[p] = u[0];
       s->uy[p] = u[1];
       s->uz[p] = u[2];
-      s->ze[p] = c->zbc == 0 ? z1 - c->nz * floor(z1 / c->nz) : z1;
-      s->xe[p] = x1 - c->nx * floor(x1 / c->nx);
-      s->ye[p] = d3 ? y1 - c->ny * floor(y1 / c->ny) : y1;
+      s->ze[p] = c->zbc == 0 ? z1 - (xpos)c->nz * floorl(z1 / (xpos)c->nz) : z1;
+      s->xe[p] = x1 - (xpos)c->nx * floorl(x1 / (xpos)c->nx);
+      s->ye[p] = d3 ? y1 - (xpos)c->ny * floorl(y1 / (xpos)c->ny) : y1;
       if (c->ions && sb != 0.0) {
-        double zi0 = s->zi[p], zi1 = zi0 - sb;
+        xpos zi0 = s->zi[p], zi1 = zi0 - (xpos)sb;
         if (d3) deposit_3d(s, Jt, 1.0, s->w[p], zi0, s->xi[p], s->yi[p], zi1, s->xi[p], s->yi[p]);
         else deposit_2d(s, Jt, 1.0, s->w[p], 0.0, zi0, s->xi[p], zi1, s->xi[p]);
-        s->zi[p] = c->zbc == 0 ? zi1 - c->nz * floor(zi1 / c->nz) : zi1;
+        s->zi[p] = c->zbc == 0 ? zi1 - (xpos)c->nz * floorl(zi1 / (xpos)c->nz) : zi1;
       }
     }
     for (int t = 1; t < nt; t++)
@@ -990,8 +1036,8 @@ int orc_step(orc_sim* s, int32_t nsteps) {
       double lim = (double)(c->order + 1);
       int64_t q = 0;
       for (int64_t p = 0; p < s->np; p++) {
-        int eout = s->ze[p] < -lim || s->ze[p] > c->nz + lim;
-        int iout = !c->ions || s->zi[p] < -lim || s->zi[p] > c->nz + lim;
+        int eout = s->ze[p] < -lim || s->ze[p] > (xpos)(c->nz + lim);
+        int iout = !c->ions || s->zi[p] < -lim || s->zi[p] > (xpos)(c->nz + lim);
         if (eout && iout) continue;
         if (q != p) {
           s->ze[q] = s->ze[p]; s->xe[q] = s->xe[p]; s->ye[q] = s->ye[p];
@@ -1040,7 +1086,7 @@ int orc_diagnostics(orc_sim* s, orc_diag* o, double* lineout) {
   for (int64_t p = 0; p < s->np; p++) {
     double u2 = s->ux[p] * s->ux[p] + s->uy[p] * s->uy[p] + s->uz[p] * s->uz[p];
     double g = sqrt(1.0 + u2);
-    if (!isfinite(g) || !isfinite(s->ze[p]) || !isfinite(s->xe[p])) nanf = 1;
+    if (!isfinite(g) || !isfinite((double)s->ze[p]) || !isfinite((double)s->xe[p])) nanf = 1;
     ukin += s->w[p] * (g - 1.0);
     ukd += s->w[p] * (g - gb);
     charge += -s->w[p];
@@ -1120,13 +1166,15 @@ int64_t orc_num_pairs(const orc_sim* s) { return s->np; }
 int orc_get_particles(const orc_sim* s, double* ze, double* xe, double* ye, double* uz,
                       double* ux, double* uy, double* zi, double* w, int64_t* id) {
   size_t nb = sizeof(double) * (size_t)s->np;
-  if (ze) memcpy(ze, s->ze, nb);
-  if (xe) memcpy(xe, s->xe, nb);
-  if (ye) memcpy(ye, s->ye, nb);
+  for (int64_t p = 0; p < s->np; p++) {
+    if (ze) ze[p] = (double)s->ze[p];
+    if (xe) xe[p] = (double)s->xe[p];
+    if (ye) ye[p] = (double)s->ye[p];
+    if (zi) zi[p] = (double)s->zi[p];
+  }
   if (uz) memcpy(uz, s->uz, nb);
   if (ux) memcpy(ux, s->ux, nb);
   if (uy) memcpy(uy, s->uy, nb);
-  if (zi) memcpy(zi, s->zi, nb);
   if (w) memcpy(w, s->w, nb);
   if (id) memcpy(id, s->id, sizeof(int64_t) * (size_t)s->np);
   return 0;
@@ -1142,12 +1190,12 @@ int orc_sort_keys(const orc_sim* s, int32_t tz, int32_t tx, int32_t ty, int64_t 
   int d3 = c->dim == 3;
   if (!d3) ty = 1;
   int64_t ntx = c->nx / tx, nty = d3 ? c->ny / ty : 1;
-  double D = drift_cells(s);
+  xpos D = drift_cells_x(s);
   for (int64_t p = 0; p < s->np; p++) {
-    int64_t kz = (int64_t)floor(s->ze[p] + D);
+    int64_t kz = (int64_t)floorl(s->ze[p] + D);
     if (c->zbc == 0) kz = wrapi(kz, c->nz);
-    int64_t kx = wrapi((int64_t)floor(s->xe[p]), c->nx);
-    int64_t ky = d3 ? wrapi((int64_t)floor(s->ye[p]), c->ny) : 0;
+    int64_t kx = wrapi((int64_t)floorl(s->xe[p]), c->nx);
+    int64_t ky = d3 ? wrapi((int64_t)floorl(s->ye[p]), c->ny) : 0;
     int64_t rz = kz - tz_min * tz;
     if (rz < 0) rz = 0;
     if (rz >= (int64_t)ntz * tz) rz = (int64_t)ntz * tz - 1;

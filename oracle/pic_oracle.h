@@ -125,8 +125,10 @@ int orc_init(orc_sim* s, const orc_density* dens, const orc_laser* laser, int32_
 int orc_step(orc_sim* s, int32_t nsteps);
 int orc_window_shift(orc_sim* s, int32_t ncells);
 int orc_diagnostics(orc_sim* s, orc_diag* out, double* lineout /* nz or NULL */);
-/* Threads of the particle loop (OpenMP, per-thread current buffers summed
- * after the loop); 1 by default.  -1 for n < 1, or n > 1 in a build without
+/* Threads (OpenMP) of the particle loop, whose per-thread current buffers
+ * are summed after it, and of the laser initialisation, filter passes and
+ * Yee updates, whose iterations write disjoint nodes; 1 by default.  Set
+ * before orc_init for the laser.  -1 for n < 1, or n > 1 in a build without
  * OpenMP.  orc_max_threads: the OpenMP default thread count (1 without). */
 int orc_set_threads(orc_sim* s, int32_t n);
 int32_t orc_max_threads(void);
