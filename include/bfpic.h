@@ -254,6 +254,23 @@ int bfpic_window_due(bfpic_ctx* h, int32_t* ncells);
  * mask is reserved (pass 0xffffffff).  Synchronises the stream. */
 int diagnostics(bfpic_ctx* h, uint32_t mask, bfpic_diag* out, double* lineout_dev);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid allocation): the same
+ * diagnostics as diagnostics(), with the same arguments and results, whose
+ * reduction scratch (block partials, final values, non-finite flag) lives
+ * in a static device array of 32 KiB that the library holds on each device
+ * until the process ends, instead of the context's workspace.  The charge
+ * grids of the Gauss residual are the context's own, inside the workspace
+ * the caller passed to bfpic_create.  The call allocates nothing and clears
+ * what it reads with fill kernels (no memset).  Every call on one device
+ * shares that array: calls that overlap on one device (contexts on
+ * different streams, or different threads) race and must be serialised by
+ * the caller.  ERR_STATE if the context's device is not current or before
+ * init; ERR_HIP if the array's device address cannot be resolved;
+ * ERR_ARG if the reductions would need more than the array holds (they are
+ * capped below it).  Synchronises the stream. */
+int diagnostics_noalloc(bfpic_ctx* h, uint32_t mask, bfpic_diag* out, double* lineout_dev);
+
 /* ---- lab-frame and spectral diagnostics of the on-axis laser field ---- */
 
 /* Where and when a record was taken: boosted-frame time t' = step dt, the

@@ -89,7 +89,8 @@ _lib = None
 EXPORTS = ["bfpic_beta", "bfpic_drift_u", "bfpic_group_gamma", "bfpic_boosted_group_beta",
            "bfpic_boosted_dz", "bfpic_yee_dt", "bfpic_query_sizes", "bfpic_create",
            "bfpic_destroy", "bfpic_last_error", "init_boosted_plasma", "pic_step",
-           "moving_window_shift", "bfpic_window_due", "diagnostics", "bfpic_get_field",
+           "moving_window_shift", "bfpic_window_due", "diagnostics", "diagnostics_noalloc",
+           "bfpic_get_field",
            "bfpic_set_field", "bfpic_num_slots", "bfpic_get_particles", "bfpic_sort",
            "bfpic_last_sort", "bfpic_sort_permutation", "bfpic_tile_shape", "bfpic_kernel_timing", "bfpic_kernel_time",
            "bfpic_adjoint_tape_bytes", "bfpic_forward_loss", "pic_step_adjoint",
@@ -121,6 +122,7 @@ def lib():
         "pic_step": (C.c_int, [p, i32]), "moving_window_shift": (C.c_int, [p, i32]),
         "bfpic_window_due": (C.c_int, [p, C.POINTER(i32)]),
         "diagnostics": (C.c_int, [p, C.c_uint32, C.POINTER(Diag), p]),
+        "diagnostics_noalloc": (C.c_int, [p, C.c_uint32, C.POINTER(Diag), p]),
         "bfpic_get_field": (C.c_int, [p, i32, p]), "bfpic_set_field": (C.c_int, [p, i32, p]),
         "bfpic_num_slots": (C.c_int, [p, C.POINTER(i64)]),
         "bfpic_get_particles": (C.c_int, [p] * 9),
@@ -255,12 +257,15 @@ class Simulation:
         _check(lib().bfpic_window_due(self.h, C.byref(n)), self.h)
         return n.value
 
-    def diagnostics(self, lineout=False) -> dict:
+    def diagnostics(self, lineout=False, noalloc=False) -> dict:
+        """FP64 diagnostics; noalloc=True calls diagnostics_noalloc (static
+        device scratch) instead of diagnostics."""
         import torch
         d = Diag()
         lo = torch.zeros(self.cfg.nz, dtype=torch.float64, device=self.device) if lineout else None
-        _check(lib().diagnostics(self.h, 0xFFFFFFFF, C.byref(d),
-                                 C.c_void_p(lo.data_ptr()) if lo is not None else None), self.h)
+        fn = lib().diagnostics_noalloc if noalloc else lib().diagnostics
+        _check(fn(self.h, 0xFFFFFFFF, C.byref(d),
+                  C.c_void_p(lo.data_ptr()) if lo is not None else None), self.h)
         out = d.as_dict()
         if lineout:
             out["lineout"] = lo.cpu().numpy()

@@ -9,6 +9,7 @@
 #include <cmath>
 #include <cstdio>
 #include <cstring>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -23,6 +24,35 @@
 #include "kernels_witness.hpp"
 
 using namespace bfpic;
+
+// ---------------------------------------------------------------------------
+// Static device scratch of diagnostics_noalloc: the block partials of its
+// reductions, its final values and its non-finite flag.  Each device that
+// runs the library holds one copy until the process ends; every call on a
+// device shares it (calls that overlap on one device race).  Host code never
+// passes the array's name to a kernel: it uses the address that
+// hipGetSymbolAddress returns for the current device.
+// ---------------------------------------------------------------------------
+constexpr int64_t kStaticScratchBytes = 32768;
+static __device__ __align__(256) unsigned char scratch[kStaticScratchBytes];
+constexpr int kMaxDevices = 64;
+static std::mutex g_scratch_mu;
+static void* g_scratch_ptr[kMaxDevices] = {};
+
+// Address of `scratch` on device dev (which must be current), resolved once.
+static hipError_t static_scratch_of(int dev, void** out) {
+  *out = nullptr;
+  if (dev < 0 || dev >= kMaxDevices) return hipErrorInvalidDevice;
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (!g_scratch_ptr[dev]) {
+    void* ptr = nullptr;
+    hipError_t e = hipGetSymbolAddress((void**)&ptr, HIP_SYMBOL(scratch));
+    if (e != hipSuccess) return e;
+    g_scratch_ptr[dev] = ptr;
+  }
+  *out = g_scratch_ptr[dev];
+  return hipSuccess;
+}
 
 // ---------------------------------------------------------------------------
 // Boost helper (host FP64).  Frame change along +z by rapidity artanh(beta_b).
@@ -95,6 +125,7 @@ static inline int floor_div(int a, int b) { return a >= 0 ? a / b : -((b - 1 - a
 struct bfpic_ctx {
   bfpic_config cfg;
   hipStream_t stream = nullptr;
+  int device = -1;  // HIP device current at create
   std::string err;
   int dim = 2, nz = 0, nx = 0, ny = 1, order = 1;
   bool fp64 = false;
@@ -393,7 +424,7 @@ static int64_t plan(bfpic_ctx* h, int64_t cap, bfpic_ctx* fill, bfpic_sizes* sz)
   if (fill) fill->g64a = (double*)p;
   p = P(grid * 8);
   if (fill) fill->g64b = (double*)p;
-  p = P(4096 * 4 * 8);
+  p = P(7 * kDiagMaxBlocks * 8);
   if (fill) fill->partials = (double*)p;
   p = P(16 * 8);
   if (fill) fill->dout = (double*)p;
@@ -1523,21 +1554,61 @@ struct Impl {
     return BFPIC_OK;
   }
 
+  // Reduction buffers of the diagnostics: block partials of the field sums
+  // (2 per block), particle sums (4 per block) and Gauss maxima (1 per
+  // block), the final values and the non-finite flag.
+  struct DiagBufs {
+    double *pf, *pp, *pg, *dout;
+    int* nanflag;
+  };
+  // Blocks per reduction: one per 2048 items, at most kDiagMaxBlocks.
+  static int diag_blocks(int64_t items) {
+    return (int)std::max<int64_t>(1, std::min<int64_t>(kDiagMaxBlocks, cdiv(items, 2048)));
+  }
+
   static int diag(bfpic_ctx* h, bfpic_diag* o, double* lineout) {
+    DiagBufs B{h->partials, h->partials + 2 * kDiagMaxBlocks, h->partials + 6 * kDiagMaxBlocks,
+               h->dout, h->nanflag};
+    return diag_with(h, o, lineout, B);
+  }
+
+  // The same diagnostics with every reduction buffer in the static scratch
+  // at `base` (device address of `scratch` on the context's device).
+  static int diag_static(bfpic_ctx* h, bfpic_diag* o, double* lineout, uint8_t* base) {
+    DiagBufs B;
+    B.nanflag = (int*)base;
+    B.dout = (double*)(base + 256);
+    B.pf = B.dout + 16;
+    B.pp = B.pf + 2 * kDiagMaxBlocks;
+    B.pg = B.pp + 4 * kDiagMaxBlocks;
+    const int64_t need = (int64_t)((uint8_t*)(B.pg + kDiagMaxBlocks) - base);
+    if (need > kStaticScratchBytes)
+      return fail(h, BFPIC_ERR_ARG, "diagnostics need " + std::to_string(need) +
+                                        " bytes of static scratch, above its " +
+                                        std::to_string(kStaticScratchBytes));
+    return diag_with(h, o, lineout, B);
+  }
+
+  static int diag_with(bfpic_ctx* h, bfpic_diag* o, double* lineout, const DiagBufs& B) {
     const Geo& g = h->g;
     Fields<R> F = fields(h);
     PSoA<R> S = soa(h, h->cur);
-    double* pf = h->partials;
-    double* pp = h->partials + 2 * 1024;
-    double* pg = h->partials + 6 * 1024;
-    HIPCHK(h, hipMemsetAsync(h->nanflag, 0, 4, h->stream));
-    const int nbf = 512, nbp = 512, nbg = 512;
-    k_diag_fields<R><<<nbf, kDiagBlock, 0, h->stream>>>(g, F, pf, h->nanflag);
-    k_diag_particles<R, DIM><<<nbp, kDiagBlock, 0, h->stream>>>(S, h->counts, h->u_b, h->gamma_b,
-                                                                pp, h->nanflag);
+    double* pf = B.pf;
+    double* pp = B.pp;
+    double* pg = B.pg;
     const int64_t grid = g.rows * g.plane;
-    HIPCHK(h, hipMemsetAsync(h->g64a, 0, grid * 8, h->stream));
-    HIPCHK(h, hipMemsetAsync(h->g64b, 0, grid * 8, h->stream));
+    // cleared by fill kernels, so that no memset node enters a captured graph
+    k_zero_f64<<<1, 64, 0, h->stream>>>((double*)B.nanflag, 1);
+    k_zero_f64<<<(unsigned)std::min<int64_t>(cdiv(grid, 256), 4096), 256, 0, h->stream>>>(
+        h->g64a, grid);
+    k_zero_f64<<<(unsigned)std::min<int64_t>(cdiv(grid, 256), 4096), 256, 0, h->stream>>>(
+        h->g64b, grid);
+    const int nbf = diag_blocks((int64_t)(h->nz + 1) * g.plane);
+    const int nbp = diag_blocks(h->slots_bound);
+    const int nbg = diag_blocks((int64_t)(h->nz + 1) * g.plane);
+    k_diag_fields<R><<<nbf, kDiagBlock, 0, h->stream>>>(g, F, pf, B.nanflag);
+    k_diag_particles<R, DIM><<<nbp, kDiagBlock, 0, h->stream>>>(S, h->counts, h->u_b, h->gamma_b,
+                                                                pp, B.nanflag);
     double dV = h->dz * h->dx * (DIM == 3 ? h->dy : 1.0);
     if (h->slots_bound > 0)
       k_rho<R, DIM, ORDER><<<(unsigned)cdiv(h->slots_bound, 256), 256, 0, h->stream>>>(
@@ -1567,14 +1638,14 @@ struct Impl {
       k_gauss<R, DIM><<<nbg, kDiagBlock, 0, h->stream>>>(g, F, h->g64b, 1.0 / h->dz, 1.0 / h->dx,
                                                          1.0 / h->dy, lo, hi, pg);
     else
-      HIPCHK(h, hipMemsetAsync(pg, 0, nbg * 8, h->stream));
+      k_zero_f64<<<1, 256, 0, h->stream>>>(pg, nbg);
     k_diag_final<R><<<1, kDiagBlock, 0, h->stream>>>(g, (const R*)h->F[2], pf, nbf, pp, nbp, pg,
-                                                     nbg, h->dout, lineout);
+                                                     nbg, B.dout, lineout);
     HIPCHK(h, hipGetLastError());
     double out[8];
     int nanf = 0;
-    HIPCHK(h, hipMemcpyAsync(out, h->dout, sizeof(out), hipMemcpyDeviceToHost, h->stream));
-    HIPCHK(h, hipMemcpyAsync(&nanf, h->nanflag, 4, hipMemcpyDeviceToHost, h->stream));
+    HIPCHK(h, hipMemcpyAsync(out, B.dout, sizeof(out), hipMemcpyDeviceToHost, h->stream));
+    HIPCHK(h, hipMemcpyAsync(&nanf, B.nanflag, 4, hipMemcpyDeviceToHost, h->stream));
     HIPCHK(h, hipStreamSynchronize(h->stream));
     o->step = h->step;
     o->t = (double)h->step * h->dt;
@@ -1696,9 +1767,15 @@ extern "C" int bfpic_create(const bfpic_config* cfg, int64_t cap, void* workspac
   plan(h, cap, h, nullptr);
   h->stream = (hipStream_t)stream;
   int dev = 0, lds = 65536;
-  if (hipGetDevice(&dev) == hipSuccess &&
-      hipDeviceGetAttribute(&lds, hipDeviceAttributeMaxSharedMemoryPerBlock, dev) == hipSuccess)
-    h->lds_limit = (size_t)lds;
+  if (hipGetDevice(&dev) == hipSuccess) {
+    h->device = dev;
+    if (hipDeviceGetAttribute(&lds, hipDeviceAttributeMaxSharedMemoryPerBlock, dev) == hipSuccess)
+      h->lds_limit = (size_t)lds;
+    // set-up of the static scratch on this device (retried by its first
+    // use if it fails here)
+    void* sp = nullptr;
+    (void)static_scratch_of(dev, &sp);
+  }
   if (h->lds_tiled > h->lds_limit && h->dim == 3) {
     // 3D tiles whose staged fields do not fit: gather from global memory and
     // keep only the FP64 (or int64) currents in LDS
@@ -1777,6 +1854,22 @@ extern "C" int diagnostics(bfpic_ctx* h, uint32_t mask, bfpic_diag* out, double*
   if (!h || !out) return BFPIC_ERR_ARG;
   if (!h->inited) return fail(h, BFPIC_ERR_STATE, "diagnostics before init");
   BFPIC_DISPATCH(h, I::diag(h, out, lineout));
+}
+
+extern "C" int diagnostics_noalloc(bfpic_ctx* h, uint32_t mask, bfpic_diag* out,
+                                   double* lineout) {
+  (void)mask;
+  if (!h || !out) return BFPIC_ERR_ARG;
+  if (!h->inited) return fail(h, BFPIC_ERR_STATE, "diagnostics before init");
+  int cur = -1;
+  HIPCHK(h, hipGetDevice(&cur));
+  if (cur != h->device) return fail(h, BFPIC_ERR_STATE, "the context's device is not current");
+  void* base = nullptr;
+  hipError_t e = static_scratch_of(cur, &base);
+  if (e != hipSuccess)
+    return fail(h, BFPIC_ERR_HIP, std::string("hipGetSymbolAddress(scratch): ") +
+                                      hipGetErrorString(e));
+  BFPIC_DISPATCH(h, I::diag_static(h, out, lineout, (uint8_t*)base));
 }
 
 extern "C" int bfpic_axis_record(bfpic_ctx* h, int32_t frame, double* out, bfpic_axis_meta* meta) {

@@ -9,6 +9,14 @@
 namespace bfpic {
 
 constexpr int kDiagBlock = 256;
+constexpr int kDiagMaxBlocks = 512;
+
+// p[0..n) = 0 (a fill kernel rather than a memset node).
+__global__ __launch_bounds__(256) void k_zero_f64(double* p, int64_t n) {
+  for (int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; q < n;
+       q += (int64_t)gridDim.x * blockDim.x)
+    p[q] = 0.0;
+}
 
 template <int N>
 __device__ __forceinline__ void block_sum(double (&v)[N], double* sh) {
