@@ -56,6 +56,7 @@ extern "C" {
 enum { BFPIC_FP64 = 0, BFPIC_FP32_SPLIT = 1 };
 enum { BFPIC_BC_PERIODIC = 0, BFPIC_BC_MUR = 1 };
 enum { BFPIC_LOAD_RANDOM = 0, BFPIC_LOAD_CENTERED = 1 };
+enum { BFPIC_GATHER_MOMENTUM = 0, BFPIC_GATHER_ENERGY = 1 };
 
 /* Field component ids for bfpic_get_field / bfpic_set_field. */
 enum { BFPIC_EX = 0, BFPIC_EY, BFPIC_EZ, BFPIC_BX, BFPIC_BY, BFPIC_BZ,
@@ -82,6 +83,21 @@ typedef struct bfpic_config {
   uint64_t seed;             /* generator key of the in-cell positions */
   double beta_window;        /* window speed along +z (calculation frame) */
   int32_t auto_window;       /* 1: pic_step shifts the window on schedule */
+  int32_t gather_form;       /* BFPIC_GATHER_MOMENTUM: every field component
+                                interpolated with the deposit's shape on every
+                                axis (momentum-conserving).  BFPIC_GATHER_ENERGY
+                                (Galerkin, energy-conserving): along each axis
+                                on which a component sits at half-integer nodes
+                                it takes the shape of one order lower (nearest
+                                half node for linear shapes, linear for
+                                quadratic), the shape the charge-conserving
+                                current of that component has along that axis.
+                                One of the numerical levers against the
+                                drifting-plasma instability (section
+                                "Mitigation of a numerical instability": the
+                                instability depends on the scheme's
+                                smoothing and damping).  Witness electrons use
+                                the same form. */
 } bfpic_config;
 
 /* Lab-frame plasma density.  nknots == 0: n_uniform everywhere.  nknots >= 2:

@@ -41,7 +41,8 @@ class Config(C.Structure):
                 ("order", C.c_int32), ("filter_passes", C.c_int32),
                 ("filter_compensate", C.c_int32), ("zbc", C.c_int32), ("ppc", C.c_int32),
                 ("seed", C.c_uint64), ("gamma_b", C.c_double), ("beta_window", C.c_double),
-                ("auto_window", C.c_int32), ("ions", C.c_int32), ("load", C.c_int32)]
+                ("auto_window", C.c_int32), ("ions", C.c_int32), ("load", C.c_int32),
+                ("gather", C.c_int32)]
 
 
 class Density(C.Structure):
@@ -174,12 +175,12 @@ class Sim:
 
     def __init__(self, dim=2, nz=16, nx=16, ny=1, dz=1.0, dx=1.0, dy=1.0, dt=0.5, order=1,
                  filter_passes=0, filter_compensate=0, zbc=0, ppc=1, seed=0, gamma_b=1.0,
-                 beta_window=0.0, auto_window=0, ions=1, load=0):
+                 beta_window=0.0, auto_window=0, ions=1, load=0, gather=0):
         c = Config(dim=dim, nz=nz, nx=nx, ny=ny if dim == 3 else 1, dz=dz, dx=dx, dy=dy, dt=dt,
                    order=order, filter_passes=filter_passes,
                    filter_compensate=filter_compensate, zbc=zbc, ppc=ppc, seed=seed,
                    gamma_b=gamma_b, beta_window=beta_window, auto_window=auto_window, ions=ions,
-                   load=load)
+                   load=load, gather=gather)
         self.cfg = c
         self.h = lib().orc_create(C.byref(c))
         self.shape = (nz + 1, nx, (ny if dim == 3 else 1))

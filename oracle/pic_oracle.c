@@ -52,6 +52,13 @@ static const double SIG[ORC_NCOMP][3] = {
 
 typedef long double xpos; /* particle coordinates (see the conventions above) */
 
+/* floor of an extended-precision coordinate as an integer: truncation toward
+ * zero, one lower for a negative non-integer (|x| < 2^62) */
+static int64_t ifloorx(xpos x) {
+  int64_t i = (int64_t)x;
+  return x < (xpos)i ? i - 1 : i;
+}
+
 struct orc_sim {
   orc_config c;
   int nyy;        /* ny in 3D, 1 in 2D */
@@ -163,10 +170,13 @@ double orc_cell_offset(uint64_t seed, int64_t k, int64_t l, int64_t j, int32_t s
 }
 
 /* ------------------------------------------------------------------------ */
-/* Shape functions: linear S1 = max(0, 1-|d|) and the quadratic B-spline.    */
+/* Shape functions: the B-splines of order 0 (nearest grid point: 1 on        */
+/* [-1/2, 1/2), the half-open cell of the node), 1 (linear, max(0, 1-|d|))    */
+/* and 2 (quadratic).                                                          */
 /* ------------------------------------------------------------------------ */
 double orc_shape(int32_t order, double d) {
   double a = fabs(d);
+  if (order == 0) return (d >= -0.5 && d < 0.5) ? 1.0 : 0.0;
   if (order == 1) return a < 1.0 ? 1.0 - a : 0.0;
   if (a <= 0.5) return 0.75 - a * a;
   if (a < 1.5) {
@@ -269,27 +279,38 @@ static int in_domain(const orc_sim* s, double sz, int64_t i) {
 
 /* ------------------------------------------------------------------------ */
 /* Gather: F_p = sum_nodes F(node) S(z - i - sz) S(x - j - sx) [S(y - k - sy)]*/
-/* with the deposit's shape order (momentum-conserving gather).               */
+/* Momentum-conserving form: every axis with the deposit's shape order.      */
+/* Energy-conserving (Galerkin) form: an axis on which the component sits at */
+/* half-integer nodes (s = 1/2) takes the shape of one order lower, the      */
+/* shape that the charge-conserving current of that component has along it   */
+/* (Esirkepov's J_z is a z-difference of the charge shape, so along z it      */
+/* carries the integral of S^l, a shape of order l - 1 on the half nodes).    */
 /* ------------------------------------------------------------------------ */
+static int axis_order(const orc_sim* s, int comp, int axis) {
+  int o = s->c.order;
+  return (s->c.gather == 1 && SIG[comp][axis] == 0.5) ? o - 1 : o;
+}
+
 static double gather(const orc_sim* s, int comp, xpos z, xpos x, xpos y) {
   const orc_config* c = &s->c;
+  const int oz = axis_order(s, comp, 0), ox = axis_order(s, comp, 1), oy = axis_order(s, comp, 2);
   xpos pz = z - SIG[comp][0], px = x - SIG[comp][1], py = y - SIG[comp][2];
-  int64_t i0 = (int64_t)floorl(pz) - 2, j0 = (int64_t)floorl(px) - 2;
-  int64_t k0 = (int64_t)floorl(py) - 2;
+  int64_t i0 = ifloorx(pz) - 2, j0 = ifloorx(px) - 2;
+  int64_t k0 = ifloorx(py) - 2;
   /* offsets from the stencil base, small enough for FP64 */
   double lz = (double)(pz - (xpos)i0), lx = (double)(px - (xpos)j0), ly = (double)(py - (xpos)k0);
   double sum = 0.0;
   for (int a = 0; a < 6; a++) {
-    double wz = orc_shape(c->order, lz - (double)a);
+    double wz = orc_shape(oz, lz - (double)a);
     if (wz == 0.0) continue;
     for (int b = 0; b < 6; b++) {
-      double wx = orc_shape(c->order, lx - (double)b);
+      double wx = orc_shape(ox, lx - (double)b);
       if (wx == 0.0) continue;
       if (c->dim == 2) {
         sum += fget(s, comp, i0 + a, j0 + b, 0) * wz * wx;
       } else {
         for (int d = 0; d < 6; d++) {
-          double wy = orc_shape(c->order, ly - (double)d);
+          double wy = orc_shape(oy, ly - (double)d);
           if (wy == 0.0) continue;
           sum += fget(s, comp, i0 + a, j0 + b, k0 + d) * wz * wx * wy;
         }
@@ -314,8 +335,8 @@ static double gather(const orc_sim* s, int comp, xpos z, xpos x, xpos y) {
 
 static void shape_row(int order, xpos p0, xpos p1, int64_t* lo, int* n, double* S0,
                       double* S1) {
-  int64_t a = (int64_t)floorl(p0 < p1 ? p0 : p1) - 2;
-  int64_t b = (int64_t)floorl(p0 > p1 ? p0 : p1) + 3;
+  int64_t a = ifloorx(p0 < p1 ? p0 : p1) - 2;
+  int64_t b = ifloorx(p0 > p1 ? p0 : p1) + 3;
   *lo = a;
   *n = (int)(b - a + 1);
   if (*n > STN) *n = STN; /* displacements are below one cell per step */
@@ -415,7 +436,7 @@ static void deposit_3d(const orc_sim* s, double* const* J, double q, double w, x
 static void deposit_rho(orc_sim* s, double* R, double q, double w, xpos z, xpos x, xpos y) {
   const orc_config* c = &s->c;
   double dV = c->dz * c->dx * (c->dim == 3 ? c->dy : 1.0);
-  int64_t i0 = (int64_t)floorl(z) - 2, j0 = (int64_t)floorl(x) - 2, k0 = (int64_t)floorl(y) - 2;
+  int64_t i0 = ifloorx(z) - 2, j0 = ifloorx(x) - 2, k0 = ifloorx(y) - 2;
   double lz = (double)(z - (xpos)i0), lx = (double)(x - (xpos)j0), ly = (double)(y - (xpos)k0);
   for (int a = 0; a < 6; a++) {
     double wz = orc_shape(c->order, lz - (double)a);
@@ -1008,14 +1029,14 @@ int orc_step(orc_sim* s, int32_t nsteps) {
       s->ux[p] = u[0];
       s->uy[p] = u[1];
       s->uz[p] = u[2];
-      s->ze[p] = c->zbc == 0 ? z1 - (xpos)c->nz * floorl(z1 / (xpos)c->nz) : z1;
-      s->xe[p] = x1 - (xpos)c->nx * floorl(x1 / (xpos)c->nx);
-      s->ye[p] = d3 ? y1 - (xpos)c->ny * floorl(y1 / (xpos)c->ny) : y1;
+      s->ze[p] = c->zbc == 0 ? z1 - (xpos)c->nz * (xpos)ifloorx(z1 / (xpos)c->nz) : z1;
+      s->xe[p] = x1 - (xpos)c->nx * (xpos)ifloorx(x1 / (xpos)c->nx);
+      s->ye[p] = d3 ? y1 - (xpos)c->ny * (xpos)ifloorx(y1 / (xpos)c->ny) : y1;
       if (c->ions && sb != 0.0) {
         xpos zi0 = s->zi[p], zi1 = zi0 - (xpos)sb;
         if (d3) deposit_3d(s, Jt, 1.0, s->w[p], zi0, s->xi[p], s->yi[p], zi1, s->xi[p], s->yi[p]);
         else deposit_2d(s, Jt, 1.0, s->w[p], 0.0, zi0, s->xi[p], zi1, s->xi[p]);
-        s->zi[p] = c->zbc == 0 ? zi1 - (xpos)c->nz * floorl(zi1 / (xpos)c->nz) : zi1;
+        s->zi[p] = c->zbc == 0 ? zi1 - (xpos)c->nz * (xpos)ifloorx(zi1 / (xpos)c->nz) : zi1;
       }
     }
     for (int t = 1; t < nt; t++)
@@ -1192,10 +1213,10 @@ int orc_sort_keys(const orc_sim* s, int32_t tz, int32_t tx, int32_t ty, int64_t 
   int64_t ntx = c->nx / tx, nty = d3 ? c->ny / ty : 1;
   xpos D = drift_cells_x(s);
   for (int64_t p = 0; p < s->np; p++) {
-    int64_t kz = (int64_t)floorl(s->ze[p] + D);
+    int64_t kz = ifloorx(s->ze[p] + D);
     if (c->zbc == 0) kz = wrapi(kz, c->nz);
-    int64_t kx = wrapi((int64_t)floorl(s->xe[p]), c->nx);
-    int64_t ky = d3 ? wrapi((int64_t)floorl(s->ye[p]), c->ny) : 0;
+    int64_t kx = wrapi(ifloorx(s->xe[p]), c->nx);
+    int64_t ky = d3 ? wrapi(ifloorx(s->ye[p]), c->ny) : 0;
     int64_t rz = kz - tz_min * tz;
     if (rz < 0) rz = 0;
     if (rz >= (int64_t)ntz * tz) rz = (int64_t)ntz * tz - 1;

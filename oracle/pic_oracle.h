@@ -59,6 +59,10 @@ typedef struct orc_config {
   int32_t auto_window;       /* 1: shift after each step per the schedule */
   int32_t ions;              /* 1: every electron has a co-located ion partner */
   int32_t load;              /* 0: SplitMix64 in-cell offsets; 1: every slot at the cell centre */
+  int32_t gather;            /* 0: momentum-conserving (every axis with the deposit's
+                                shape); 1: energy-conserving (Galerkin): along each
+                                axis on which a component sits at half-integer
+                                nodes, the shape of one order lower */
 } orc_config;
 
 typedef struct orc_density {

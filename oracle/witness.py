@@ -38,15 +38,18 @@ def gather(F: dict, sim: Sim, z: float, x: float, y: float = 0.0):
     """E, B (x, y, z order) at the position, from component arrays of rows
     0..nz (rows beyond them hold zero fields; periodic z wraps)."""
     c = sim.cfg
-    order = c.order
     dim = c.dim
     periodic = c.zbc == 0
     out = {}
     for name, (sz, sx, sy) in STAGGER.items():
+        # energy-conserving (Galerkin) form: one order lower along each axis
+        # on which the component sits at half-integer nodes
+        oz, ox, oy = (c.order - 1 if (c.gather == 1 and s == 0.5) else c.order
+                      for s in (sz, sx, sy))
         A = F[name]
         acc = 0.0
         for i in range(math.floor(z - sz) - 2, math.floor(z - sz) + 3):
-            wz = shape(order, z - (i + sz))
+            wz = shape(oz, z - (i + sz))
             if wz == 0.0:
                 continue
             if periodic:
@@ -56,13 +59,13 @@ def gather(F: dict, sim: Sim, z: float, x: float, y: float = 0.0):
             else:
                 continue
             for j in range(math.floor(x - sx) - 2, math.floor(x - sx) + 3):
-                wx = shape(order, x - (j + sx))
+                wx = shape(ox, x - (j + sx))
                 if wx == 0.0:
                     continue
                 jj = j % c.nx
                 if dim == 3:
                     for k in range(math.floor(y - sy) - 2, math.floor(y - sy) + 3):
-                        wy = shape(order, y - (k + sy))
+                        wy = shape(oy, y - (k + sy))
                         if wy != 0.0:
                             acc += wz * wx * wy * A[ii, jj, k % c.ny]
                 else:

@@ -18,6 +18,7 @@ LIB_PATH = os.path.join(_HERE, "libbfpic.so")
 FP64, FP32_SPLIT = 0, 1
 BC_PERIODIC, BC_MUR = 0, 1
 LOAD_RANDOM, LOAD_CENTERED = 0, 1
+GATHER_MOMENTUM, GATHER_ENERGY = 0, 1
 COMP = {"Ex": 0, "Ey": 1, "Ez": 2, "Bx": 3, "By": 4, "Bz": 5, "Jx": 6, "Jy": 7, "Jz": 8}
 TIMER = {"gpd_tiled": 0, "gpd_global": 1, "fold_filter": 2, "yee": 3, "sort": 4,
          "inject": 5, "window": 6}
@@ -36,7 +37,8 @@ class Config(C.Structure):
                 ("filter_compensate", C.c_int32), ("precision", C.c_int32),
                 ("deterministic", C.c_int32), ("z_boundary", C.c_int32), ("ppc", C.c_int32),
                 ("load", C.c_int32), ("sort_interval", C.c_int32), ("seed", C.c_uint64),
-                ("beta_window", C.c_double), ("auto_window", C.c_int32)]
+                ("beta_window", C.c_double), ("auto_window", C.c_int32),
+                ("gather_form", C.c_int32)]
 
 
 class Density(C.Structure):
@@ -166,7 +168,7 @@ def make_config(**kw) -> Config:
     base = dict(dim=2, nz=64, nx=32, ny=1, dz=1.0, dx=1.0, dy=1.0, cfl=0.95, shape_order=1,
                 filter_passes=0, filter_compensate=0, precision=FP64, deterministic=0,
                 z_boundary=BC_PERIODIC, ppc=1, load=LOAD_RANDOM, sort_interval=20, seed=0,
-                beta_window=0.0, auto_window=0)
+                beta_window=0.0, auto_window=0, gather_form=GATHER_MOMENTUM)
     base.update(kw)
     for k, v in base.items():
         setattr(c, k, v)

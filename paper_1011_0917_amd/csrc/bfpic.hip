@@ -269,6 +269,8 @@ static int check_cfg(const bfpic_config* c, std::string& why) {
   if (c->z_boundary != BFPIC_BC_PERIODIC && c->z_boundary != BFPIC_BC_MUR) return (why = "z_boundary", 0);
   if (c->ppc < 1) return (why = "ppc", 0);
   if (c->sort_interval < 0) return (why = "sort_interval", 0);
+  if (c->gather_form != BFPIC_GATHER_MOMENTUM && c->gather_form != BFPIC_GATHER_ENERGY)
+    return (why = "gather_form", 0);
   return 1;
 }
 
@@ -719,6 +721,7 @@ struct Impl {
       for (int a = 0; a < 3; a++) P.kj[a] = (R)((double)P.kj[a] * h->fx_scale);
       P.ky2d = (R)((double)P.ky2d * h->fx_scale);
     }
+    P.galerkin = h->cfg.gather_form == BFPIC_GATHER_ENERGY;
     P.ion_moves = h->sb != 0.0;
     P.remove = !h->g.periodic_z;
     P.lim = ORDER + 1;
@@ -1354,7 +1357,8 @@ struct Impl {
           k_adj_particles<R, ORDER><<<nbq, 256, 0, h->stream>>>(P, F, TP, LJ, LF, A);
           if (wit_adj) {
             WitK W{(double*)(b + off_wit(h, false)), h->nwit,
-                   {h->dt / h->dz, h->dt / h->dx, h->dt / h->dy}, -0.5 * h->dt};
+                   {h->dt / h->dz, h->dt / h->dx, h->dt / h->dy}, -0.5 * h->dt,
+                   h->cfg.gather_form};
             k_adj_witness<R, ORDER><<<nbw, 256, 0, h->stream>>>(g, F, W, T.wl, LF);
           }
           HIPCHK(h, hipGetLastError());
@@ -1407,7 +1411,8 @@ struct Impl {
 
   // Witness electrons through the start-of-step fields (FP64).
   static int witness_push(bfpic_ctx* h) {
-    WitK W{h->wit, h->nwit, {h->dt / h->dz, h->dt / h->dx, h->dt / h->dy}, -0.5 * h->dt};
+    WitK W{h->wit, h->nwit, {h->dt / h->dz, h->dt / h->dx, h->dt / h->dy}, -0.5 * h->dt,
+           h->cfg.gather_form};
     k_witness_push<R, DIM, ORDER><<<(unsigned)cdiv(h->nwit, 256), 256, 0, h->stream>>>(
         h->g, fields(h), W);
     HIPCHK(h, hipGetLastError());
@@ -2029,7 +2034,8 @@ bool same_physics(const bfpic_config& a, const bfpic_config& b) {
          a.filter_passes == b.filter_passes && a.filter_compensate == b.filter_compensate &&
          a.precision == b.precision && a.deterministic == b.deterministic &&
          a.z_boundary == b.z_boundary && a.ppc == b.ppc && a.load == b.load &&
-         a.seed == b.seed && a.beta_window == b.beta_window && a.auto_window == b.auto_window;
+         a.seed == b.seed && a.beta_window == b.beta_window && a.auto_window == b.auto_window &&
+         a.gather_form == b.gather_form;
 }
 
 // Device arrays of the state in blob order: E, B, id, displacements,

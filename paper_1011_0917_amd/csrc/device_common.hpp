@@ -24,12 +24,22 @@ __device__ __forceinline__ int wrapi(int i, int n) {
   return r < 0 ? r + n : r;
 }
 
-// Storage index of node (i, j, k) or -1 outside storage (open z only).
+// Wrap into [0, n) for x in (-n, 2n); other values take the full modulo.
+__device__ __forceinline__ int wrap_small(int x, int n) {
+  if (x < 0) x += n;
+  else if (x >= n) x -= n;
+  if ((unsigned)x >= (unsigned)n) x = wrapi(x, n);
+  return x;
+}
+
+// Storage index of node (i, j, k) or -1 outside storage (open z only).  Node
+// indices lie within a few cells of the grid, where one period of wrap is
+// exact; farther ones take the modulo.
 __device__ __forceinline__ int64_t gidx(const Geo& g, int i, int j, int k) {
-  if (g.periodic_z) i = wrapi(i, g.nz);
+  if (g.periodic_z) i = wrap_small(i, g.nz);
   else if (i < -kGuard || i > g.nz + kGuard) return -1;
-  j = wrapi(j, g.nx);
-  k = g.ny > 1 ? wrapi(k, g.ny) : 0;
+  j = wrap_small(j, g.nx);
+  k = g.ny > 1 ? wrap_small(k, g.ny) : 0;
   return ((int64_t)(i + kGuard) * g.nx + j) * g.ny + k;
 }
 
@@ -97,14 +107,6 @@ __device__ __forceinline__ Birth decode_id(const LatticeP& L, int id) {
 // test the result against a range inside [0, n) reject anything else.
 __device__ __forceinline__ int wrap_once(int x, int n) {
   return x + (x < 0 ? n : 0) - (x >= n ? n : 0);
-}
-
-// Wrap into [0, n) for x in (-n, 2n); other values take the full modulo.
-__device__ __forceinline__ int wrap_small(int x, int n) {
-  if (x < 0) x += n;
-  else if (x >= n) x -= n;
-  if ((unsigned)x >= (unsigned)n) x = wrapi(x, n);
-  return x;
 }
 
 // In-cell birth offsets: 24-bit fields of SplitMix64 outputs times 2^-24
@@ -249,6 +251,27 @@ __device__ __forceinline__ int shape(int c, R o, int half, R w[ORDER + 1]) {
     w[1] = (R)0.75 - d * d;
     w[ORDER] = (R)0.5 * e * e;
     return m - 1;
+  }
+}
+
+// Energy-conserving (Galerkin) gather: on the half-integer lattice the shape
+// of one order lower, written on the node window of shape(c, o, 1, w) so that
+// it reads the same nodes: order 0 (the half node c + 1/2 of the particle's
+// cell) for ORDER 1, linear on the half nodes for ORDER 2.
+template <typename R, int ORDER>
+__device__ __forceinline__ void shape_half_reduced(R o, R w[ORDER + 1]) {
+  const bool hi = o >= (R)0.5;
+  if (ORDER == 1) {
+    // window (c - 1, c) for o < 1/2, (c, c + 1) for o >= 1/2
+    w[0] = hi ? (R)1 : (R)0;
+    w[1] = hi ? (R)0 : (R)1;
+  } else {
+    // window (c - 1, c, c + 1); the linear pair is (c, c + 1) for o >= 1/2,
+    // (c - 1, c) below
+    const R f = hi ? o - (R)0.5 : o + (R)0.5;
+    w[0] = hi ? (R)0 : (R)1 - f;
+    w[1] = hi ? (R)1 - f : f;
+    w[ORDER] = hi ? f : (R)0;
   }
 }
 

@@ -112,6 +112,7 @@ __device__ __forceinline__ StepK<Dual<T>> dualize(const StepK<T>& p) {
     q.kj[a] = p.kj[a];
   }
   q.ky2d = p.ky2d;
+  q.galerkin = p.galerkin;
   q.ion_moves = p.ion_moves;
   q.remove = p.remove;
   q.lim = p.lim;
@@ -136,9 +137,14 @@ struct AdjJSink {
   const T* const* lj;  // adjoint of the unfiltered current, Jx Jy Jz
   Geo g;
   T* acc;
+  T* accv;             // if set: the same contraction with the current's value
   __device__ __forceinline__ void add(int comp, int i, int j, int k, Dual<T> v) const {
     const int64_t n = gidx(g, i, j, k);
-    if (n >= 0) *acc += lj[comp][n] * v.d;
+    if (n >= 0) {
+      const T l = lj[comp][n];
+      *acc += l * v.d;
+      if (accv) *accv += l * v.v;
+    }
   }
 };
 
@@ -174,12 +180,15 @@ __device__ __forceinline__ void scatter_node_weights(R* const* lf, const Geo& g,
 
 template <typename R, int ORDER>
 __device__ __forceinline__ void gather_transpose(R* const* lf, const Geo& g, const Pos<R>& p,
-                                                 const R gE[3], const R gB[3]) {
+                                                 const R gE[3], const R gB[3], bool gk) {
   R wz0[ORDER + 1], wz1[ORDER + 1], wx0[ORDER + 1], wx1[ORDER + 1];
   const int z0 = shape<R, ORDER>(p.c[0], p.o[0], 0, wz0);
   const int z1 = shape<R, ORDER>(p.c[0], p.o[0], 1, wz1);
   const int x0 = shape<R, ORDER>(p.c[1], p.o[1], 0, wx0);
   const int x1 = shape<R, ORDER>(p.c[1], p.o[1], 1, wx1);
+  // the Galerkin form reads the half lattices with the reduced shape
+  galerkin_half<R, ORDER>(gk, p.o[0], wz1);
+  galerkin_half<R, ORDER>(gk, p.o[1], wx1);
   // staggering (z, x): Ex (0,h) Ey (0,0) Ez (h,0) Bx (h,0) By (h,h) Bz (0,h)
   scatter_node_weights<R, ORDER>(lf, g, 0, z0, wz0, x1, wx1, gE[0]);
   scatter_node_weights<R, ORDER>(lf, g, 1, z0, wz0, x0, wx0, gE[1]);
@@ -236,8 +245,16 @@ __global__ __launch_bounds__(256) void k_adj_particles(StepK<R> P, Fields<R> F,
     const R lx0 = A.lxi[0][p], lx1 = A.lxi[1][p];
     const R lu0 = A.ldu[0][p], lu1 = A.ldu[1][p], lu2 = A.ldu[2][p];
     R gdir[12];
+    // The current is linear in the weight and nothing else depends on it, so
+    // the weight direction is the current's value contracted with its adjoint,
+    // divided by w: taken from the first pass (a zero weight runs its own).
+    R accv = (R)0;
 #pragma unroll 1
     for (int dir = 0; dir < 12; dir++) {
+      if (dir == 5 && w != (R)0) {
+        gdir[5] = accv / w;
+        continue;
+      }
       D xi[3] = {D((double)xi0), D((double)xi1), D(0.0)};
       D du[3] = {D((double)du0), D((double)du1), D((double)du2)};
       D wd = D((double)w);
@@ -245,7 +262,7 @@ __global__ __launch_bounds__(256) void k_adj_particles(StepK<R> P, Fields<R> F,
       else if (dir < 5) du[dir - 2].d = (R)1;
       else if (dir == 5) wd.d = (R)1;
       R acc = (R)0;
-      AdjJSink<R> snk{(const R* const*)LJ.F, g, &acc};
+      AdjJSink<R> snk{(const R* const*)LJ.F, g, &acc, dir == 0 ? &accv : nullptr};
       const Pos<D> e0 = add_xi<D, 2>(i0, xi);
       const int bc[3] = {e0.c[0], e0.c[1], 0};
       (void)particle_step<D, 2, ORDER>(PD, fetch, snk, bc, e0, i0, i1, xi, du, wd,
@@ -263,7 +280,7 @@ __global__ __launch_bounds__(256) void k_adj_particles(StepK<R> P, Fields<R> F,
     R xr[3] = {xi0, xi1, (R)0};
     const Pos<R> e0p = add_xi<R, 2>(ion_at<R, 2>(b, r, P.D0), xr);
     const R gE[3] = {gdir[6], gdir[7], gdir[8]}, gB[3] = {gdir[9], gdir[10], gdir[11]};
-    gather_transpose<R, ORDER>(LF.F, g, e0p, gE, gB);
+    gather_transpose<R, ORDER>(LF.F, g, e0p, gE, gB, P.galerkin != 0);
   }
 }
 
@@ -572,7 +589,7 @@ __global__ __launch_bounds__(256) void k_adj_witness(Geo g, Fields<R> F, WitK W,
   p.o[2] = (R)0;
   const R gE[3] = {(R)gdir[6], (R)gdir[7], (R)gdir[8]};
   const R gB[3] = {(R)gdir[9], (R)gdir[10], (R)gdir[11]};
-  gather_transpose<R, ORDER>(LF.F, g, p, gE, gB);
+  gather_transpose<R, ORDER>(LF.F, g, p, gE, gB, W.galerkin != 0);
 }
 
 }  // namespace bfpic

@@ -40,6 +40,7 @@ struct StepK {
   R dtd[3];          // dt / d along z, x, y: cells moved per unit velocity
   R kj[3];           // prefix scale per unit q w: Jz 1/(dx[dy] dt), Jx 1/(dz[dy] dt), Jy 1/(dz dx dt)
   R ky2d;            // 2D out-of-plane: 1/(dz dx)
+  int galerkin;      // 1: energy-conserving gather (one order lower on half nodes)
   int ion_moves;     // the partner drifts (boosted frame)
   int remove;        // open z: drop pairs beyond `lim` cells outside [0, nz]
   int lim;
@@ -257,9 +258,17 @@ __device__ __forceinline__ R interp_axes(const F& f, int comp, const int64_t* zr
   return acc;
 }
 
+// Galerkin (energy-conserving) form: every half-lattice weight set replaced
+// by the shape of one order lower on the same nodes (a component staggered
+// along an axis takes the reduced shape along that axis).
+template <typename R, int ORDER>
+__device__ __forceinline__ void galerkin_half(bool gk, R o, R w[ORDER + 1]) {
+  if (gk) shape_half_reduced<R, ORDER>(o, w);
+}
+
 template <typename R, int DIM, int ORDER, class F>
 __device__ __forceinline__ void gather_axes(const F& f, const int bc[3], const Pos<R>& p, R E[3],
-                                            R B[3]) {
+                                            R B[3], bool gk) {
   R wz[2][ORDER + 1], wx[2][ORDER + 1], wy[2][ORDER + 1];
   int64_t zr[2][ORDER + 1];
   int xc[2][ORDER + 1], yc[2][ORDER + 1];
@@ -267,6 +276,10 @@ __device__ __forceinline__ void gather_axes(const F& f, const int bc[3], const P
   for (int h = 0; h < 2; h++) {
     const int bz = shape<R, ORDER>(p.c[0], p.o[0], h, wz[h]) - p.c[0] + bc[0];
     const int bx = shape<R, ORDER>(p.c[1], p.o[1], h, wx[h]) - p.c[1] + bc[1];
+    if (h == 1) {
+      galerkin_half<R, ORDER>(gk, p.o[0], wz[h]);
+      galerkin_half<R, ORDER>(gk, p.o[1], wx[h]);
+    }
 #pragma unroll
     for (int a = 0; a <= ORDER; a++) {
       bool ok;
@@ -276,6 +289,7 @@ __device__ __forceinline__ void gather_axes(const F& f, const int bc[3], const P
     }
     if (DIM == 3) {
       const int by = shape<R, ORDER>(p.c[2], p.o[2], h, wy[h]) - p.c[2] + bc[2];
+      if (h == 1) galerkin_half<R, ORDER>(gk, p.o[2], wy[h]);
 #pragma unroll
       for (int c = 0; c <= ORDER; c++) yc[h][c] = f.dep(by + c);
     } else {
@@ -297,17 +311,20 @@ __device__ __forceinline__ void gather_axes(const F& f, const int bc[3], const P
 
 template <typename R, int DIM, int ORDER, class F>
 __device__ __forceinline__ void gather_nodes(const F& f, const int bc[3], const Pos<R>& p,
-                                             R E[3], R B[3]) {
+                                             R E[3], R B[3], bool gk) {
   R wz0[ORDER + 1], wz1[ORDER + 1], wx0[ORDER + 1], wx1[ORDER + 1];
   R wy0[ORDER + 1], wy1[ORDER + 1];
   int z0 = shape<R, ORDER>(p.c[0], p.o[0], 0, wz0) - p.c[0] + bc[0];
   int z1 = shape<R, ORDER>(p.c[0], p.o[0], 1, wz1) - p.c[0] + bc[0];
   int x0 = shape<R, ORDER>(p.c[1], p.o[1], 0, wx0) - p.c[1] + bc[1];
   int x1 = shape<R, ORDER>(p.c[1], p.o[1], 1, wx1) - p.c[1] + bc[1];
+  galerkin_half<R, ORDER>(gk, p.o[0], wz1);
+  galerkin_half<R, ORDER>(gk, p.o[1], wx1);
   int y0 = 0, y1 = 0;
   if (DIM == 3) {
     y0 = shape<R, ORDER>(p.c[2], p.o[2], 0, wy0) - p.c[2] + bc[2];
     y1 = shape<R, ORDER>(p.c[2], p.o[2], 1, wy1) - p.c[2] + bc[2];
+    galerkin_half<R, ORDER>(gk, p.o[2], wy1);
   }
   // staggering (z, x, y): Ex (0,h,0) Ey (0,0,h) Ez (h,0,0) Bx (h,0,h) By (h,h,0) Bz (0,h,h)
   E[0] = interp<R, DIM, ORDER>(f, 0, z0, wz0, x1, wx1, y0, wy0);
@@ -320,9 +337,9 @@ __device__ __forceinline__ void gather_nodes(const F& f, const int bc[3], const 
 
 template <typename R, int DIM, int ORDER, class F>
 __device__ __forceinline__ void gather(const F& f, const int bc[3], const Pos<R>& p, R E[3],
-                                       R B[3]) {
-  if constexpr (HasAxes<F>::value) gather_axes<R, DIM, ORDER>(f, bc, p, E, B);
-  else gather_nodes<R, DIM, ORDER>(f, bc, p, E, B);
+                                       R B[3], bool gk) {
+  if constexpr (HasAxes<F>::value) gather_axes<R, DIM, ORDER>(f, bc, p, E, B, gk);
+  else gather_nodes<R, DIM, ORDER>(f, bc, p, E, B, gk);
 }
 
 // --------------------------------------------------------------------------
@@ -684,7 +701,7 @@ __device__ __forceinline__ bool particle_step(const StepK<R>& P, const F& fetch,
                                               R du[3], R w, const Hook& hook = Hook(),
                                               bool near = true) {
   R E[3], B[3], dv[3], gam;
-  gather<R, DIM, ORDER>(fetch, bc, e0, E, B);
+  gather<R, DIM, ORDER>(fetch, bc, e0, E, B, P.galerkin != 0);
   hook(E, B);
   boris_split(P.push, E, B, du, dv, gam);
   const R xi_old[3] = {xi[0], xi[1], xi[2]};

@@ -36,6 +36,7 @@ struct WitK {
   int n;
   double dtd[3];  // dt / d along z, x, y
   double qdt2;    // q dt / 2, q = -1
+  int galerkin;   // 1: energy-conserving gather, as the plasma's
 };
 
 struct NoSeed {
@@ -63,7 +64,7 @@ __device__ __forceinline__ void witness_advance(const Fch& f, const Geo& g, cons
   p.o[2] = DIM == 3 ? y - T((double)p.c[2]) : T(0.0);
   const int bc[3] = {p.c[0], p.c[1], p.c[2]};
   T E[3], B[3];
-  gather_nodes<T, DIM, ORDER>(f, bc, p, E, B);
+  gather_nodes<T, DIM, ORDER>(f, bc, p, E, B, W.galerkin != 0);
   seed(E, B);
   const T h = T(W.qdt2);
   T m[3], t[3];

@@ -181,7 +181,8 @@ def resolve_gpu(W, precision=None, sort_interval=20, capacity=None):
         precision=P.FP64 if prec == "fp64" else P.FP32_SPLIT,
         z_boundary=P.BC_PERIODIC if W["zbc"] == "periodic" else P.BC_MUR, ppc=W["ppc"],
         load=W.get("load", 0), sort_interval=sort_interval, seed=W["seed"],
-        beta_window=r["beta_window"], auto_window=1 if W.get("window") else 0)
+        beta_window=r["beta_window"], auto_window=1 if W.get("window") else 0,
+        gather_form=P.GATHER_ENERGY if W.get("gather") == "energy" else P.GATHER_MOMENTUM)
     cells = W["nz"] * W["nx"] * W.get("ny", 1)
     if capacity is None:
         # initial plasma + injected columns over the run + margin
@@ -204,7 +205,8 @@ def resolve_oracle(W):
               filter_compensate=W["filter_compensate"],
               zbc=0 if W["zbc"] == "periodic" else 1, ppc=W["ppc"], seed=W["seed"],
               gamma_b=W["gamma_b"], beta_window=r["beta_window"],
-              auto_window=1 if W.get("window") else 0, ions=1, load=W.get("load", 0))
+              auto_window=1 if W.get("window") else 0, ions=1, load=W.get("load", 0),
+              gather=1 if W.get("gather") == "energy" else 0)
     init = dict(n_lab=W["n_lab"], laser=O.make_laser(**r["laser"]))
     return kw, init
 
