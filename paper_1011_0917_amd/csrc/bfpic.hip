@@ -748,6 +748,7 @@ struct Impl {
     K.LX = h->LX;
     K.LY = h->LY;
     K.LV = h->LV;
+    K.zero_base = h->maxtiles * 3 * (int64_t)h->LV;
     K.o = ovf(h);
     return K;
   }

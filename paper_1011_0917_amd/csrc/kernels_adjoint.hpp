@@ -125,10 +125,15 @@ struct DualFetch {
   const T* const* F;
   Geo g;
   __device__ __forceinline__ Dual<T> operator()(int comp, int i, int j, int k) const {
+    // branchless: a node outside storage reads element 0 and takes zero
     const int64_t n = gidx(g, i, j, k);
-    return Dual<T>(n < 0 ? 0.0 : (double)F[comp][n]);
+    const T v = F[comp][n < 0 ? 0 : n];
+    return Dual<T>(n < 0 ? 0.0 : (double)v);
   }
 };
+
+template <typename T>
+struct LoadsFirst<DualFetch<T>> : std::true_type {};
 
 // Current "sink" of the adjoint: contracts each current contribution's
 // tangent with the current adjoint at its node.
@@ -140,11 +145,10 @@ struct AdjJSink {
   T* accv;             // if set: the same contraction with the current's value
   __device__ __forceinline__ void add(int comp, int i, int j, int k, Dual<T> v) const {
     const int64_t n = gidx(g, i, j, k);
-    if (n >= 0) {
-      const T l = lj[comp][n];
-      *acc += l * v.d;
-      if (accv) *accv += l * v.v;
-    }
+    const T ln = lj[comp][n < 0 ? 0 : n];  // branchless, as in DualFetch
+    const T l = n < 0 ? (T)0 : ln;
+    *acc += l * v.d;
+    if (accv) *accv += l * v.v;
   }
 };
 

@@ -25,6 +25,7 @@ struct FoldK {
   int ntz, ntx, nty, ntiles;
   int gz0, gx0, gy0;  // region origin of tile (0,0,0) in grid cells
   int TZ, TX, TY, LZ, LX, LY, LV;
+  int64_t zero_base;    // element offset of the row of zero tiles past the last tile
   Ovf<R> o;
 };
 
@@ -47,23 +48,31 @@ __device__ __forceinline__ R fold_at(const FoldK<R>& K, const Geo& g, int comp, 
     const int hz = qz >= 0 ? qz / TZ : -((TZ - 1 - qz) / TZ);
     const int hx = qx / TX, hy = DIM == 3 ? qy / TY : 0;
     const int lz = qz - hz * TZ, lx = qx - hx * TX, ly = qy - hy * TY;
+    // Every candidate is loaded unconditionally, so that all the loads of a
+    // node are in flight together: a tile that does not cover the node reads
+    // the zeroed tile row kept past the last tile.
 #pragma unroll
     for (int a = 0; a < 3; a++) {
-      int tz = hz - a, rz = lz + a * TZ;
+      int tz = hz - a;
+      const int rz = lz + a * TZ;
       if (g.periodic_z && tz < 0) tz += K.ntz;
-      if (tz < 0 || tz >= K.ntz || rz >= K.LZ) continue;
+      const bool vz = tz >= 0 && tz < K.ntz && rz < K.LZ;
 #pragma unroll
       for (int b = 0; b < 3; b++) {
-        int tx = hx - b, rx = lx + b * TX;
+        int tx = hx - b;
+        const int rx = lx + b * TX;
         if (tx < 0) tx += K.ntx;
-        if (rx >= K.LX) continue;
+        const bool vx = vz && rx < K.LX;
 #pragma unroll
         for (int c = 0; c < (DIM == 3 ? 3 : 1); c++) {
-          int ty = hy - c, ry = ly + c * TY;
+          int ty = hy - c;
+          const int ry = ly + c * TY;
           if (ty < 0) ty += K.nty;
-          if (DIM == 3 && ry >= K.LY) continue;
-          int t = (tz * K.ntx + tx) * K.nty + ty;
-          acc += scratch[((int64_t)t * 3 + comp) * K.LV + (rz * K.LX + rx) * K.LY + ry];
+          const bool v = vx && (DIM != 3 || ry < K.LY);
+          const int t = (tz * K.ntx + tx) * K.nty + ty;
+          const int64_t e = v ? ((int64_t)t * 3 + comp) * K.LV + (rz * K.LX + rx) * K.LY + ry
+                              : K.zero_base;
+          acc += scratch[e];
         }
       }
     }

@@ -135,6 +135,7 @@ struct GlobalFetch {
   }
 };
 
+
 // LDS current accumulator of element type A.  FP32 atomic adds on LDS are
 // serialised lane by lane on this hardware, FP64 ones are not, so where the
 // LDS budget allows the currents accumulate in FP64 (one rounding to the
@@ -207,9 +208,44 @@ struct GlobalSinkFx {
 // deposit's shape (momentum-conserving gather).  bc = the particle's cell in
 // the fetcher's frame, p its absolute position.
 // --------------------------------------------------------------------------
+// Fetches that read global memory: their stencil values are all loaded
+// before any is used (LDS fetches keep the interleaved form).
+template <class F>
+struct LoadsFirst : std::false_type {};
+template <typename R>
+struct LoadsFirst<GlobalFetch<R>> : std::true_type {};
+
 template <typename R, int DIM, int ORDER, class F>
 __device__ __forceinline__ R interp(const F& f, int comp, int bz, const R* wz, int bx, const R* wx,
                                     int by, const R* wy) {
+  if constexpr (LoadsFirst<F>::value) {
+    constexpr int N = ORDER + 1, NY = DIM == 3 ? N : 1;
+    R v[N][N][NY];
+#pragma unroll
+    for (int a = 0; a < N; a++)
+#pragma unroll
+      for (int b = 0; b < N; b++)
+#pragma unroll
+        for (int c = 0; c < NY; c++) v[a][b][c] = f(comp, bz + a, bx + b, DIM == 3 ? by + c : 0);
+    R acc = (R)0;
+#pragma unroll
+    for (int a = 0; a < N; a++) {
+      R rowz = (R)0;
+#pragma unroll
+      for (int b = 0; b < N; b++) {
+        if (DIM == 3) {
+          R cy = (R)0;
+#pragma unroll
+          for (int c = 0; c < N; c++) cy += v[a][b][c] * wy[c];
+          rowz += cy * wx[b];
+        } else {
+          rowz += v[a][b][0] * wx[b];
+        }
+      }
+      acc += rowz * wz[a];
+    }
+    return acc;
+  }
   R acc = (R)0;
 #pragma unroll
   for (int a = 0; a <= ORDER; a++) {
@@ -233,24 +269,36 @@ __device__ __forceinline__ R interp(const F& f, int comp, int bz, const R* wz, i
 // Gather through a fetch that exposes its axes: per staggering set (integer,
 // half) and axis, the node offsets are formed once, then each component's
 // stencil reads base(comp, row)[col + dep].
+// All the stencil's node values are loaded before any is used, so that the
+// loads of one component are in flight together (from L2 or HBM, each takes
+// hundreds of cycles).
 template <typename R, int DIM, int ORDER, class F>
 __device__ __forceinline__ R interp_axes(const F& f, int comp, const int64_t* zr, const R* wz,
                                          const int* xc, const R* wx, const int* yc,
                                          const R* wy) {
+  constexpr int N = ORDER + 1, NY = DIM == 3 ? N : 1;
+  R v[N][N][NY];
+#pragma unroll
+  for (int a = 0; a < N; a++) {
+    const R* rp = f.base(comp, zr[a]);
+#pragma unroll
+    for (int b = 0; b < N; b++)
+#pragma unroll
+      for (int c = 0; c < NY; c++) v[a][b][c] = rp[xc[b] + (DIM == 3 ? yc[c] : 0)];
+  }
   R acc = (R)0;
 #pragma unroll
-  for (int a = 0; a <= ORDER; a++) {
-    const R* rp = f.base(comp, zr[a]);
+  for (int a = 0; a < N; a++) {
     R rowz = (R)0;
 #pragma unroll
-    for (int b = 0; b <= ORDER; b++) {
+    for (int b = 0; b < N; b++) {
       if (DIM == 3) {
         R cy = (R)0;
 #pragma unroll
-        for (int c = 0; c <= ORDER; c++) cy += rp[xc[b] + yc[c]] * wy[c];
+        for (int c = 0; c < N; c++) cy += v[a][b][c] * wy[c];
         rowz += cy * wx[b];
       } else {
-        rowz += rp[xc[b]] * wx[b];
+        rowz += v[a][b][0] * wx[b];
       }
     }
     acc += rowz * wz[a];
@@ -878,10 +926,13 @@ struct TileGeom {
 // STAGE = false: the fields are gathered from global memory (L2-resident
 // tile neighbourhoods) and only the currents live in LDS -- for tiles whose
 // staged fields would not fit (3D quadratic shapes).
+// The variant that gathers from global memory runs one workgroup per CU (its
+// LDS region), two waves per SIMD: it may spend the registers that leaves to
+// keep a whole stencil's loads in flight.
 template <typename R, int DIM, int ORDER, int TZ, int TX, int TY, int EXC, int NT, bool DET,
           bool STAGE = true>
-__global__ __launch_bounds__(NT) void k_gpd_tiled(StepK<R> P, Fields<R> F, PSoA<R> S, TileK T,
-                                                  Ovf<R> O, void* scratch) {
+__global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(1, STAGE ? 8 : NT / 256))) void
+k_gpd_tiled(StepK<R> P, Fields<R> F, PSoA<R> S, TileK T, Ovf<R> O, void* scratch) {
   using TG = TileGeom<DIM, ORDER, TZ, TX, TY, EXC>;
   constexpr int LZ = TG::LZ, LX = TG::LX, LY = TG::LY, LV = TG::LV;
   using A = LdsAcc<R, DIM, DET, STAGE>;
