@@ -321,3 +321,60 @@ def channel_guiding(matched=True):
     W["rayleigh"] = math.pi * w0 ** 2 / LAMBDA0
     W["propagation_rayleigh"] = 1.5
     return W
+
+
+# One stage in plasma in the lab frame and in a frame boosted at gamma = 5,
+# for their comparison in the lab frame (the lab-against-boost comparison of
+# the section "Effect of the hyperbolic rotation in Minkowski space", Fig. 2).
+#   * plasma: 0.01 n_c (k_p = 0.1) behind a 125 c/omega0 linear ramp, at rest
+#     in the lab, ions as co-located partners; 2 pairs per cell at the cell
+#     centres (a quiet start), a slab of 4 periodic transverse cells of
+#     16 lambda0 (the problem is one-dimensional);
+#   * laser: plane wave, a0 = 1, resonant Gaussian length L = sqrt(2) / k_p;
+#   * numerics in both frames: `cells` cells per laser wavelength of the frame
+#     (16 gamma_b (1 + beta_b) ... the Doppler-stretched one in the boosted
+#     frame), CFL 0.95, 4 binomial passes with compensation, Mur ends, window
+#     at the laser group velocity of the frame;
+#   * placement: the boosted pulse is centred at z' = 2600 at t' = 0 and the
+#     plasma front lies 200 c/omega0 beyond the pulse's leading cut (4 L'),
+#     so that the whole t' = 0 field is a vacuum field; in lab coordinates the
+#     plasma then starts at z_p = gamma_b z'_front.  The lab run starts at the
+#     lab time T0 at which the pulse centre is 150 c/omega0 from the plasma
+#     (row 0 of its window at lab z Z0, the pulse centre 290 above it) and runs
+#     900 time units; the boosted run runs 2100 of its own;
+#   * comparison grid (original lab coordinates): t from 50 after the pulse
+#     centre meets the plasma, 280 samples 2 apart; zeta = z - v_g t from 300
+#     behind the pulse centre, 720 samples 0.5 apart; the plasma front and its
+#     transient have left that window from sample 240 on.
+def lab_boost_pair(beta, boosted_dz, group_beta, yee_dt, cells=32):
+    n0, a0, gb = 0.01, 1.0, 5.0
+    kp = math.sqrt(n0)
+    L = math.sqrt(2.0) / kp
+    bb = beta(gb)
+    dx, nx = 16.0 * LAMBDA0, 4
+    ramp = 125.0
+    scale = cells // 16
+    dzb = boosted_dz(gb, LAMBDA0, cells)
+    zL_b = 2600.0
+    z_front_b = zL_b + 4.0 * L * gb * (1.0 + bb) + 200.0
+    z_p = gb * z_front_b
+    z_c = zL_b / (gb * (1.0 + bb))
+    vg = group_beta(1.0, n0)
+    T0 = (z_p - 150.0) - z_c
+    Z0 = (z_p - 150.0) - 290.0
+    dzl = LAMBDA0 / cells
+    boost = dict(gamma_b=gb, nz=1024 * scale, dz=dzb, z_center=z_c,
+                 knots_z=[z_p, z_p + ramp, 1.0e7], knots_n=[0.0, n0, n0],
+                 beta_window=group_beta(gb, n0),
+                 steps=int(2100.0 / yee_dt(2, dzb, dx, 1.0, 0.95)), every=1,
+                 t_shift=0.0, z_shift=0.0)
+    lab = dict(gamma_b=1.0, nz=1024 * scale, dz=dzl, z_center=290.0,
+               knots_z=[z_p - Z0, z_p - Z0 + ramp, 1.0e7], knots_n=[0.0, n0, n0],
+               beta_window=vg, steps=int(900.0 / yee_dt(2, dzl, dx, 1.0, 0.95)), every=2,
+               t_shift=T0, z_shift=Z0)
+    tc = z_p - z_c
+    zeta_pc = z_c + (1.0 - vg) * tc
+    grid = dict(t0=tc + 50.0, dt=2.0, nt=280, zeta0=zeta_pc - 300.0, dzeta=0.5, nzeta=720,
+                front_gone=240)
+    return dict(n0=n0, a0=a0, L=L, nx=nx, dx=dx, ppc=2, cfl=0.95, passes=4, seed=77,
+                v_window=vg, boost=boost, lab=lab, grid=grid)
