@@ -486,6 +486,13 @@ int bfpic_adjoint_tape_bytes(bfpic_ctx* h, int32_t nsteps, int32_t interval, int
 int bfpic_forward_loss(bfpic_ctx* h, int32_t nsteps, int32_t interval, const bfpic_loss* loss,
                        void* tape, int64_t tape_bytes, double* loss_out);
 int pic_step_adjoint(bfpic_ctx* h, double* dL_da0, double* dL_dn, int32_t nn);
+/* The per-particle vector-Jacobian product of pic_step_adjoint is formed by
+ * stages by default (gather, push and deposit each evaluated once with one
+ * tangent per input of the stage).  enable != 0 selects instead one dual
+ * evaluation of the whole particle step per input direction (twelve): the
+ * same product by another route, kept as a reference for tests.  Takes
+ * effect at the next pic_step_adjoint.  ERR_ARG for a null context. */
+int bfpic_adjoint_per_direction(bfpic_ctx* h, int32_t enable);
 
 #ifdef __cplusplus
 }

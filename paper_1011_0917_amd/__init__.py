@@ -96,6 +96,7 @@ EXPORTS = ["bfpic_beta", "bfpic_drift_u", "bfpic_group_gamma", "bfpic_boosted_gr
            "bfpic_set_field", "bfpic_num_slots", "bfpic_get_particles", "bfpic_sort",
            "bfpic_last_sort", "bfpic_sort_permutation", "bfpic_tile_shape", "bfpic_kernel_timing", "bfpic_kernel_time",
            "bfpic_adjoint_tape_bytes", "bfpic_forward_loss", "pic_step_adjoint",
+           "bfpic_adjoint_per_direction",
            "bfpic_axis_record", "bfpic_back_transform", "bfpic_axis_spectrum",
            "bfpic_witness_bind", "bfpic_witness_lab", "bfpic_state_bytes", "pic_save",
            "pic_load"]
@@ -138,6 +139,7 @@ def lib():
         "bfpic_adjoint_tape_bytes": (C.c_int, [p, i32, i32, C.POINTER(i64)]),
         "bfpic_forward_loss": (C.c_int, [p, i32, i32, C.POINTER(Loss), p, i64, C.POINTER(d)]),
         "pic_step_adjoint": (C.c_int, [p, C.POINTER(d), C.POINTER(d), i32]),
+        "bfpic_adjoint_per_direction": (C.c_int, [p, i32]),
         "bfpic_axis_record": (C.c_int, [p, i32, p, C.POINTER(AxisMeta)]),
         "bfpic_back_transform": (C.c_int, [p, p, p, p, i64, i32, d, d, d, d, i32, d, d, i32, d,
                                            p]),
@@ -438,6 +440,10 @@ class Simulation:
                                         C.c_void_p(self.tape.data_ptr()), nb.value,
                                         C.byref(out)), self.h)
         return out.value
+
+    def adjoint_per_direction(self, enable=True):
+        """Selects the per-direction reverse particle step (the reference)."""
+        _check(lib().bfpic_adjoint_per_direction(self.h, int(bool(enable))), self.h)
 
     def adjoint(self, nknots=1):
         """Reverse sweep of the last taped run: (dL/da0, dL/dn) with dL/dn per

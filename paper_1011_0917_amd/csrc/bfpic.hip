@@ -193,6 +193,7 @@ struct bfpic_ctx {
   bool no_sort = false;      // particle slots stay put (taped runs)
   bool adj_ready = false;    // the tape holds a forward run
   bool adj_recompute = false;
+  bool adj_per_direction = false;  // reverse particle step: one dual pass per direction
   int adj_nsteps = 0, adj_interval = 0;
   int64_t adj_slots = 0;     // slots created by the taped run
   int adj_nwit = 0;          // witnesses bound during the taped run
@@ -1355,7 +1356,10 @@ struct Impl {
           TP.count = (const int*)(b + off_tail(h, false));
           const unsigned nbq = (unsigned)std::max<int64_t>(1, std::min<int64_t>(
                                    cdiv(std::max<int64_t>(h->slots_bound, 1), 256), 4096));
-          k_adj_particles<R, ORDER><<<nbq, 256, 0, h->stream>>>(P, F, TP, LJ, LF, A);
+          if (h->adj_per_direction)
+            k_adj_particles<R, ORDER><<<nbq, 256, 0, h->stream>>>(P, F, TP, LJ, LF, A);
+          else
+            k_adj_particles_staged<R, ORDER><<<nbq, 256, 0, h->stream>>>(P, F, TP, LJ, LF, A);
           if (wit_adj) {
             WitK W{(double*)(b + off_wit(h, false)), h->nwit,
                    {h->dt / h->dz, h->dt / h->dx, h->dt / h->dy}, -0.5 * h->dt,
@@ -2256,6 +2260,12 @@ extern "C" int bfpic_forward_loss(bfpic_ctx* h, int32_t nsteps, int32_t interval
                                   double* loss_out) {
   if (!h || !loss || !loss_out) return BFPIC_ERR_ARG;
   BFPIC_DISPATCH(h, I::forward_loss(h, nsteps, interval, loss, tape, tape_bytes, loss_out));
+}
+
+extern "C" int bfpic_adjoint_per_direction(bfpic_ctx* h, int32_t enable) {
+  if (!h) return BFPIC_ERR_ARG;
+  h->adj_per_direction = enable != 0;
+  return BFPIC_OK;
 }
 
 extern "C" int pic_step_adjoint(bfpic_ctx* h, double* dL_da0, double* dL_dn, int32_t nn) {

@@ -81,9 +81,110 @@ struct Dual {
   }
 };
 
-template <typename T>
-__device__ __forceinline__ PushC<Dual<T>> dualize(const PushC<T>& p) {
-  PushC<Dual<T>> q;
+// --------------------------------------------------------------------------
+// Forward-mode dual number with N tangents: one evaluation carries the
+// derivatives along N input directions at once, each tangent by the rules of
+// Dual.  Equality compares every tangent.
+// --------------------------------------------------------------------------
+template <typename T, int N>
+struct DualN {
+  T v, d[N];
+  __device__ __forceinline__ DualN() : v((T)0) {
+#pragma unroll
+    for (int k = 0; k < N; k++) d[k] = (T)0;
+  }
+  __device__ __forceinline__ DualN(double x) : v((T)x) {
+#pragma unroll
+    for (int k = 0; k < N; k++) d[k] = (T)0;
+  }
+  // value x with tangent 1 along direction k (k outside [0, N): none)
+  __device__ __forceinline__ static DualN seed(T x, int k) {
+    DualN r;
+    r.v = x;
+#pragma unroll
+    for (int m = 0; m < N; m++) r.d[m] = m == k ? (T)1 : (T)0;
+    return r;
+  }
+  __device__ __forceinline__ explicit operator int() const { return (int)v; }
+
+  friend __device__ __forceinline__ DualN operator+(DualN a, DualN b) {
+    a.v += b.v;
+#pragma unroll
+    for (int k = 0; k < N; k++) a.d[k] += b.d[k];
+    return a;
+  }
+  friend __device__ __forceinline__ DualN operator-(DualN a, DualN b) {
+    a.v -= b.v;
+#pragma unroll
+    for (int k = 0; k < N; k++) a.d[k] -= b.d[k];
+    return a;
+  }
+  friend __device__ __forceinline__ DualN operator-(DualN a) {
+    a.v = -a.v;
+#pragma unroll
+    for (int k = 0; k < N; k++) a.d[k] = -a.d[k];
+    return a;
+  }
+  friend __device__ __forceinline__ DualN operator*(DualN a, DualN b) {
+    DualN r;
+    r.v = a.v * b.v;
+#pragma unroll
+    for (int k = 0; k < N; k++) r.d[k] = a.d[k] * b.v + a.v * b.d[k];
+    return r;
+  }
+  friend __device__ __forceinline__ DualN operator/(DualN a, DualN b) {
+    DualN r;
+    r.v = a.v / b.v;
+#pragma unroll
+    for (int k = 0; k < N; k++) r.d[k] = (a.d[k] - r.v * b.d[k]) / b.v;
+    return r;
+  }
+  __device__ __forceinline__ DualN& operator+=(DualN b) { return *this = *this + b; }
+  __device__ __forceinline__ DualN& operator-=(DualN b) { return *this = *this - b; }
+  __device__ __forceinline__ DualN& operator*=(DualN b) { return *this = *this * b; }
+  __device__ __forceinline__ DualN& operator/=(DualN b) { return *this = *this / b; }
+  friend __device__ __forceinline__ bool operator<(DualN a, DualN b) { return a.v < b.v; }
+  friend __device__ __forceinline__ bool operator<=(DualN a, DualN b) { return a.v <= b.v; }
+  friend __device__ __forceinline__ bool operator>(DualN a, DualN b) { return a.v > b.v; }
+  friend __device__ __forceinline__ bool operator>=(DualN a, DualN b) { return a.v >= b.v; }
+  friend __device__ __forceinline__ bool operator==(DualN a, DualN b) {
+    bool e = a.v == b.v;
+#pragma unroll
+    for (int k = 0; k < N; k++) e = e && a.d[k] == b.d[k];
+    return e;
+  }
+  friend __device__ __forceinline__ bool operator!=(DualN a, DualN b) { return !(a == b); }
+  friend __device__ __forceinline__ DualN floor(DualN a) { return DualN((double)floor(a.v)); }
+  friend __device__ __forceinline__ DualN sqrt(DualN a) {
+    DualN r;
+    r.v = sqrt(a.v);
+    const T h = r.v > (T)0 ? (T)1 / (r.v + r.v) : (T)0;
+#pragma unroll
+    for (int k = 0; k < N; k++) r.d[k] = a.d[k] * h;
+    return r;
+  }
+  friend __device__ __forceinline__ DualN root(DualN a) {
+    DualN r;
+    r.v = root(a.v);
+    const T h = r.v > (T)0 ? (T)1 / (r.v + r.v) : (T)0;
+#pragma unroll
+    for (int k = 0; k < N; k++) r.d[k] = a.d[k] * h;
+    return r;
+  }
+  friend __device__ __forceinline__ DualN rcp(DualN a) {
+    DualN r;
+    r.v = rcp(a.v);
+    const T m = -r.v * r.v;
+#pragma unroll
+    for (int k = 0; k < N; k++) r.d[k] = a.d[k] * m;
+    return r;
+  }
+};
+
+// The step constants as constants of a dual type D (zero tangents).
+template <class D, typename T>
+__device__ __forceinline__ PushC<D> to_dual(const PushC<T>& p) {
+  PushC<D> q;
   q.ub = p.ub;
   q.gb = p.gb;
   q.gb2 = p.gb2;
@@ -91,22 +192,22 @@ __device__ __forceinline__ PushC<Dual<T>> dualize(const PushC<T>& p) {
   return q;
 }
 
-template <typename T>
-__device__ __forceinline__ Drift<Dual<T>> dualize(const Drift<T>& p) {
-  Drift<Dual<T>> q;
+template <class D, typename T>
+__device__ __forceinline__ Drift<D> to_dual(const Drift<T>& p) {
+  Drift<D> q;
   q.Dint = p.Dint;
   q.Dfrac = p.Dfrac;
   return q;
 }
 
-template <typename T>
-__device__ __forceinline__ StepK<Dual<T>> dualize(const StepK<T>& p) {
-  StepK<Dual<T>> q;
+template <class D, typename T>
+__device__ __forceinline__ StepK<D> to_dual(const StepK<T>& p) {
+  StepK<D> q;
   q.g = p.g;
   q.L = p.L;
-  q.push = dualize(p.push);
-  q.D0 = dualize(p.D0);
-  q.D1 = dualize(p.D1);
+  q.push = to_dual<D>(p.push);
+  q.D0 = to_dual<D>(p.D0);
+  q.D1 = to_dual<D>(p.D1);
   for (int a = 0; a < 3; a++) {
     q.dtd[a] = p.dtd[a];
     q.kj[a] = p.kj[a];
@@ -117,6 +218,11 @@ __device__ __forceinline__ StepK<Dual<T>> dualize(const StepK<T>& p) {
   q.remove = p.remove;
   q.lim = p.lim;
   return q;
+}
+
+template <typename T>
+__device__ __forceinline__ StepK<Dual<T>> dualize(const StepK<T>& p) {
+  return to_dual<Dual<T>>(p);
 }
 
 // Field fetch of constant grid values as duals.
@@ -159,6 +265,37 @@ struct SeedFields {
   __device__ __forceinline__ void operator()(Dual<T>* E, Dual<T>* B) const {
     if (dir >= 6 && dir < 9) E[dir - 6].d = (T)1;
     if (dir >= 9 && dir < 12) B[dir - 9].d = (T)1;
+  }
+};
+
+// The same fetch and current sink for N-tangent duals: grid values are
+// constants, and each current contribution's tangents are contracted with
+// the current adjoint at its node into acc[0..N).
+template <typename T, int N>
+struct DualFetchN {
+  const T* const* F;
+  Geo g;
+  __device__ __forceinline__ DualN<T, N> operator()(int comp, int i, int j, int k) const {
+    const int64_t n = gidx(g, i, j, k);
+    const T v = F[comp][n < 0 ? 0 : n];
+    return DualN<T, N>(n < 0 ? 0.0 : (double)v);
+  }
+};
+
+template <typename T, int N>
+struct LoadsFirst<DualFetchN<T, N>> : std::true_type {};
+
+template <typename T, int N>
+struct AdjJSinkN {
+  const T* const* lj;
+  Geo g;
+  T* acc;
+  __device__ __forceinline__ void add(int comp, int i, int j, int k, DualN<T, N> v) const {
+    const int64_t n = gidx(g, i, j, k);
+    const T ln = lj[comp][n < 0 ? 0 : n];
+    const T l = n < 0 ? (T)0 : ln;
+#pragma unroll
+    for (int m = 0; m < N; m++) acc[m] += l * v.d[m];
   }
 };
 
@@ -285,6 +422,109 @@ __global__ __launch_bounds__(256) void k_adj_particles(StepK<R> P, Fields<R> F,
     const Pos<R> e0p = add_xi<R, 2>(ion_at<R, 2>(b, r, P.D0), xr);
     const R gE[3] = {gdir[6], gdir[7], gdir[8]}, gB[3] = {gdir[9], gdir[10], gdir[11]};
     gather_transpose<R, ORDER>(LF.F, g, e0p, gE, gB, P.galerkin != 0);
+  }
+}
+
+// The same reverse particle step by stages.  The step factors as
+//   (xi) -> gather -> (E, B);  (E, B, du) -> push -> (du', v);
+//   xi' = xi + v dt/d;  (xi, xi', w, v_y) -> deposit -> J,
+// and each stage's Jacobian has few input directions, so each is evaluated
+// once on a dual type with one tangent per input of that stage: the gather
+// on 2 (the displacement), the push on 9 (fields and momentum), the deposit
+// on 6 (old and new displacement, weight, v_y; the deposit is contracted
+// with the current adjoint at once).  The chain rule then gives the same
+// vector-Jacobian product as the twelve passes of k_adj_particles, from the
+// same templated gather, push and deposit.
+template <typename R, int ORDER>
+__global__ __launch_bounds__(256) void k_adj_particles_staged(StepK<R> P, Fields<R> F,
+                                                              TapeParticles<R> T, Fields<R> LJ,
+                                                              Fields<R> LF, AdjSlots<R> A) {
+  using D2 = DualN<R, 2>;
+  using D9 = DualN<R, 9>;
+  using D6 = DualN<R, 6>;
+  const StepK<D2> P2 = to_dual<D2>(P);
+  const PushC<D9> push9 = to_dual<D9>(P.push);
+  const StepK<D6> P6 = to_dual<D6>(P);
+  const Geo& g = P.g;
+  const int n = *T.count;
+  const bool gk = P.galerkin != 0;
+  DualFetchN<R, 2> fetch{(const R* const*)F.F, g};
+  for (int p = blockIdx.x * blockDim.x + threadIdx.x; p < n; p += gridDim.x * blockDim.x) {
+    const int id = T.id[p];
+    if (id < 0) continue;
+    const R xi0 = T.xi[0][p], xi1 = T.xi[1][p];
+    const R w = T.w[p];
+    const Birth b = decode_id(P.L, id);
+    R r[3];
+    birth_offsets<R, 2>(P.L, id, r);
+    // gather: E, B and their derivatives along the displacement
+    D2 E2[3], B2[3];
+    int bc[3];
+    {
+      const D2 r2[3] = {D2((double)r[0]), D2((double)r[1]), D2(0.0)};
+      const D2 x2[3] = {D2::seed(xi0, 0), D2::seed(xi1, 1), D2(0.0)};
+      const Pos<D2> e0 = add_xi<D2, 2>(ion_at<D2, 2>(b, r2, P2.D0), x2);
+      bc[0] = e0.c[0];
+      bc[1] = e0.c[1];
+      bc[2] = 0;
+      gather<D2, 2, ORDER>(fetch, bc, e0, E2, B2, gk);
+    }
+    // push: derivatives along (E, B, du)
+    D9 E9[3], B9[3], du9[3], dv9[3], gam9;
+#pragma unroll
+    for (int c = 0; c < 3; c++) {
+      E9[c] = D9::seed(E2[c].v, c);
+      B9[c] = D9::seed(B2[c].v, 3 + c);
+      du9[c] = D9::seed(T.du[c][p], 6 + c);
+    }
+    boris_split(push9, E9, B9, du9, dv9, gam9);
+    // move, as the forward step: position axes (z, x) take v_z, v_x
+    const R xn0 = xi0 + dv9[2].v * P.dtd[0];
+    const R xn1 = xi1 + dv9[0].v * P.dtd[1];
+    // deposit, contracted with the current adjoint: derivatives along
+    // (xi_z, xi_x, xi'_z, xi'_x, w, v_y)
+    R s[6] = {(R)0, (R)0, (R)0, (R)0, (R)0, (R)0};
+    {
+      const D6 r6[3] = {D6((double)r[0]), D6((double)r[1]), D6(0.0)};
+      const Pos<D6> i0 = ion_at<D6, 2>(b, r6, P6.D0);
+      const Pos<D6> i1 = ion_at<D6, 2>(b, r6, P6.D1);
+      D6 xo[3] = {D6::seed(xi0, 0), D6::seed(xi1, 1), D6(0.0)};
+      D6 xn[3] = {D6::seed(xn0, 2), D6::seed(xn1, 3), D6(0.0)};
+      const D6 w6 = D6::seed(w, 4), vy = D6::seed(dv9[1].v, 5);
+      const Pos<D6> e0 = add_xi<D6, 2>(i0, xo);
+      const Pos<D6> e1 = add_xi<D6, 2>(i1, xn);
+      AdjJSinkN<R, 6> snk{(const R* const*)LJ.F, g, s};
+      bool done = false;
+      if constexpr (ORDER == 1) done = deposit2d_pair<D6>(P6, snk, bc, e0, e1, i0, i1, xo, xn, w6, vy);
+      if (!done) deposit2d<D6, ORDER>(P6, snk, bc, e0, e1, i0, i1, w6, vy, true);
+    }
+    // chain rule, outputs to inputs
+    const R axn0 = A.lxi[0][p] + s[2], axn1 = A.lxi[1][p] + s[3];
+    const R adv[3] = {axn1 * P.dtd[1], s[5], axn0 * P.dtd[0]};
+    const R adu[3] = {A.ldu[0][p], A.ldu[1][p], A.ldu[2][p]};
+    R ain[9];
+#pragma unroll
+    for (int k = 0; k < 9; k++) {
+      R a = (R)0;
+#pragma unroll
+      for (int c = 0; c < 3; c++) a += adu[c] * du9[c].d[k] + adv[c] * dv9[c].d[k];
+      ain[k] = a;
+    }
+    R axo[2] = {s[0] + axn0, s[1] + axn1};
+#pragma unroll
+    for (int m = 0; m < 2; m++)
+#pragma unroll
+      for (int c = 0; c < 3; c++) axo[m] += ain[c] * E2[c].d[m] + ain[3 + c] * B2[c].d[m];
+    A.lxi[0][p] = axo[0];
+    A.lxi[1][p] = axo[1];
+    A.ldu[0][p] = ain[6];
+    A.ldu[1][p] = ain[7];
+    A.ldu[2][p] = ain[8];
+    A.lw[p] += (double)s[4];
+    // gather transpose at the primal position
+    R xr[3] = {xi0, xi1, (R)0};
+    const Pos<R> e0p = add_xi<R, 2>(ion_at<R, 2>(b, r, P.D0), xr);
+    gather_transpose<R, ORDER>(LF.F, g, e0p, ain, ain + 3, gk);
   }
 }
 

@@ -25,7 +25,7 @@ import numpy as np
 import pytest
 
 import oracle as O
-from workloads import WORKLOADS, adjoint_setup, resolve_gpu, resolve_oracle
+from workloads import WORKLOADS, adjoint_setup, resolve_gpu, resolve_oracle, small
 
 pytestmark = pytest.mark.gpu
 
@@ -210,3 +210,51 @@ def test_adjoint_full_config_fp32(P):
     print("loss", L, "adjoint", {m: g[m] for m in fd}, "differences", fd, flush=True)
     for m, v in fd.items():
         assert abs(g[m] - v) <= 1e-3 * abs(v), (m, g[m], v)
+
+
+def _both_paths(P, W, precision):
+    cfg, init, nst = resolve_gpu(W, precision=precision, sort_interval=0)
+    cfg.deterministic = 1  # the taped forward repeats bitwise
+    dt = P.yee_dt(2, cfg.dz, cfg.dx, 1.0, cfg.cfl)
+    a = adjoint_setup(W, cfg.dz, P.beta, dt)
+    out = []
+    for per_direction in (True, False, False):
+        sim = P.Simulation(cfg, capacity=init["capacity"])
+        las = P.Laser()
+        for f, _ in P.Laser._fields_:
+            setattr(las, f, getattr(init["laser"], f))
+        sim.init_boosted_plasma(init["gamma_b"], knots_z=a["knots_z"], knots_n=list(a["knots_n"]),
+                                laser=las)
+        L = sim.forward_loss(nst, a["interval"], a["window"][0], a["window"][1], a["box"])
+        sim.adjoint_per_direction(per_direction)
+        da0, dn = sim.adjoint(len(a["knots_n"]))
+        sim.close()
+        out.append((L, np.array([da0] + list(dn))))
+    return out
+
+
+@pytest.mark.parametrize("case", ["linear", "quadratic", "quadratic_galerkin"])
+def test_staged_reverse_step_matches_per_direction(P, case):
+    """The staged per-particle product (gather, push and deposit each evaluated
+    once on a multi-tangent dual) against the twelve single-direction passes:
+    the same gradient by the chain rule, FP64, to 1e-12 relative to the
+    largest entry (observed: the order of the adjoint's atomic sums, which two
+    runs of one path already differ by)."""
+    W = {"linear": WORKLOADS["adjoint_2d_small"],
+         "quadratic": small("adjoint_2d_tiny", order=2),
+         "quadratic_galerkin": small("adjoint_2d_tiny", order=2, gather="energy")}[case]
+    print("case staged adjoint", case, flush=True)
+    (L1, g1), (L2, g2), (L3, g3) = _both_paths(P, W, "fp64")
+    assert L1 == L2 == L3
+    scale = np.abs(g1).max()
+    print("per-direction vs staged", np.abs(g2 - g1).max() / scale,
+          "staged run to run", np.abs(g3 - g2).max() / scale, flush=True)
+    assert np.abs(g2 - g1).max() <= 1e-12 * scale
+    assert np.abs(g3 - g2).max() <= 1e-12 * scale
+
+
+def test_staged_reverse_step_fp32(P):
+    print("case staged adjoint fp32", flush=True)
+    (L1, g1), (L2, g2), _ = _both_paths(P, WORKLOADS["adjoint_2d_small"], "fp32")
+    assert L1 == L2
+    assert np.abs(g2 - g1).max() <= 1e-4 * np.abs(g1).max()
