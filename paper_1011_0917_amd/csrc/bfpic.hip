@@ -110,6 +110,11 @@ constexpr bool kTileOrder = BFPIC_TILE_ORDER != 0;
 #define BFPIC_YEE_ROWS 16
 #endif
 constexpr int kYeeRows = BFPIC_YEE_ROWS;
+// Tile rows per window of the 2D fold + filter
+#ifndef BFPIC_FOLD_ROWS
+#define BFPIC_FOLD_ROWS 1
+#endif
+constexpr int kFoldRows = BFPIC_FOLD_ROWS;
 // Rows per thread of the 3D z sweep (fold + z passes)
 #ifndef BFPIC_FILT3_ROWS
 #define BFPIC_FILT3_ROWS 32
@@ -771,14 +776,16 @@ struct Impl {
   static void cols(bfpic_ctx* h, const FoldK<R>& K, const FiltK& fk, const Fields<R>& Jf) {
     using TG = TileGeom<2, ORDER, kT2Z, kT2X, 1, kExc>;
     constexpr int FX = 64 - 2 * NP;
-    // windows are rows of tiles: tile row t holds output rows gz0 + t TZ ...
+    // windows are rows of tiles: tile row t holds output rows gz0 + t TZ ...,
+    // a window kFoldRows of them
+    constexpr int WT = kFoldRows;
     const int tz_lo = floor_div(-K.gz0, kT2Z), tz_hi = floor_div(h->nz - K.gz0, kT2Z);
-    const int nseg = tz_hi - tz_lo + 1, nbx = (int)cdiv(h->nx, FX);
+    const int nseg = (tz_hi - tz_lo + WT) / WT, nbx = (int)cdiv(h->nx, FX);
     const int64_t nw = (int64_t)nseg * nbx;
     // FP64 windows run one component per wave (more waves in flight hide the
     // loads); FP32 ones all three (measured faster)
     constexpr int NC = sizeof(R) == 8 ? 1 : 3;
-    k_fold_filter_cols<R, NP, kT2Z, kT2X, TG::LZ, TG::LX, DET, NC>
+    k_fold_filter_cols<R, NP, kT2Z, kT2X, TG::LZ, TG::LX, DET, NC, WT>
         <<<dim3((unsigned)cdiv(nw, 4), 3 / NC), 256, 0, h->stream>>>(h->g, K, fk, Jf, tz_lo,
                                                                      nseg, nbx, h->ntz_max);
   }
@@ -815,10 +822,22 @@ struct Impl {
       T2.F[c] = (R*)h->Fs[3 + c];
       T1.F[3 + c] = T2.F[3 + c] = nullptr;
     }
-    const int nsz = (int)cdiv(h->nz + 1, SZ);
-    k_filt3_z<R, NP, SZ, kT3, kT3, kT3, DET>
-        <<<dim3((unsigned)cdiv((int64_t)nsz * g.plane, 256), 1, 3), 256, 0, h->stream>>>(
-            g, K, fk, T1, nsz);
+    if (!g.periodic_z && h->tiled) {
+      // windows aligned to the tile rows' regions (only the regions holding
+      // a node are read)
+      using TG = TileGeom<3, ORDER, kT3, kT3, kT3, kExc>;
+      const int m_first = floor_div(-K.gz0 - NP, kT3);
+      const int i0_first = K.gz0 + NP + m_first * kT3;
+      const int nsz = (int)cdiv(h->nz + 1 - i0_first, SZ);
+      k_filt3_z_aligned<R, NP, SZ, kT3, kT3, kT3, TG::LZ, TG::LX, TG::LY, DET>
+          <<<dim3((unsigned)cdiv((int64_t)nsz * g.plane, 256), 1, 3), 256, 0, h->stream>>>(
+              g, K, fk, T1, nsz, i0_first, m_first);
+    } else {
+      const int nsz = (int)cdiv(h->nz + 1, SZ);
+      k_filt3_z<R, NP, SZ, kT3, kT3, kT3, DET>
+          <<<dim3((unsigned)cdiv((int64_t)nsz * g.plane, 256), 1, 3), 256, 0, h->stream>>>(
+              g, K, fk, T1, nsz);
+    }
     const int nsx = (int)cdiv(h->nx, SX);
     k_filt3_x<R, NP, SX>
         <<<dim3((unsigned)cdiv((int64_t)(h->nz + 1) * nsx * h->ny, 256), 1, 3), 256, 0,

@@ -196,9 +196,11 @@ __global__ __launch_bounds__(256) void k_fold_filter(Geo g, FoldK<R> K, FiltK fk
 }
 
 // 2D fold + filter on register columns.  A wave owns NC of the three current
-// components (1 or 3; blockIdx.y picks them) over a window of TZ output rows (the z extent of one row of
-// co-moving tiles, so that every row's candidate tiles and local row are
-// fixed at compile time) by 64 - 2 NP output columns.  Lane c holds column j0 - NP + c over the TZ + 2 NP rows
+// components (1 or 3; blockIdx.y picks them) over a window of WT TZ output
+// rows (the z extent of WT rows of co-moving tiles, so that every row's
+// candidate tiles and local row are fixed at compile time; the 2 NP halo rows
+// are read once per window, so longer windows re-read less) by 64 - 2 NP
+// output columns.  Lane c holds column j0 - NP + c over the TZ + 2 NP rows
 // the filter needs; the z passes run in registers, the x passes exchange
 // neighbours across lanes.  After NP passes along an axis the values NP or
 // more nodes inside the window are exact; those are stored.  Tile rows
@@ -210,12 +212,11 @@ __global__ __launch_bounds__(256) void k_fold_filter(Geo g, FoldK<R> K, FiltK fk
 // the order of fold_at.
 // A wave that folds all three components gets the register budget of four
 // waves per SIMD, so that each window's loads are all in flight at once.
-template <typename R, int NP, int TZ, int TX, int LZ, int LX, bool DET, int NC>
+template <typename R, int NP, int TZ, int TX, int LZ, int LX, bool DET, int NC, int WT = 1>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(1, NC == 3 ? 4 : 8))) void
-k_fold_filter_cols(Geo g, FoldK<R> K, FiltK fk,
-                                                          Fields<R> Jf, int tz_lo, int nseg,
-                                                          int nbx, int zero_row) {
-  constexpr int H = NP, L = TZ + 2 * H;
+k_fold_filter_cols(Geo g, FoldK<R> K, FiltK fk, Fields<R> Jf, int tz_lo, int nseg, int nbx,
+                   int zero_row) {
+  constexpr int H = NP, L = WT * TZ + 2 * H;
   constexpr int FX = 64 - 2 * H;
   static_assert(H <= TZ && LZ <= 2 * TZ, "window geometry");
   const int lane = threadIdx.x & 63;
@@ -225,7 +226,7 @@ k_fold_filter_cols(Geo g, FoldK<R> K, FiltK fk,
                                                (int)(threadIdx.x >> 6));
   if (w >= nseg * nbx) return;  // the whole wave leaves together
   const int sw = w / nbx, bx = w - sw * nbx;
-  const int tzw = tz_lo + sw;
+  const int tzw = tz_lo + sw * WT;
   const int iw0 = K.gz0 + tzw * TZ;  // first output row of the window
   const int j0 = bx * FX;
   const int j = j0 - H + lane;
@@ -240,12 +241,13 @@ k_fold_filter_cols(Geo g, FoldK<R> K, FiltK fk,
   const int xa = hx * 3 * LV + lx;
   const int xb = vb ? txb * 3 * LV + lx + TX : xa;
   const int jw = wrap_small(j, g.nx);
-  // tile rows tzw - 2 .. tzw + 1
+  // tile rows tzw - 2 .. tzw + WT
+  constexpr int NTR = WT + 3;
   using A = typename std::conditional<DET, long long, R>::type;  // fold sums
   const A* scratch = reinterpret_cast<const A*>(K.scratch);
-  int64_t trow[4];
+  int64_t trow[NTR];
 #pragma unroll
-  for (int d = 0; d < 4; d++) {
+  for (int d = 0; d < NTR; d++) {
     int t = tzw + d - 2;
     if (g.periodic_z) t = wrap_small(t, K.ntz);
     else if (t < 0 || t >= K.ntz) t = zero_row;
@@ -261,10 +263,10 @@ k_fold_filter_cols(Geo g, FoldK<R> K, FiltK fk,
     const bool interior = g.periodic_z || (ilo >= 0 && ihi <= row_hi(g, hz));
     // per-lane pointers to row 0 of each candidate tile; rows are then
     // compile-time offsets
-    const A* pA[4];
-    const A* pB[4];
+    const A* pA[NTR];
+    const A* pB[NTR];
 #pragma unroll
-    for (int d = 0; d < 4; d++) {
+    for (int d = 0; d < NTR; d++) {
       pA[d] = scratch + trow[d] + comp * LV + xa;
       pB[d] = scratch + trow[d] + comp * LV + xb;
     }
@@ -326,7 +328,7 @@ k_fold_filter_cols(Geo g, FoldK<R> K, FiltK fk,
     }
     R* out = Jf.F[comp];
 #pragma unroll
-    for (int r = H; r < H + TZ; r++) {
+    for (int r = H; r < H + WT * TZ; r++) {
       R x = v[r];
 #pragma unroll
       for (int p = 0; p < NP; p++) {
@@ -397,6 +399,133 @@ __global__ __launch_bounds__(256) void k_filt3_z(Geo g, FoldK<R> K, FiltK fk, Fi
     const int i = i0 + r - H;
     if (in_domain(g, hz, i)) o[(int64_t)(i + kGuard) * g.plane + q] = v[r];
   }
+}
+
+// z sweep with the fold, open z, windows aligned to the tile rows: window
+// rows start where a tile row's region starts (row gz0 + m TZ), so that each
+// window row's local row in a region, and with it the set of tile rows whose
+// regions hold it, are compile-time constants; only the regions that do
+// hold a node are read.  Along x the candidates are the same for a whole
+// thread column (NBX: 3 where some lane of the wave needs a third, else 2),
+// along y a lane without a third candidate reads its first one again and
+// discards it.  Same sums, in the same order, as fold_at.
+template <typename R, int NP, int SZ, int TZ, int TX, int TY, int LZ, int LX, int LY, bool DET,
+          int NBX>
+__device__ __forceinline__ void filt3_z_aligned_body(const Geo& g, const FoldK<R>& K,
+                                                     const FiltK& fk, Fields<R>& out, int comp,
+                                                     int i0, int m, int q, int j, int k) {
+  constexpr int H = NP, L = SZ + 2 * H;
+  constexpr int LV = LZ * LX * LY;
+  using A = typename std::conditional<DET, long long, R>::type;
+  const A* scratch = reinterpret_cast<const A*>(K.scratch);
+  const int hz = half_z_j(comp);
+  // x and y candidates of this column
+  const int qx = wrap_small(j - K.gx0, g.nx), qy = wrap_small(k - K.gy0, g.ny);
+  const int hx = qx / TX, lx = qx - hx * TX;
+  const int hy = qy / TY, ly = qy - hy * TY;
+  int off[NBX][3];
+  bool val[NBX][3];
+#pragma unroll
+  for (int b = 0; b < NBX; b++) {
+    int tx = hx - b;
+    if (tx < 0) tx += K.ntx;
+    const int rx = lx + b * TX;
+#pragma unroll
+    for (int c = 0; c < 3; c++) {
+      int ty = hy - c;
+      if (ty < 0) ty += K.nty;
+      const int ry = ly + c * TY;
+      val[b][c] = rx < LX && ry < LY;
+      off[b][c] = val[b][c] ? (tx * K.nty + ty) * 3 * LV + rx * LY + ry : 0;
+    }
+  }
+#pragma unroll
+  for (int b = 0; b < NBX; b++)
+#pragma unroll
+    for (int c = 0; c < 3; c++)
+      if (!val[b][c]) off[b][c] = off[0][0];
+  // tile rows m - 2 .. m + (L - 1) / TZ; outside [0, ntz) the zero row
+  constexpr int NTR = (L - 1) / TZ + 3;
+  const int64_t tile_row = (int64_t)K.ntx * K.nty * 3 * LV;
+  const A* rowp[NTR];
+#pragma unroll
+  for (int d = 0; d < NTR; d++) {
+    const int t = m + d - 2;
+    rowp[d] = scratch + (t >= 0 && t < K.ntz ? (int64_t)t * tile_row : K.zero_base) + comp * LV;
+  }
+  const int r0 = K.o.rows[0], r1 = K.o.rows[1];
+  R v[L];
+#pragma unroll
+  for (int r = 0; r < L; r++) {
+    const int lz = r % TZ, hzr = r / TZ;  // tile row m + hzr holds row r at local lz
+    A acc = (A)0;
+#pragma unroll
+    for (int a = 0; a < 3; a++) {
+      if (lz + a * TZ >= LZ) continue;  // compile-time
+      const A* rp = rowp[hzr - a + 2] + (lz + a * TZ) * LX * LY;
+#pragma unroll
+      for (int b = 0; b < NBX; b++)
+#pragma unroll
+        for (int c = 0; c < 3; c++) {
+          const A x = rp[off[b][c]];
+          acc += val[b][c] ? x : (A)0;
+        }
+    }
+    const int i = i0 - H + r;
+    if (i >= r0 && i <= r1 && i >= -kGuard && i <= g.nz + kGuard) {
+      const int64_t n = (int64_t)(i + kGuard) * g.plane + q;
+      if constexpr (DET) acc += K.o.Jq[comp][n];
+      else acc += K.o.J[comp][n];
+    }
+    R x;
+    if constexpr (DET) x = (R)((double)acc * K.inv_scale);
+    else x = acc;
+    v[r] = in_domain(g, hz, i) ? x : (R)0;
+  }
+#pragma unroll
+  for (int p = 0; p < NP; p++) {
+    const R a = filt_pass_w<R>(fk, p), b = filt_pass_c<R>(fk, p);
+    R prev = v[0];
+#pragma unroll
+    for (int r = 1; r < L - 1; r++) {
+      const R cur = v[r];
+      v[r] = a * prev + b * cur + a * v[r + 1];
+      prev = cur;
+    }
+#pragma unroll
+    for (int r = 0; r < L; r++)
+      if (!in_domain(g, hz, i0 - H + r)) v[r] = (R)0;
+  }
+  R* o = out.F[comp];
+#pragma unroll
+  for (int r = H; r < H + SZ; r++) {
+    const int i = i0 + r - H;
+    if (in_domain(g, hz, i)) o[(int64_t)(i + kGuard) * g.plane + q] = v[r];
+  }
+}
+
+template <typename R, int NP, int SZ, int TZ, int TX, int TY, int LZ, int LX, int LY, bool DET>
+__global__ __launch_bounds__(256) void k_filt3_z_aligned(Geo g, FoldK<R> K, FiltK fk,
+                                                         Fields<R> out, int nseg, int i0_first,
+                                                         int m_first) {
+  static_assert(SZ % TZ == 0, "windows of whole tile rows");
+  const int comp = blockIdx.z;
+  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const bool live = t < (int64_t)nseg * g.plane;
+  const int tt = live ? (int)t : 0;
+  const int seg = tt / g.plane;
+  const int q = tt - seg * g.plane;
+  const int j = q / g.ny, k = q - j * g.ny;
+  const int i0 = i0_first + seg * SZ, m = m_first + seg * (SZ / TZ);
+  const int qx = wrap_small(j - K.gx0, g.nx);
+  const bool third = live && qx % TX + 2 * TX < LX;
+  if (!live) return;
+  if (__any(third))
+    filt3_z_aligned_body<R, NP, SZ, TZ, TX, TY, LZ, LX, LY, DET, 3>(g, K, fk, out, comp, i0, m,
+                                                                    q, j, k);
+  else
+    filt3_z_aligned_body<R, NP, SZ, TZ, TX, TY, LZ, LX, LY, DET, 2>(g, K, fk, out, comp, i0, m,
+                                                                    q, j, k);
 }
 
 // x sweep (periodic): thread = one (i, k) line and one window of SX outputs.

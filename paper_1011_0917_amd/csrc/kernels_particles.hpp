@@ -92,8 +92,11 @@ struct LdsFetch {
 // fetch exposes its axes (row offset, column offset, y offset) so that
 // gather_axes forms each once per particle; a row outside storage (open z)
 // maps to offset 0 and reports !ok, and its weight is then zeroed.
-template <typename R>
+// YC: the tile's region lies inside [0, ny) along y (no wrap), so that a
+// stencil's y nodes are consecutive in memory and load as one vector.
+template <typename R, bool YC = false>
 struct RegionFetch {
+  static constexpr bool kYContig = YC;
   const R* const* F;
   Geo g;
   int gz0, gx0, gy0;
@@ -109,6 +112,7 @@ struct RegionFetch {
   }
   __device__ __forceinline__ int col(int j) const { return wrap_once(j + gx0, g.nx) * g.ny; }
   __device__ __forceinline__ int dep(int k) const {
+    if constexpr (YC) return k + gy0;
     return g.ny > 1 ? wrap_once(k + gy0, g.ny) : 0;
   }
   __device__ __forceinline__ const R* base(int comp, int64_t r) const { return F[comp] + r; }
@@ -122,8 +126,13 @@ struct RegionFetch {
 
 template <class F>
 struct HasAxes : std::false_type {};
+template <typename R, bool YC>
+struct HasAxes<RegionFetch<R, YC>> : std::true_type {};
+
+template <class F>
+struct YContig : std::false_type {};
 template <typename R>
-struct HasAxes<RegionFetch<R>> : std::true_type {};
+struct YContig<RegionFetch<R, true>> : std::true_type {};
 
 template <typename R>
 struct GlobalFetch {
@@ -282,9 +291,15 @@ __device__ __forceinline__ R interp_axes(const F& f, int comp, const int64_t* zr
   for (int a = 0; a < N; a++) {
     const R* rp = f.base(comp, zr[a]);
 #pragma unroll
-    for (int b = 0; b < N; b++)
+    for (int b = 0; b < N; b++) {
+      if constexpr (DIM == 3 && YContig<F>::value) {
+        // consecutive y nodes: one multi-dword load (element alignment only)
+        __builtin_memcpy(&v[a][b][0], rp + xc[b] + yc[0], sizeof(R) * NY);
+      } else {
 #pragma unroll
-      for (int c = 0; c < NY; c++) v[a][b][c] = rp[xc[b] + (DIM == 3 ? yc[c] : 0)];
+        for (int c = 0; c < NY; c++) v[a][b][c] = rp[xc[b] + (DIM == 3 ? yc[c] : 0)];
+      }
+    }
   }
   R acc = (R)0;
 #pragma unroll
@@ -870,8 +885,21 @@ __global__ __launch_bounds__(256) void k_gpd_global(StepK<R> P, Fields<R> F, PSo
   const int total = ntail + (strag ? *nstrag : 0);
   GlobalFetch<R> f{(const R* const*)F.F, P.g};
   typename std::conditional<DET, GlobalSinkFx<R>, GlobalSink<R>>::type sk{O, P.g};
+  // An injected tail is whole lattice columns, the ppc slots of a cell in a
+  // row: it is taken slot-major (thread q: cell q mod m, slot q / m), so that
+  // the lanes of a wave deposit around distinct cells rather than piling
+  // their atomics onto the nodes of one cell.
+  const int ppc = P.L.ppc;
+  const bool il = from_sorted && ppc > 1 && ntail % ppc == 0;
+  const int m = il ? ntail / ppc : 1;
   for (int q = blockIdx.x * blockDim.x + threadIdx.x; q < total; q += gridDim.x * blockDim.x) {
-    const int p = q < ntail ? first + q : strag[q - ntail];
+    int p;
+    if (q < ntail) {
+      const int qs = q / m;
+      p = first + (il ? (q - qs * m) * ppc + qs : q);
+    } else {
+      p = strag[q - ntail];
+    }
     const int id = S.id[p];
     if (id < 0) continue;
     R xi[3], du[3], w;
@@ -1018,64 +1046,73 @@ k_gpd_tiled(StepK<R> P, Fields<R> F, PSoA<R> S, TileK T, Ovf<R> O, void* scratch
     far_rows[1] = INT_MIN;
   }
   __syncthreads();
-  typename std::conditional<STAGE, LdsFetch<R, LX, LY>, RegionFetch<R>>::type lf;
-  if constexpr (STAGE) lf = LdsFetch<R, LX, LY>{sF, LV};
-  else lf = RegionFetch<R>{(const R* const*)F.F, g, g.periodic_z ? wrapi(gz0, g.nz) : gz0, gx0, gy0};
   LdsSinkT<A, LX, LY, DET> ls{sJ, LV};
   const int p0 = T.start[t], p1 = T.start[t + 1];
-  // the whole state of the next particle is loaded while this one is pushed
-  int p = p0 + (int)threadIdx.x;
-  int id_n = -1;
-  R xn[3] = {(R)0, (R)0, (R)0}, un[3] = {(R)0, (R)0, (R)0}, wn = (R)0;
-  if (p < p1) {
-    id_n = S.id[p];
-    load_state(S, p, xn, un, wn);
-  }
-  for (; p < p1; p += NT) {
-    const int id = id_n;
-    R xi[3] = {xn[0], xn[1], xn[2]}, du[3] = {un[0], un[1], un[2]};
-    const R w = wn;
-    if (p + NT < p1) {
-      id_n = S.id[p + NT];
-      load_state(S, p + NT, xn, un, wn);
+  auto particles = [&](const auto& lf) {
+    // the whole state of the next particle is loaded while this one is pushed
+    int p = p0 + (int)threadIdx.x;
+    int id_n = -1;
+    R xn[3] = {(R)0, (R)0, (R)0}, un[3] = {(R)0, (R)0, (R)0}, wn = (R)0;
+    if (p < p1) {
+      id_n = S.id[p];
+      load_state(S, p, xn, un, wn);
     }
-    if (id < 0) continue;
-    Birth b = decode_id(P.L, id);
-    R r[3];
-    birth_offsets<R, DIM>(P.L, id, r);
-    Pos<R> i0 = ion_at<R, DIM>(b, r, P.D0);
-    Pos<R> e0 = add_xi<R, DIM>(i0, xi);
-    // cells relative to the LDS region (wrapped where the axis is periodic)
-    int rz = e0.c[0] - gz0, riz = i0.c[0] - gz0;
-    if (g.periodic_z) {
-      rz = wrap_once(rz, g.nz);
-      riz = wrap_once(riz, g.nz);
+    for (; p < p1; p += NT) {
+      const int id = id_n;
+      R xi[3] = {xn[0], xn[1], xn[2]}, du[3] = {un[0], un[1], un[2]};
+      const R w = wn;
+      if (p + NT < p1) {
+        id_n = S.id[p + NT];
+        load_state(S, p + NT, xn, un, wn);
+      }
+      if (id < 0) continue;
+      Birth b = decode_id(P.L, id);
+      R r[3];
+      birth_offsets<R, DIM>(P.L, id, r);
+      Pos<R> i0 = ion_at<R, DIM>(b, r, P.D0);
+      Pos<R> e0 = add_xi<R, DIM>(i0, xi);
+      // cells relative to the LDS region (wrapped where the axis is periodic)
+      int rz = e0.c[0] - gz0, riz = i0.c[0] - gz0;
+      if (g.periodic_z) {
+        rz = wrap_once(rz, g.nz);
+        riz = wrap_once(riz, g.nz);
+      }
+      const int rx = wrap_once(e0.c[1] - gx0, g.nx), rix = wrap_once(i0.c[1] - gx0, g.nx);
+      // the electron's stencil must lie in the region; the partner's may not
+      // (its separate stencil then reaches the overflow grid)
+      bool inside = rz >= TG::HLO && rz < LZ - TG::HHI && rx >= TG::HLO && rx < LX - TG::HHI;
+      bool near = riz >= TG::HLO && riz < LZ - TG::HHI && rix >= TG::HLO && rix < LX - TG::HHI;
+      int ry = 0;
+      if (DIM == 3) {
+        ry = wrap_once(e0.c[2] - gy0, g.ny);
+        const int riy = wrap_once(i0.c[2] - gy0, g.ny);
+        inside = inside && ry >= TG::HLO && ry < LY - TG::HHI;
+        near = near && riy >= TG::HLO && riy < LY - TG::HHI;
+      }
+      if (!inside) {
+        T.strag[atomicAdd(T.nstrag, 1)] = p;
+        continue;
+      }
+      Pos<R> i1 = ion_at<R, DIM>(b, r, P.D1);
+      int bc[3] = {rz, rx, ry};
+      bool dead = particle_step<R, DIM, ORDER>(P, lf, ls, bc, e0, i0, i1, xi, du, w, NoHook(), near);
+      if (!near) {
+        atomicMin(&far_rows[0], min(e0.c[0], i0.c[0]) - ORDER - 1);
+        atomicMax(&far_rows[1], max(e0.c[0], i0.c[0]) + ORDER + 2);
+        partner_far<R, DIM, ORDER, DET>(P, O, i0, i1, w);
+      }
+      store_state<R, DIM>(S, p, xi, du, dead);
     }
-    const int rx = wrap_once(e0.c[1] - gx0, g.nx), rix = wrap_once(i0.c[1] - gx0, g.nx);
-    // the electron's stencil must lie in the region; the partner's may not
-    // (its separate stencil then reaches the overflow grid)
-    bool inside = rz >= TG::HLO && rz < LZ - TG::HHI && rx >= TG::HLO && rx < LX - TG::HHI;
-    bool near = riz >= TG::HLO && riz < LZ - TG::HHI && rix >= TG::HLO && rix < LX - TG::HHI;
-    int ry = 0;
-    if (DIM == 3) {
-      ry = wrap_once(e0.c[2] - gy0, g.ny);
-      const int riy = wrap_once(i0.c[2] - gy0, g.ny);
-      inside = inside && ry >= TG::HLO && ry < LY - TG::HHI;
-      near = near && riy >= TG::HLO && riy < LY - TG::HHI;
-    }
-    if (!inside) {
-      T.strag[atomicAdd(T.nstrag, 1)] = p;
-      continue;
-    }
-    Pos<R> i1 = ion_at<R, DIM>(b, r, P.D1);
-    int bc[3] = {rz, rx, ry};
-    bool dead = particle_step<R, DIM, ORDER>(P, lf, ls, bc, e0, i0, i1, xi, du, w, NoHook(), near);
-    if (!near) {
-      atomicMin(&far_rows[0], min(e0.c[0], i0.c[0]) - ORDER - 1);
-      atomicMax(&far_rows[1], max(e0.c[0], i0.c[0]) + ORDER + 2);
-      partner_far<R, DIM, ORDER, DET>(P, O, i0, i1, w);
-    }
-    store_state<R, DIM>(S, p, xi, du, dead);
+  };
+  if constexpr (STAGE) {
+    particles(LdsFetch<R, LX, LY>{sF, LV});
+  } else {
+    const int gzr = g.periodic_z ? wrapi(gz0, g.nz) : gz0;
+    // a region inside the grid along y: the stencils' y rows load as vectors
+    if (DIM == 3 && gy0 >= 0 && gy0 + LY <= g.ny)
+      particles(RegionFetch<R, true>{(const R* const*)F.F, g, gzr, gx0, gy0});
+    else
+      particles(RegionFetch<R>{(const R* const*)F.F, g, gzr, gx0, gy0});
   }
   __syncthreads();
   if (threadIdx.x == 0 && far_rows[0] <= far_rows[1]) {
