@@ -117,7 +117,7 @@ constexpr int kYeeRows = BFPIC_YEE_ROWS;
 constexpr int kFoldRows = BFPIC_FOLD_ROWS;
 // Rows per thread of the 3D z sweep (fold + z passes)
 #ifndef BFPIC_FILT3_ROWS
-#define BFPIC_FILT3_ROWS 32
+#define BFPIC_FILT3_ROWS 16
 #endif
 constexpr int kFilt3Rows = BFPIC_FILT3_ROWS;
 constexpr int kF3 = 8;
