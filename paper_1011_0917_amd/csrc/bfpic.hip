@@ -783,11 +783,16 @@ struct Impl {
     const int nseg = (tz_hi - tz_lo + WT) / WT, nbx = (int)cdiv(h->nx, FX);
     const int64_t nw = (int64_t)nseg * nbx;
     // FP64 windows run one component per wave (more waves in flight hide the
-    // loads); FP32 ones all three (measured faster)
-    constexpr int NC = sizeof(R) == 8 ? 1 : 3;
-    k_fold_filter_cols<R, NP, kT2Z, kT2X, TG::LZ, TG::LX, DET, NC, WT>
-        <<<dim3((unsigned)cdiv(nw, 4), 3 / NC), 256, 0, h->stream>>>(h->g, K, fk, Jf, tz_lo,
-                                                                     nseg, nbx, h->ntz_max);
+    // loads); FP32 ones all three (measured faster) unless the grid has too
+    // few windows to give every SIMD two waves
+    if (sizeof(R) == 8 || nw < 2048)
+      k_fold_filter_cols<R, NP, kT2Z, kT2X, TG::LZ, TG::LX, DET, 1, WT>
+          <<<dim3((unsigned)cdiv(nw, 4), 3), 256, 0, h->stream>>>(h->g, K, fk, Jf, tz_lo, nseg,
+                                                                  nbx, h->ntz_max);
+    else
+      k_fold_filter_cols<R, NP, kT2Z, kT2X, TG::LZ, TG::LX, DET, 3, WT>
+          <<<dim3((unsigned)cdiv(nw, 4), 1), 256, 0, h->stream>>>(h->g, K, fk, Jf, tz_lo, nseg,
+                                                                  nbx, h->ntz_max);
   }
   template <bool DET>
   static bool fold_filter_cols(bfpic_ctx* h, const FoldK<R>& K, const FiltK& fk,
@@ -1178,17 +1183,29 @@ struct Impl {
       k_note_ids<<<(unsigned)cdiv(n, 256), 256, 0, h->stream>>>((const int*)h->pid[h->cur],
                                                                  h->counts, T.idb);
     if (slot >= 0) {
+      // the step's tape in one launch: E, B, the particle slots, the slot
+      // count and the witnesses
       uint8_t* b = T.sg + (int64_t)slot * T.sgb;
       const int64_t gb = gbytes(h);
-      for (int c = 0; c < 6 && !rc; c++) rc = copy(h, b + off_f(h, c), h->F[c], gb);
+      CopyBatch cb;
+      int nc = 0;
+      auto add = [&](void* dst, const void* src, int64_t bytes) {
+        if (bytes <= 0) return;
+        cb.dst[nc] = dst;
+        cb.src[nc] = src;
+        cb.words[nc] = bytes / 4;
+        nc++;
+      };
+      for (int c = 0; c < 6; c++) add(b + off_f(h, c), h->F[c], gb);
       void* parts[6] = {h->pid[h->cur], h->pxi[h->cur][0], h->pxi[h->cur][1], h->pdu[h->cur][0],
                         h->pdu[h->cur][1], h->pdu[h->cur][2]};
-      for (int q = 0; q < 6 && !rc; q++)
-        rc = copy(h, b + (q == 0 ? off_id(h) : off_r(h, q - 1)), parts[q],
-                  n * (q == 0 ? 4 : (int64_t)sizeof(R)));
-      if (!rc) rc = copy(h, b + off_tail(h, false), h->counts, 4);
-      if (!rc && h->nwit > 0) rc = copy(h, b + off_wit(h, false), h->wit, h->nwit * 48);
-      if (rc) return rc;
+      for (int q = 0; q < 6; q++)
+        add(b + (q == 0 ? off_id(h) : off_r(h, q - 1)), parts[q],
+            n * (q == 0 ? 4 : (int64_t)sizeof(R)));
+      add(b + off_tail(h, false), h->counts, 4);
+      if (h->nwit > 0) add(b + off_wit(h, false), h->wit, h->nwit * 48);
+      k_copy_batch<<<dim3(256, (unsigned)nc), 256, 0, h->stream>>>(cb);
+      HIPCHK(h, hipGetLastError());
     }
     StepK<R> P = step_consts(h);
     if (h->nwit > 0) {
@@ -1323,6 +1340,11 @@ struct Impl {
         LF.F[3 + c] = T.LB[c];
         LJ.F[3 + c] = nullptr;
       }
+      Grid3R<R> fio;
+      for (int c = 0; c < 3; c++) {
+        fio.in[c] = T.LJf[c];
+        fio.out[c] = T.LJ[c];
+      }
       AdjSlots<R> A;
       for (int a = 0; a < 2; a++) A.lxi[a] = T.lxi[a];
       for (int a = 0; a < 3; a++) A.ldu[a] = T.ldu[a];
@@ -1356,9 +1378,8 @@ struct Impl {
           if (!g.periodic_z) k_adj_mur_post<R><<<nbp, 256, 0, h->stream>>>(g, Y, T.mur);
           Y.h = (R)(0.5 * h->dt);
           k_adj_yee_b<R><<<nbg, 256, 0, h->stream>>>(g, Y);
-          for (int c = 0; c < 3; c++)
-            k_filter_grid_r<R, kF2Z, kF2X><<<(unsigned)(fnbz * fnbx), 256, flds, h->stream>>>(
-                g, fk, T.LJf[c], T.LJ[c], c == 2 ? 1 : 0, fnbz, fnbx);
+          k_filter_grid_r3<R, kF2Z, kF2X>
+              <<<dim3((unsigned)(fnbz * fnbx), 3), 256, flds, h->stream>>>(g, fk, fio, fnbz, fnbx);
           // particles of step s
           uint8_t* b = T.sg + (int64_t)(s - s0) * T.sgb;
           const int64_t save_step = h->step;

@@ -449,7 +449,17 @@ __global__ __launch_bounds__(256) void k_adj_particles_staged(StepK<R> P, Fields
   const int n = *T.count;
   const bool gk = P.galerkin != 0;
   DualFetchN<R, 2> fetch{(const R* const*)F.F, g};
-  for (int p = blockIdx.x * blockDim.x + threadIdx.x; p < n; p += gridDim.x * blockDim.x) {
+  // Slots stay in creation order during a taped run (no sort): whole lattice
+  // columns, the ppc slots of a cell in a row.  They are taken slot-major
+  // (thread q: cell q mod m, slot q / m), so that the lanes of a wave scatter
+  // their field adjoints around distinct cells rather than onto one cell's
+  // nodes.
+  const int ppc = P.L.ppc;
+  const bool il = ppc > 1 && n % ppc == 0;
+  const int m = il ? n / ppc : 1;
+  for (int q = blockIdx.x * blockDim.x + threadIdx.x; q < n; q += gridDim.x * blockDim.x) {
+    const int qs = q / m;
+    const int p = il ? (q - qs * m) * ppc + qs : q;
     const int id = T.id[p];
     if (id < 0) continue;
     const R xi0 = T.xi[0][p], xi1 = T.xi[1][p];
@@ -659,6 +669,56 @@ __global__ __launch_bounds__(256) void k_filter_grid_r(Geo g, FiltK fk, const R*
   const int bx = b % nbx, bz = b / nbx;
   GridSrcR<R> src{in, g};
   filter_tile<R, 2, FZ, FX, 1>(g, fk, half_z, bz * FZ, bx * FX, 0, src, out, lds);
+}
+
+// The same for the three current components in one launch (blockIdx.y: Jx,
+// Jy, Jz; Jz on the half rows).
+template <typename R>
+struct Grid3R {
+  const R* in[3];
+  R* out[3];
+};
+
+template <typename R, int FZ, int FX>
+__global__ __launch_bounds__(256) void k_filter_grid_r3(Geo g, FiltK fk, Grid3R<R> io, int nbz,
+                                                        int nbx) {
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  R* lds = reinterpret_cast<R*>(smem_raw);
+  const int c = blockIdx.y;
+  const int b = blockIdx.x;
+  const int bx = b % nbx, bz = b / nbx;
+  GridSrcR<R> src{io.in[c], g};
+  filter_tile<R, 2, FZ, FX, 1>(g, fk, c == 2 ? 1 : 0, bz * FZ, bx * FX, 0, src, io.out[c], lds);
+}
+
+// --------------------------------------------------------------------------
+// Several device copies in one launch (the per-step tape): copy blockIdx.y
+// moves words[y] 32-bit words; 16-byte chunks where both ends are 16-byte
+// aligned, then the remaining words.
+// --------------------------------------------------------------------------
+constexpr int kMaxCopies = 16;
+struct CopyBatch {
+  const void* src[kMaxCopies];
+  void* dst[kMaxCopies];
+  int64_t words[kMaxCopies];
+};
+
+__global__ __launch_bounds__(256) void k_copy_batch(CopyBatch cb) {
+  const int c = blockIdx.y;
+  const int64_t nw = cb.words[c];
+  const uint32_t* s = reinterpret_cast<const uint32_t*>(cb.src[c]);
+  uint32_t* d = reinterpret_cast<uint32_t*>(cb.dst[c]);
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  const int64_t t0 = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  int64_t done = 0;
+  if (((reinterpret_cast<uintptr_t>(s) | reinterpret_cast<uintptr_t>(d)) & 15) == 0) {
+    const int64_t n4 = nw / 4;
+    const uint4* s4 = reinterpret_cast<const uint4*>(s);
+    uint4* d4 = reinterpret_cast<uint4*>(d);
+    for (int64_t q = t0; q < n4; q += stride) d4[q] = s4[q];
+    done = n4 * 4;
+  }
+  for (int64_t q = done + t0; q < nw; q += stride) d[q] = s[q];
 }
 
 // --------------------------------------------------------------------------
