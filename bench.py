@@ -226,6 +226,7 @@ def side_workload(name, steps, warmup, sort_interval):
            "step_roofline_frac": step_bytes / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS,
            "roofline": gpd_roofline(r),
            "kernel_ms_per_step": {k: v["ms"] / r["steps"] for k, v in r["kernels"].items()}}
+    out["roofline"]["traffic"] = measured_traffic("k_gpd_tiled", name, "fp32")
     if dim == 3 and W["order"] == 2:
         kms = out["roofline"]["kernel_ms"]
         tf = FLOPS_PER_PARTICLE_3D_QUADRATIC * r["particles"] / (kms * 1e-3) / 1e12
