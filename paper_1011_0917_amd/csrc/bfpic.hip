@@ -204,6 +204,8 @@ struct bfpic_ctx {
   int adj_nwit = 0;          // witnesses bound during the taped run
   bfpic_loss adj_loss{};
   std::vector<HostCkpt> ckpt;
+  std::vector<int64_t> adj_wc;  // taped run: window cells at the start of each step
+  std::vector<int> adj_shift;   // taped run: window shift at the end of each step
   uint8_t* tape = nullptr;
   int64_t tape_bytes = 0;
   // timing
@@ -1176,6 +1178,8 @@ struct Impl {
   // One step of a taped run; slot >= 0 also stores the state at the start of
   // the step (after injection) as taped step `slot`.
   static int taped_step(bfpic_ctx* h, const Tape& T, int slot) {
+    const int64_t s = h->step;
+    h->adj_wc[(size_t)s] = h->window_cells;
     int rc = inject(h);
     if (rc) return rc;
     const int64_t n = h->slots_bound;
@@ -1217,6 +1221,17 @@ struct Impl {
     rc = yee(h);
     if (rc) return rc;
     h->step++;
+    // the moving window, as in a plain step; the loss reads the shifted state
+    int due = 0;
+    if (h->cfg.auto_window && !h->g.periodic_z) {
+      const double t = (double)h->step * h->dt;
+      due = (int)(std::floor((h->cfg.beta_window * t) / h->dz) - (double)h->window_cells);
+      if (due != 0) {
+        rc = shift(h, due);
+        if (rc) return rc;
+      }
+    }
+    h->adj_shift[(size_t)s] = due;
     const bfpic_loss& L = h->adj_loss;
     if (!h->adj_recompute && h->step >= L.step_first && h->step <= L.step_last) {
       const int nb = (L.i1 - L.i0 + 1) * (L.j1 - L.j0 + 1);
@@ -1234,8 +1249,6 @@ struct Impl {
     } else {
       if (!h->inited) return fail(h, BFPIC_ERR_STATE, "init_boosted_plasma first");
       if (nsteps < 1 || interval < 1) return fail(h, BFPIC_ERR_ARG, "nsteps, interval >= 1");
-      if (h->cfg.auto_window || h->cfg.beta_window != 0.0)
-        return fail(h, BFPIC_ERR_UNSUPPORTED, "the adjoint is built for runs without window");
       return BFPIC_OK;
     }
   }
@@ -1263,6 +1276,8 @@ struct Impl {
     h->adj_recompute = false;
     h->no_sort = true;
     h->ckpt.assign((size_t)cdiv(nsteps, interval), bfpic_ctx::HostCkpt{});
+    h->adj_wc.assign((size_t)nsteps, 0);
+    h->adj_shift.assign((size_t)nsteps, 0);
     HIPCHK(h, hipMemsetAsync(T.acc, 0, 8 * (2 + kMaxKnots), h->stream));
     HIPCHK(h, hipMemsetAsync(T.idb, 0xff, (size_t)h->cap * 4, h->stream));
     for (int s = 0; s < nsteps; s++) {
@@ -1329,6 +1344,7 @@ struct Impl {
       const R mur = (R)((h->dt - h->dz) / (h->dt + h->dz));
       const int64_t nrow = g.periodic_z ? h->nz : h->nz + 1;
       const unsigned nbg = (unsigned)cdiv(nrow * g.plane, 256);
+      const unsigned nbs = (unsigned)cdiv(g.rows * g.plane, 256);
       const unsigned nbp = (unsigned)cdiv(g.plane, 256);
       FiltK fk = filt(h);
       const int fnbz = (int)cdiv(h->nz + 1, kF2Z), fnbx = (int)cdiv(h->nx, kF2X);
@@ -1370,6 +1386,28 @@ struct Impl {
           if (s + 1 >= L.step_first && s + 1 <= L.step_last)
             k_loss_ez_adj<R><<<(unsigned)cdiv(nbox, 256), 256, 0, h->stream>>>(
                 g, T.LE[2], L.i0, L.i1, L.j0, L.j1, lsc);
+          // transpose of the window shift that ended step s: lambda moves back
+          // by the shift, through the current-adjoint arrays (free here: the
+          // step's Yee transpose rewrites them) and one batched copy
+          if (const int sh = h->adj_shift[(size_t)s]) {
+            ShiftAdj<R> S6;
+            for (int c = 0; c < 3; c++) {
+              S6.src[c] = T.LE[c];
+              S6.src[3 + c] = T.LB[c];
+              S6.dst[c] = T.LJf[c];
+              S6.dst[3 + c] = T.LJ[c];
+            }
+            k_shift_adj<R><<<dim3(nbs, 6), 256, 0, h->stream>>>(g, S6, sh);
+            CopyBatch cb;
+            for (int c = 0; c < 3; c++) {
+              cb.src[c] = T.LJf[c];
+              cb.dst[c] = T.LE[c];
+              cb.src[3 + c] = T.LJ[c];
+              cb.dst[3 + c] = T.LB[c];
+            }
+            for (int c = 0; c < 6; c++) cb.words[c] = gb / 4;
+            k_copy_batch<<<dim3(256, 6), 256, 0, h->stream>>>(cb);
+          }
           Y.h = (R)(0.5 * h->dt);
           k_adj_yee_b<R><<<nbg, 256, 0, h->stream>>>(g, Y);
           if (!g.periodic_z) k_adj_mur_pre<R><<<nbp, 256, 0, h->stream>>>(g, Y, mur, T.mur);
@@ -1382,10 +1420,12 @@ struct Impl {
               <<<dim3((unsigned)(fnbz * fnbx), 3), 256, flds, h->stream>>>(g, fk, fio, fnbz, fnbx);
           // particles of step s
           uint8_t* b = T.sg + (int64_t)(s - s0) * T.sgb;
-          const int64_t save_step = h->step;
+          const int64_t save_step = h->step, save_wc = h->window_cells;
           h->step = s;
+          h->window_cells = h->adj_wc[(size_t)s];
           StepK<R> P = step_consts(h, true);
           h->step = save_step;
+          h->window_cells = save_wc;
           Fields<R> F;
           for (int c = 0; c < 6; c++) F.F[c] = (R*)(b + off_f(h, c));
           TapeParticles<R> TP;

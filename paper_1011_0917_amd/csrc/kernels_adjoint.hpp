@@ -692,6 +692,35 @@ __global__ __launch_bounds__(256) void k_filter_grid_r3(Geo g, FiltK fk, Grid3R<
 }
 
 // --------------------------------------------------------------------------
+// Transpose of the window shift.  The shift by n sets, on a component's
+// domain rows i, F'(i) = F(i + n) (zero where i + n leaves storage) and
+// leaves zeros elsewhere; the rows outside the domain hold no state.  So
+// lambda(j) = lambda'(j - n) on domain rows j whose source row j - n is a
+// domain row, else zero.  blockIdx.y: Ex Ey Ez Bx By Bz (Ez, Bx, By on the
+// half rows).
+// --------------------------------------------------------------------------
+template <typename R>
+struct ShiftAdj {
+  const R* src[6];
+  R* dst[6];
+};
+
+template <typename R>
+__global__ __launch_bounds__(256) void k_shift_adj(Geo g, ShiftAdj<R> S, int n) {
+  const int c = blockIdx.y;
+  const int half = c == 2 || c == 3 || c == 4;
+  const int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (v >= g.rows * g.plane) return;
+  const int row = (int)(v / g.plane);
+  const int64_t q = v - (int64_t)row * g.plane;
+  const int j = row - kGuard, i = j - n;
+  R val = (R)0;
+  if (in_domain(g, half, j) && in_domain(g, half, i))
+    val = S.src[c][(int64_t)(i + kGuard) * g.plane + q];
+  S.dst[c][v] = val;
+}
+
+// --------------------------------------------------------------------------
 // Several device copies in one launch (the per-step tape): copy blockIdx.y
 // moves words[y] 32-bit words; 16-byte chunks where both ends are 16-byte
 // aligned, then the remaining words.

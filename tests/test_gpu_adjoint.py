@@ -258,3 +258,49 @@ def test_staged_reverse_step_fp32(P):
     (L1, g1), (L2, g2), _ = _both_paths(P, WORKLOADS["adjoint_2d_small"], "fp32")
     assert L1 == L2
     assert np.abs(g2 - g1).max() <= 1e-4 * np.abs(g1).max()
+
+
+def _window_setup(P, precision):
+    W = small("adjoint_2d_tiny", window="group")
+    cfg, init, nst = resolve_gpu(W, precision=precision, sort_interval=0)
+    assert cfg.auto_window == 1 and cfg.beta_window > 0.0
+    dt = P.yee_dt(2, cfg.dz, cfg.dx, 1.0, cfg.cfl)
+    a = adjoint_setup(W, cfg.dz, P.beta, dt, cfg.beta_window)
+    return W, cfg, init, nst, a
+
+
+def test_adjoint_with_moving_window_matches_differences(P):
+    """The window at the boosted group velocity shifts 7 times over the 40
+    taped steps; the reverse sweep applies each shift's transpose.  FP64
+    adjoint against central differences of the FP64 forward (h = 1e-6,
+    tolerance 1e-4 as for the kinked losses above), and the GPU's taped loss
+    against the oracle's loss of the same windowed run."""
+    print("case adjoint with moving window", flush=True)
+    W, cfg, init, nst, a = _window_setup(P, "fp64")
+    sim = P.Simulation(cfg, capacity=init["capacity"])
+    sim.init_boosted_plasma(init["gamma_b"], knots_z=a["knots_z"], knots_n=a["knots_n"],
+                            laser=init["laser"])
+    sim.pic_step(nst)
+    moved = sim.diagnostics()["window_cells"]
+    sim.close()
+    assert moved >= 5, moved
+    L, da0, dn = gpu_run(P, cfg, init, nst, a, init["laser"].a0, a["knots_n"], grad=True)
+    a0, kn = init["laser"].a0, np.array(a["knots_n"])
+    Lo = oracle_loss(W, a0, kn, a)
+    assert abs(L - Lo) <= 1e-8 * abs(Lo), (L, Lo)
+    fd = fd_gpu(P, cfg, init, nst, a, [-1] + list(range(len(dn))))
+    print("window cells", moved, "adjoint", da0, list(dn), "differences", fd, flush=True)
+    compare(as_dict(da0, dn), fd, 1e-4)
+
+
+def test_adjoint_with_moving_window_independent_of_checkpoint_interval(P):
+    """Deterministic mode: restoring a checkpoint restores the window, so the
+    loss is bitwise the same for every interval and the gradients agree."""
+    print("case adjoint with moving window, checkpoint interval", flush=True)
+    W, cfg, init, nst, a = _window_setup(P, "fp64")
+    cfg.deterministic = 1
+    r1 = gpu_run(P, cfg, init, nst, a, init["laser"].a0, a["knots_n"], grad=True, interval=10)
+    r2 = gpu_run(P, cfg, init, nst, a, init["laser"].a0, a["knots_n"], grad=True, interval=7)
+    assert r2[0] == r1[0]
+    assert abs(r2[1] - r1[1]) <= 1e-10 * abs(r1[1])
+    assert np.allclose(r2[2], r1[2], rtol=1e-10, atol=1e-10 * np.abs(r1[2]).max())

@@ -65,11 +65,13 @@ WORKLOADS["adjoint_2d"] = dict(
                collimated=1))
 
 
-def adjoint_setup(W, dz, beta, dt):
+def adjoint_setup(W, dz, beta, dt, beta_window=0.0):
     """Density knots (lab z, values), loss window and Ez box of an adjoint run.
 
     The knots cover the lab length of every lattice column the run holds
-    (the box at t' = 0 plus the columns injected over the run).  The box spans
+    (the box at t' = 0 plus the columns injected over the run, as the plasma
+    drifts in and, with a moving window at beta_window, as the window
+    advances).  The box spans
     rows [i_L - 2.5 L', i_L - L'] behind the pulse centre i_L (L' the boosted
     envelope length in cells), |j - nx/2| <= 4: within the 500 steps of the
     adjoint configuration the wake forms just behind the pulse (an FP64 run
@@ -78,7 +80,7 @@ def adjoint_setup(W, dz, beta, dt):
     as long as a small box) is 9 rows centred on i_L."""
     import numpy as np
     g = W["gamma_b"]
-    sb = beta(g) * dt / dz
+    sb = (beta(g) + abs(beta_window)) * dt / dz
     cols = W["nz"] + W["steps"] * sb + 8
     nk = W.get("nknots", 4)
     kz = list(np.linspace(-2.0 * g * dz, g * dz * cols, nk))
