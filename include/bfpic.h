@@ -144,6 +144,7 @@ typedef struct bfpic_loss {
   int32_t step_first, step_last;
   int32_t i0, i1, j0, j1;
   double witness_weight;
+  int32_t k0, k1;  /* 3D: y nodes of the box; 2D: both 0 */
 } bfpic_loss;
 
 typedef struct bfpic_sizes {
@@ -455,7 +456,7 @@ int bfpic_kernel_timing(bfpic_ctx* h, int32_t enable);
 int bfpic_kernel_time(bfpic_ctx* h, int32_t cls, double* total_ms, int64_t* launches);
 
 /* ---------------------------------------------------------------------------
- * Adjoint (2D).  The paper prints no adjoint; these calls give the exact
+ * Adjoint (2D and 3D).  The paper prints no adjoint; these calls give the exact
  * discrete gradient of a field loss (bfpic_loss) through the step above with
  * respect to the laser amplitude a0 and the lab density profile (the knot
  * values of init_boosted_plasma, or n_uniform), the two inputs that set a
@@ -465,7 +466,8 @@ int bfpic_kernel_time(bfpic_ctx* h, int32_t cls, double* total_ms, int64_t* laun
  * segment of `interval` steps from its checkpoint.  Bound witness electrons
  * are carried: their states are taped, and with a witness term in the loss
  * their vector-Jacobian product (gather, push, move) is run backwards too,
- * its gathered-field part added to the field adjoint.  With auto_window the
+ * its gathered-field part added to the field adjoint (2D; in 3D a witness
+ * term in the loss is ERR_UNSUPPORTED).  With auto_window the
  * taped run shifts the window as pic_step does (the loss reads each step's
  * shifted state) and the reverse sweep applies the shift's transpose;
  * particles are not re-sorted during a taped run.

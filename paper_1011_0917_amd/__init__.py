@@ -74,7 +74,7 @@ class Diag(C.Structure):
 class Loss(C.Structure):
     _fields_ = [("step_first", C.c_int32), ("step_last", C.c_int32), ("i0", C.c_int32),
                 ("i1", C.c_int32), ("j0", C.c_int32), ("j1", C.c_int32),
-                ("witness_weight", C.c_double)]
+                ("witness_weight", C.c_double), ("k0", C.c_int32), ("k1", C.c_int32)]
 
 
 class AxisMeta(C.Structure):
@@ -426,15 +426,16 @@ class Simulation:
                      witness_weight=0.0) -> float:
         """Taped run of `nsteps` steps from the state right after init, with a
         checkpoint every `interval` steps; returns the loss: the mean of Ez over
-        the node box (i0, i1, j0, j1) averaged over steps step_first..step_last,
+        the node box (i0, i1, j0, j1), in 3D (i0, i1, j0, j1, k0, k1), averaged
+        over steps step_first..step_last,
         plus witness_weight times the mean lab energy of the bound witnesses
         after the last step."""
         import torch
         nb = C.c_int64()
         _check(lib().bfpic_adjoint_tape_bytes(self.h, nsteps, interval, C.byref(nb)), self.h)
         self.tape = torch.empty(nb.value, dtype=torch.uint8, device=self.device)
-        i0, i1, j0, j1 = box
-        loss = Loss(step_first, step_last, i0, i1, j0, j1, float(witness_weight))
+        i0, i1, j0, j1, k0, k1 = tuple(box) + (0, 0) if len(box) == 4 else tuple(box)
+        loss = Loss(step_first, step_last, i0, i1, j0, j1, float(witness_weight), k0, k1)
         out = C.c_double()
         _check(lib().bfpic_forward_loss(self.h, nsteps, interval, C.byref(loss),
                                         C.c_void_p(self.tape.data_ptr()), nb.value,

@@ -1084,7 +1084,7 @@ struct Impl {
     R* LJf[3] = {};  // adjoint of the filtered current
     R* LJ[3] = {};   // adjoint of the deposited (unfiltered) current
     R* mur = nullptr;
-    R* lxi[2] = {};
+    R* lxi[3] = {};
     R* ldu[3] = {};
     double* lw = nullptr;
     double* wl = nullptr;    // witness adjoints (n x 6)
@@ -1099,8 +1099,9 @@ struct Impl {
     const int64_t fb = align256(gbytes(h)), ib = align256(h->cap * 4),
                   rb = align256(h->cap * (int64_t)sizeof(R));
     const int64_t wb = align256(h->nwit * 48);
-    T.ckb = 6 * fb + ib + 6 * rb + 256 + wb;
-    T.sgb = 6 * fb + ib + 5 * rb + 256 + wb;
+    // per slot: id, xi (DIM), du (3) and, in a checkpoint, w
+    T.ckb = 6 * fb + ib + (DIM + 4) * rb + 256 + wb;
+    T.sgb = 6 * fb + ib + (DIM + 3) * rb + 256 + wb;
     const int64_t ncp = cdiv(nsteps, interval);
     int64_t o = 0;
     auto take = [&](int64_t bytes) {
@@ -1115,7 +1116,7 @@ struct Impl {
     for (int c = 0; c < 3; c++) T.LJf[c] = (R*)take(fb);
     for (int c = 0; c < 3; c++) T.LJ[c] = (R*)take(fb);
     T.mur = (R*)take(4 * h->g.plane * (int64_t)sizeof(R));
-    for (int a = 0; a < 2; a++) T.lxi[a] = (R*)take(rb);
+    for (int a = 0; a < DIM; a++) T.lxi[a] = (R*)take(rb);
     for (int a = 0; a < 3; a++) T.ldu[a] = (R*)take(rb);
     T.lw = (double*)take(h->cap * 8);
     T.wl = (double*)take(h->nwit * 48);
@@ -1128,10 +1129,10 @@ struct Impl {
   // byte offsets inside a checkpoint (ck = true) or a taped step
   static int64_t off_f(bfpic_ctx* h, int c) { return c * align256(gbytes(h)); }
   static int64_t off_id(bfpic_ctx* h) { return 6 * align256(gbytes(h)); }
-  static int64_t off_r(bfpic_ctx* h, int k) {  // k: xi0 xi1 du0 du1 du2 w
+  static int64_t off_r(bfpic_ctx* h, int k) {  // k: xi (DIM), du0 du1 du2, w
     return off_id(h) + align256(h->cap * 4) + k * align256(h->cap * (int64_t)sizeof(R));
   }
-  static int64_t off_tail(bfpic_ctx* h, bool ck) { return off_r(h, ck ? 6 : 5); }
+  static int64_t off_tail(bfpic_ctx* h, bool ck) { return off_r(h, ck ? DIM + 4 : DIM + 3); }
   static int64_t off_wit(bfpic_ctx* h, bool ck) { return off_tail(h, ck) + 256; }
 
   static int copy(bfpic_ctx* h, void* dst, const void* src, int64_t bytes) {
@@ -1153,12 +1154,17 @@ struct Impl {
       h->cur = c.cur;
     }
     const int64_t n = h->slots_bound, gb = gbytes(h);
-    void* parts[7] = {h->pid[h->cur], h->pxi[h->cur][0], h->pxi[h->cur][1], h->pdu[h->cur][0],
-                      h->pdu[h->cur][1], h->pdu[h->cur][2], h->pw[h->cur]};
+    // id, xi (DIM), du (3), w
+    void* parts[8];
+    int np = 0;
+    parts[np++] = h->pid[h->cur];
+    for (int a = 0; a < DIM; a++) parts[np++] = h->pxi[h->cur][a];
+    for (int a = 0; a < 3; a++) parts[np++] = h->pdu[h->cur][a];
+    parts[np++] = h->pw[h->cur];
     int rc = 0;
     for (int c = 0; c < 6 && !rc; c++)
       rc = save ? copy(h, b + off_f(h, c), h->F[c], gb) : copy(h, h->F[c], b + off_f(h, c), gb);
-    for (int q = 0; q < 7 && !rc; q++) {
+    for (int q = 0; q < np && !rc; q++) {
       uint8_t* t = b + (q == 0 ? off_id(h) : off_r(h, q - 1));
       const int64_t bytes = n * (q == 0 ? 4 : (int64_t)sizeof(R));
       rc = save ? copy(h, t, parts[q], bytes) : copy(h, parts[q], t, bytes);
@@ -1201,9 +1207,12 @@ struct Impl {
         nc++;
       };
       for (int c = 0; c < 6; c++) add(b + off_f(h, c), h->F[c], gb);
-      void* parts[6] = {h->pid[h->cur], h->pxi[h->cur][0], h->pxi[h->cur][1], h->pdu[h->cur][0],
-                        h->pdu[h->cur][1], h->pdu[h->cur][2]};
-      for (int q = 0; q < 6; q++)
+      void* parts[7];
+      int np = 0;
+      parts[np++] = h->pid[h->cur];
+      for (int a = 0; a < DIM; a++) parts[np++] = h->pxi[h->cur][a];
+      for (int a = 0; a < 3; a++) parts[np++] = h->pdu[h->cur][a];
+      for (int q = 0; q < np; q++)
         add(b + (q == 0 ? off_id(h) : off_r(h, q - 1)), parts[q],
             n * (q == 0 ? 4 : (int64_t)sizeof(R)));
       add(b + off_tail(h, false), h->counts, 4);
@@ -1234,23 +1243,19 @@ struct Impl {
     h->adj_shift[(size_t)s] = due;
     const bfpic_loss& L = h->adj_loss;
     if (!h->adj_recompute && h->step >= L.step_first && h->step <= L.step_last) {
-      const int nb = (L.i1 - L.i0 + 1) * (L.j1 - L.j0 + 1);
+      const int nb = (L.i1 - L.i0 + 1) * (L.j1 - L.j0 + 1) * (L.k1 - L.k0 + 1);
       const double sc = 1.0 / ((double)(L.step_last - L.step_first + 1) * nb);
       k_loss_ez<R><<<(unsigned)std::min<int64_t>(cdiv(nb, 256), 256), 256, 0, h->stream>>>(
-          h->g, (const R*)h->F[2], L.i0, L.i1, L.j0, L.j1, sc, T.acc);
+          h->g, (const R*)h->F[2], L.i0, L.i1, L.j0, L.j1, L.k0, L.k1, sc, T.acc);
       HIPCHK(h, hipGetLastError());
     }
     return BFPIC_OK;
   }
 
   static int adjoint_check(bfpic_ctx* h, int nsteps, int interval) {
-    if constexpr (DIM != 2) {
-      return fail(h, BFPIC_ERR_UNSUPPORTED, "the adjoint is built for 2D runs");
-    } else {
-      if (!h->inited) return fail(h, BFPIC_ERR_STATE, "init_boosted_plasma first");
-      if (nsteps < 1 || interval < 1) return fail(h, BFPIC_ERR_ARG, "nsteps, interval >= 1");
-      return BFPIC_OK;
-    }
+    if (!h->inited) return fail(h, BFPIC_ERR_STATE, "init_boosted_plasma first");
+    if (nsteps < 1 || interval < 1) return fail(h, BFPIC_ERR_ARG, "nsteps, interval >= 1");
+    return BFPIC_OK;
   }
 
   static int forward_loss(bfpic_ctx* h, int nsteps, int interval, const bfpic_loss* L,
@@ -1262,6 +1267,10 @@ struct Impl {
     if (L->step_first < 1 || L->step_last > nsteps || L->step_first > L->step_last ||
         L->i0 < 0 || L->i1 > rz || L->i0 > L->i1 || L->j0 < 0 || L->j1 >= h->nx || L->j0 > L->j1)
       return fail(h, BFPIC_ERR_ARG, "loss window or box out of range");
+    if (DIM == 3 ? (L->k0 < 0 || L->k1 >= h->ny || L->k0 > L->k1) : (L->k0 != 0 || L->k1 != 0))
+      return fail(h, BFPIC_ERR_ARG, "loss box y range out of range (2D: k0 = k1 = 0)");
+    if (DIM == 3 && L->witness_weight != 0.0)
+      return fail(h, BFPIC_ERR_UNSUPPORTED, "the witness term of the loss is built for 2D runs");
     if (!std::isfinite(L->witness_weight) || (L->witness_weight != 0.0 && h->nwit == 0))
       return fail(h, BFPIC_ERR_ARG, "witness weight needs bound witnesses");
     Tape T = tape_map(h, (uint8_t*)tape, nsteps, interval);
@@ -1308,10 +1317,10 @@ struct Impl {
   }
 
   static int adjoint(bfpic_ctx* h, double* da0, double* dn, int nn) {
-    if constexpr (DIM != 2) {
-      return fail(h, BFPIC_ERR_UNSUPPORTED, "the adjoint is built for 2D runs");
-    } else {
+    {
       if (!h->adj_ready) return fail(h, BFPIC_ERR_STATE, "no taped forward run");
+      if (DIM == 3 && h->adj_per_direction)
+        return fail(h, BFPIC_ERR_UNSUPPORTED, "the per-direction reference is built for 2D runs");
       if (h->nwit != h->adj_nwit)
         return fail(h, BFPIC_ERR_STATE, "witnesses rebound since the taped run");
       const int nk = h->dens.nknots >= 2 ? h->dens.nknots : 1;
@@ -1327,11 +1336,11 @@ struct Impl {
         HIPCHK(h, hipMemsetAsync(T.LJ[c], 0, gb, h->stream));
       }
       const int64_t rb = h->cap * (int64_t)sizeof(R);
-      for (int a = 0; a < 2; a++) HIPCHK(h, hipMemsetAsync(T.lxi[a], 0, rb, h->stream));
+      for (int a = 0; a < DIM; a++) HIPCHK(h, hipMemsetAsync(T.lxi[a], 0, rb, h->stream));
       for (int a = 0; a < 3; a++) HIPCHK(h, hipMemsetAsync(T.ldu[a], 0, rb, h->stream));
       HIPCHK(h, hipMemsetAsync(T.lw, 0, h->cap * 8, h->stream));
       const bfpic_loss& L = h->adj_loss;
-      const int nbox = (L.i1 - L.i0 + 1) * (L.j1 - L.j0 + 1);
+      const int nbox = (L.i1 - L.i0 + 1) * (L.j1 - L.j0 + 1) * (L.k1 - L.k0 + 1);
       const R lsc = (R)(1.0 / ((double)(L.step_last - L.step_first + 1) * nbox));
       AdjYeeK<R> Y;
       for (int c = 0; c < 3; c++) {
@@ -1341,14 +1350,20 @@ struct Impl {
       }
       Y.idz = (R)(1.0 / h->dz);
       Y.idx = (R)(1.0 / h->dx);
+      Y.idy = (R)(DIM == 3 ? 1.0 / h->dy : 0.0);
       const R mur = (R)((h->dt - h->dz) / (h->dt + h->dz));
       const int64_t nrow = g.periodic_z ? h->nz : h->nz + 1;
       const unsigned nbg = (unsigned)cdiv(nrow * g.plane, 256);
       const unsigned nbs = (unsigned)cdiv(g.rows * g.plane, 256);
       const unsigned nbp = (unsigned)cdiv(g.plane, 256);
       FiltK fk = filt(h);
-      const int fnbz = (int)cdiv(h->nz + 1, kF2Z), fnbx = (int)cdiv(h->nx, kF2X);
-      const size_t flds = 2 * sizeof(R) * (kF2Z + 2 * fk.H) * (kF2X + 2 * fk.H);
+      // filter transpose tiles: 2D kF2Z x kF2X, 3D kF3 cubes
+      const int fnbz = (int)cdiv(h->nz + 1, DIM == 2 ? kF2Z : kF3);
+      const int fnbx = (int)cdiv(h->nx, DIM == 2 ? kF2X : kF3);
+      const int fnby = DIM == 2 ? 1 : (int)cdiv(h->ny, kF3);
+      const size_t flds = DIM == 2 ? 2 * sizeof(R) * (kF2Z + 2 * fk.H) * (kF2X + 2 * fk.H)
+                                   : 2 * sizeof(R) * (size_t)(kF3 + 2 * fk.H) *
+                                         (kF3 + 2 * fk.H) * (kF3 + 2 * fk.H);
       Fields<R> LJ, LF;
       for (int c = 0; c < 3; c++) {
         LJ.F[c] = T.LJ[c];
@@ -1362,7 +1377,7 @@ struct Impl {
         fio.out[c] = T.LJ[c];
       }
       AdjSlots<R> A;
-      for (int a = 0; a < 2; a++) A.lxi[a] = T.lxi[a];
+      for (int a = 0; a < 3; a++) A.lxi[a] = a < DIM ? T.lxi[a] : nullptr;
       for (int a = 0; a < 3; a++) A.ldu[a] = T.ldu[a];
       A.lw = T.lw;
       const bool wit_adj = h->nwit > 0 && L.witness_weight != 0.0;
@@ -1385,7 +1400,7 @@ struct Impl {
         for (int s = s1 - 1; s >= s0; s--) {
           if (s + 1 >= L.step_first && s + 1 <= L.step_last)
             k_loss_ez_adj<R><<<(unsigned)cdiv(nbox, 256), 256, 0, h->stream>>>(
-                g, T.LE[2], L.i0, L.i1, L.j0, L.j1, lsc);
+                g, T.LE[2], L.i0, L.i1, L.j0, L.j1, L.k0, L.k1, lsc);
           // transpose of the window shift that ended step s: lambda moves back
           // by the shift, through the current-adjoint arrays (free here: the
           // step's Yee transpose rewrites them) and one batched copy
@@ -1409,15 +1424,20 @@ struct Impl {
             k_copy_batch<<<dim3(256, 6), 256, 0, h->stream>>>(cb);
           }
           Y.h = (R)(0.5 * h->dt);
-          k_adj_yee_b<R><<<nbg, 256, 0, h->stream>>>(g, Y);
+          k_adj_yee_b<R, DIM><<<nbg, 256, 0, h->stream>>>(g, Y);
           if (!g.periodic_z) k_adj_mur_pre<R><<<nbp, 256, 0, h->stream>>>(g, Y, mur, T.mur);
           Y.h = (R)h->dt;
-          k_adj_yee_e<R><<<nbg, 256, 0, h->stream>>>(g, Y);
+          k_adj_yee_e<R, DIM><<<nbg, 256, 0, h->stream>>>(g, Y);
           if (!g.periodic_z) k_adj_mur_post<R><<<nbp, 256, 0, h->stream>>>(g, Y, T.mur);
           Y.h = (R)(0.5 * h->dt);
-          k_adj_yee_b<R><<<nbg, 256, 0, h->stream>>>(g, Y);
-          k_filter_grid_r3<R, kF2Z, kF2X>
-              <<<dim3((unsigned)(fnbz * fnbx), 3), 256, flds, h->stream>>>(g, fk, fio, fnbz, fnbx);
+          k_adj_yee_b<R, DIM><<<nbg, 256, 0, h->stream>>>(g, Y);
+          if constexpr (DIM == 2)
+            k_filter_grid_r3<R, kF2Z, kF2X>
+                <<<dim3((unsigned)(fnbz * fnbx), 3), 256, flds, h->stream>>>(g, fk, fio, fnbz,
+                                                                             fnbx);
+          else
+            k_filter_grid_r3d<R, kF3><<<dim3((unsigned)(fnbz * fnbx * fnby), 3), 256, flds,
+                                        h->stream>>>(g, fk, fio, fnbz, fnbx, fnby);
           // particles of step s
           uint8_t* b = T.sg + (int64_t)(s - s0) * T.sgb;
           const int64_t save_step = h->step, save_wc = h->window_cells;
@@ -1430,21 +1450,26 @@ struct Impl {
           for (int c = 0; c < 6; c++) F.F[c] = (R*)(b + off_f(h, c));
           TapeParticles<R> TP;
           TP.id = (const int*)(b + off_id(h));
-          for (int a = 0; a < 2; a++) TP.xi[a] = (const R*)(b + off_r(h, a));
-          for (int a = 0; a < 3; a++) TP.du[a] = (const R*)(b + off_r(h, 2 + a));
+          for (int a = 0; a < 3; a++) TP.xi[a] = a < DIM ? (const R*)(b + off_r(h, a)) : nullptr;
+          for (int a = 0; a < 3; a++) TP.du[a] = (const R*)(b + off_r(h, DIM + a));
           TP.w = (const R*)h->pw[h->cur];
           TP.count = (const int*)(b + off_tail(h, false));
           const unsigned nbq = (unsigned)std::max<int64_t>(1, std::min<int64_t>(
                                    cdiv(std::max<int64_t>(h->slots_bound, 1), 256), 4096));
-          if (h->adj_per_direction)
-            k_adj_particles<R, ORDER><<<nbq, 256, 0, h->stream>>>(P, F, TP, LJ, LF, A);
-          else
-            k_adj_particles_staged<R, ORDER><<<nbq, 256, 0, h->stream>>>(P, F, TP, LJ, LF, A);
-          if (wit_adj) {
-            WitK W{(double*)(b + off_wit(h, false)), h->nwit,
-                   {h->dt / h->dz, h->dt / h->dx, h->dt / h->dy}, -0.5 * h->dt,
-                   h->cfg.gather_form};
-            k_adj_witness<R, ORDER><<<nbw, 256, 0, h->stream>>>(g, F, W, T.wl, LF);
+          if constexpr (DIM == 2) {
+            if (h->adj_per_direction)
+              k_adj_particles<R, ORDER><<<nbq, 256, 0, h->stream>>>(P, F, TP, LJ, LF, A);
+            else
+              k_adj_particles_staged<R, ORDER, 2><<<nbq, 256, 0, h->stream>>>(P, F, TP, LJ, LF,
+                                                                               A);
+            if (wit_adj) {
+              WitK W{(double*)(b + off_wit(h, false)), h->nwit,
+                     {h->dt / h->dz, h->dt / h->dx, h->dt / h->dy}, -0.5 * h->dt,
+                     h->cfg.gather_form};
+              k_adj_witness<R, ORDER><<<nbw, 256, 0, h->stream>>>(g, F, W, T.wl, LF);
+            }
+          } else {
+            k_adj_particles_staged<R, ORDER, 3><<<nbq, 256, 0, h->stream>>>(P, F, TP, LJ, LF, A);
           }
           HIPCHK(h, hipGetLastError());
         }
@@ -1880,6 +1905,10 @@ extern "C" int bfpic_create(const bfpic_config* cfg, int64_t cap, void* workspac
                         hipFuncAttributeMaxDynamicSharedMemorySize, lim);
     hipFuncSetAttribute((const void*)k_filter_grid<3, kF3, kF3, kF3>,
                         hipFuncAttributeMaxDynamicSharedMemorySize, lim);
+    (void)hipFuncSetAttribute((const void*)k_filter_grid_r3d<float, kF3>,
+                              hipFuncAttributeMaxDynamicSharedMemorySize, lim);
+    (void)hipFuncSetAttribute((const void*)k_filter_grid_r3d<double, kF3>,
+                              hipFuncAttributeMaxDynamicSharedMemorySize, lim);
     FiltK fk;
     fk.passes = cfg->filter_passes;
     fk.comp = cfg->filter_compensate;
@@ -2331,7 +2360,6 @@ extern "C" int bfpic_kernel_time(bfpic_ctx* h, int32_t cls, double* total_ms, in
 extern "C" int bfpic_adjoint_tape_bytes(bfpic_ctx* h, int32_t nsteps, int32_t interval,
                                         int64_t* bytes) {
   if (!h || !bytes || nsteps < 1 || interval < 1) return BFPIC_ERR_ARG;
-  if (h->dim != 2) return fail(h, BFPIC_ERR_UNSUPPORTED, "the adjoint is built for 2D runs");
   return tape_bytes_of(h, nsteps, interval, bytes);
 }
 

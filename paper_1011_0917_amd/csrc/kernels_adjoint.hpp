@@ -303,47 +303,60 @@ struct AdjJSinkN {
 // the field adjoint (same shapes and staggering as `gather`).
 // Nodes outside a component's domain rows hold constant zeros, not state:
 // they take no adjoint.
-template <typename R, int ORDER>
+template <typename R, int ORDER, int DIM = 2>
 __device__ __forceinline__ void scatter_node_weights(R* const* lf, const Geo& g, int comp, int bz,
-                                                     const R* wz, int bx, const R* wx, R gv) {
+                                                     const R* wz, int bx, const R* wx, int by,
+                                                     const R* wy, R gv) {
   if (gv == (R)0) return;
   const int hz = half_z_eb(comp);
+  constexpr int NY = DIM == 3 ? ORDER + 1 : 1;
 #pragma unroll
   for (int a = 0; a <= ORDER; a++) {
     if (!g.periodic_z && !in_domain(g, hz, bz + a)) continue;
 #pragma unroll
-    for (int b = 0; b <= ORDER; b++) {
-      const int64_t n = gidx(g, bz + a, bx + b, 0);
-      if (n >= 0) atomicAdd(&lf[comp][n], gv * wz[a] * wx[b]);
-    }
+    for (int b = 0; b <= ORDER; b++)
+#pragma unroll
+      for (int c = 0; c < NY; c++) {
+        const int64_t n = gidx(g, bz + a, bx + b, DIM == 3 ? by + c : 0);
+        const R wgt = DIM == 3 ? wz[a] * wx[b] * wy[c] : wz[a] * wx[b];
+        if (n >= 0) atomicAdd(&lf[comp][n], gv * wgt);
+      }
   }
 }
 
-template <typename R, int ORDER>
+template <typename R, int ORDER, int DIM = 2>
 __device__ __forceinline__ void gather_transpose(R* const* lf, const Geo& g, const Pos<R>& p,
                                                  const R gE[3], const R gB[3], bool gk) {
   R wz0[ORDER + 1], wz1[ORDER + 1], wx0[ORDER + 1], wx1[ORDER + 1];
+  R wy0[ORDER + 1] = {}, wy1[ORDER + 1] = {};
   const int z0 = shape<R, ORDER>(p.c[0], p.o[0], 0, wz0);
   const int z1 = shape<R, ORDER>(p.c[0], p.o[0], 1, wz1);
   const int x0 = shape<R, ORDER>(p.c[1], p.o[1], 0, wx0);
   const int x1 = shape<R, ORDER>(p.c[1], p.o[1], 1, wx1);
+  int y0 = 0, y1 = 0;
+  if constexpr (DIM == 3) {
+    y0 = shape<R, ORDER>(p.c[2], p.o[2], 0, wy0);
+    y1 = shape<R, ORDER>(p.c[2], p.o[2], 1, wy1);
+  }
   // the Galerkin form reads the half lattices with the reduced shape
   galerkin_half<R, ORDER>(gk, p.o[0], wz1);
   galerkin_half<R, ORDER>(gk, p.o[1], wx1);
-  // staggering (z, x): Ex (0,h) Ey (0,0) Ez (h,0) Bx (h,0) By (h,h) Bz (0,h)
-  scatter_node_weights<R, ORDER>(lf, g, 0, z0, wz0, x1, wx1, gE[0]);
-  scatter_node_weights<R, ORDER>(lf, g, 1, z0, wz0, x0, wx0, gE[1]);
-  scatter_node_weights<R, ORDER>(lf, g, 2, z1, wz1, x0, wx0, gE[2]);
-  scatter_node_weights<R, ORDER>(lf, g, 3, z1, wz1, x0, wx0, gB[0]);
-  scatter_node_weights<R, ORDER>(lf, g, 4, z1, wz1, x1, wx1, gB[1]);
-  scatter_node_weights<R, ORDER>(lf, g, 5, z0, wz0, x1, wx1, gB[2]);
+  if constexpr (DIM == 3) galerkin_half<R, ORDER>(gk, p.o[2], wy1);
+  // staggering (z, x, y): Ex (0,h,0) Ey (0,0,h) Ez (h,0,0) Bx (h,0,h) By (h,h,0) Bz (0,h,h);
+  // in 2D the y entries drop out
+  scatter_node_weights<R, ORDER, DIM>(lf, g, 0, z0, wz0, x1, wx1, y0, wy0, gE[0]);
+  scatter_node_weights<R, ORDER, DIM>(lf, g, 1, z0, wz0, x0, wx0, y1, wy1, gE[1]);
+  scatter_node_weights<R, ORDER, DIM>(lf, g, 2, z1, wz1, x0, wx0, y0, wy0, gE[2]);
+  scatter_node_weights<R, ORDER, DIM>(lf, g, 3, z1, wz1, x0, wx0, y1, wy1, gB[0]);
+  scatter_node_weights<R, ORDER, DIM>(lf, g, 4, z1, wz1, x1, wx1, y0, wy0, gB[1]);
+  scatter_node_weights<R, ORDER, DIM>(lf, g, 5, z0, wz0, x1, wx1, y1, wy1, gB[2]);
 }
 
 // Per-slot adjoint state: adjoints of the displacement and momentum carried
 // backwards from step to step, and the accumulated weight adjoint.
 template <typename R>
 struct AdjSlots {
-  R* lxi[2];
+  R* lxi[3];   // z, x (, y)
   R* ldu[3];
   double* lw;
 };
@@ -352,7 +365,7 @@ struct AdjSlots {
 template <typename R>
 struct TapeParticles {
   const int* id;
-  const R* xi[2];
+  const R* xi[3];     // z, x (, y)
   const R* du[3];
   const R* w;         // weights (constant per slot)
   const int* count;   // number of slots during the step
@@ -435,20 +448,23 @@ __global__ __launch_bounds__(256) void k_adj_particles(StepK<R> P, Fields<R> F,
 // with the current adjoint at once).  The chain rule then gives the same
 // vector-Jacobian product as the twelve passes of k_adj_particles, from the
 // same templated gather, push and deposit.
-template <typename R, int ORDER>
+template <typename R, int ORDER, int DIM = 2>
 __global__ __launch_bounds__(256) void k_adj_particles_staged(StepK<R> P, Fields<R> F,
                                                               TapeParticles<R> T, Fields<R> LJ,
                                                               Fields<R> LF, AdjSlots<R> A) {
-  using D2 = DualN<R, 2>;
+  // 2D: the gather on 2 tangents, the deposit on 6 (xi, xi', w, v_y: the
+  // out-of-plane current); 3D: 3 and 7 (xi, xi', w)
+  constexpr int ND = DIM == 3 ? 7 : 6;
+  using DG = DualN<R, DIM>;
   using D9 = DualN<R, 9>;
-  using D6 = DualN<R, 6>;
-  const StepK<D2> P2 = to_dual<D2>(P);
+  using DD = DualN<R, ND>;
+  const StepK<DG> PG = to_dual<DG>(P);
   const PushC<D9> push9 = to_dual<D9>(P.push);
-  const StepK<D6> P6 = to_dual<D6>(P);
+  const StepK<DD> PD = to_dual<DD>(P);
   const Geo& g = P.g;
   const int n = *T.count;
   const bool gk = P.galerkin != 0;
-  DualFetchN<R, 2> fetch{(const R* const*)F.F, g};
+  DualFetchN<R, DIM> fetch{(const R* const*)F.F, g};
   // Slots stay in creation order during a taped run (no sort): whole lattice
   // columns, the ppc slots of a cell in a row.  They are taken slot-major
   // (thread q: cell q mod m, slot q / m), so that the lanes of a wave scatter
@@ -462,55 +478,71 @@ __global__ __launch_bounds__(256) void k_adj_particles_staged(StepK<R> P, Fields
     const int p = il ? (q - qs * m) * ppc + qs : q;
     const int id = T.id[p];
     if (id < 0) continue;
-    const R xi0 = T.xi[0][p], xi1 = T.xi[1][p];
+    const R xi[3] = {T.xi[0][p], T.xi[1][p], DIM == 3 ? T.xi[2][p] : (R)0};
     const R w = T.w[p];
     const Birth b = decode_id(P.L, id);
     R r[3];
-    birth_offsets<R, 2>(P.L, id, r);
+    birth_offsets<R, DIM>(P.L, id, r);
     // gather: E, B and their derivatives along the displacement
-    D2 E2[3], B2[3];
+    DG EG[3], BG[3];
     int bc[3];
     {
-      const D2 r2[3] = {D2((double)r[0]), D2((double)r[1]), D2(0.0)};
-      const D2 x2[3] = {D2::seed(xi0, 0), D2::seed(xi1, 1), D2(0.0)};
-      const Pos<D2> e0 = add_xi<D2, 2>(ion_at<D2, 2>(b, r2, P2.D0), x2);
+      const DG rg[3] = {DG((double)r[0]), DG((double)r[1]), DG((double)r[2])};
+      DG xg[3];
+#pragma unroll
+      for (int a = 0; a < 3; a++) xg[a] = a < DIM ? DG::seed(xi[a], a) : DG(0.0);
+      const Pos<DG> e0 = add_xi<DG, DIM>(ion_at<DG, DIM>(b, rg, PG.D0), xg);
       bc[0] = e0.c[0];
       bc[1] = e0.c[1];
-      bc[2] = 0;
-      gather<D2, 2, ORDER>(fetch, bc, e0, E2, B2, gk);
+      bc[2] = DIM == 3 ? e0.c[2] : 0;
+      gather<DG, DIM, ORDER>(fetch, bc, e0, EG, BG, gk);
     }
     // push: derivatives along (E, B, du)
     D9 E9[3], B9[3], du9[3], dv9[3], gam9;
 #pragma unroll
     for (int c = 0; c < 3; c++) {
-      E9[c] = D9::seed(E2[c].v, c);
-      B9[c] = D9::seed(B2[c].v, 3 + c);
+      E9[c] = D9::seed(EG[c].v, c);
+      B9[c] = D9::seed(BG[c].v, 3 + c);
       du9[c] = D9::seed(T.du[c][p], 6 + c);
     }
     boris_split(push9, E9, B9, du9, dv9, gam9);
-    // move, as the forward step: position axes (z, x) take v_z, v_x
-    const R xn0 = xi0 + dv9[2].v * P.dtd[0];
-    const R xn1 = xi1 + dv9[0].v * P.dtd[1];
+    // move, as the forward step: position axes (z, x, y) take v_z, v_x, v_y
+    const R xnv[3] = {xi[0] + dv9[2].v * P.dtd[0], xi[1] + dv9[0].v * P.dtd[1],
+                      DIM == 3 ? xi[2] + dv9[1].v * P.dtd[2] : (R)0};
     // deposit, contracted with the current adjoint: derivatives along
-    // (xi_z, xi_x, xi'_z, xi'_x, w, v_y)
-    R s[6] = {(R)0, (R)0, (R)0, (R)0, (R)0, (R)0};
+    // (xi, xi', w[, v_y])
+    R s[ND];
+#pragma unroll
+    for (int k = 0; k < ND; k++) s[k] = (R)0;
     {
-      const D6 r6[3] = {D6((double)r[0]), D6((double)r[1]), D6(0.0)};
-      const Pos<D6> i0 = ion_at<D6, 2>(b, r6, P6.D0);
-      const Pos<D6> i1 = ion_at<D6, 2>(b, r6, P6.D1);
-      D6 xo[3] = {D6::seed(xi0, 0), D6::seed(xi1, 1), D6(0.0)};
-      D6 xn[3] = {D6::seed(xn0, 2), D6::seed(xn1, 3), D6(0.0)};
-      const D6 w6 = D6::seed(w, 4), vy = D6::seed(dv9[1].v, 5);
-      const Pos<D6> e0 = add_xi<D6, 2>(i0, xo);
-      const Pos<D6> e1 = add_xi<D6, 2>(i1, xn);
-      AdjJSinkN<R, 6> snk{(const R* const*)LJ.F, g, s};
-      bool done = false;
-      if constexpr (ORDER == 1) done = deposit2d_pair<D6>(P6, snk, bc, e0, e1, i0, i1, xo, xn, w6, vy);
-      if (!done) deposit2d<D6, ORDER>(P6, snk, bc, e0, e1, i0, i1, w6, vy, true);
+      const DD rd[3] = {DD((double)r[0]), DD((double)r[1]), DD((double)r[2])};
+      const Pos<DD> i0 = ion_at<DD, DIM>(b, rd, PD.D0);
+      const Pos<DD> i1 = ion_at<DD, DIM>(b, rd, PD.D1);
+      DD xo[3], xn[3];
+#pragma unroll
+      for (int a = 0; a < 3; a++) {
+        xo[a] = a < DIM ? DD::seed(xi[a], a) : DD(0.0);
+        xn[a] = a < DIM ? DD::seed(xnv[a], DIM + a) : DD(0.0);
+      }
+      const DD wd = DD::seed(w, 2 * DIM);
+      const Pos<DD> e0 = add_xi<DD, DIM>(i0, xo);
+      const Pos<DD> e1 = add_xi<DD, DIM>(i1, xn);
+      AdjJSinkN<R, ND> snk{(const R* const*)LJ.F, g, s};
+      if constexpr (DIM == 2) {
+        const DD vy = DD::seed(dv9[1].v, 5);
+        bool done = false;
+        if constexpr (ORDER == 1) done = deposit2d_pair<DD>(PD, snk, bc, e0, e1, i0, i1, xo, xn, wd, vy);
+        if (!done) deposit2d<DD, ORDER>(PD, snk, bc, e0, e1, i0, i1, wd, vy, true);
+      } else {
+        deposit3d<DD, ORDER>(PD, snk, bc, e0, e1, i0, i1, wd, true);
+      }
     }
     // chain rule, outputs to inputs
-    const R axn0 = A.lxi[0][p] + s[2], axn1 = A.lxi[1][p] + s[3];
-    const R adv[3] = {axn1 * P.dtd[1], s[5], axn0 * P.dtd[0]};
+    R axn[3] = {(R)0, (R)0, (R)0};
+#pragma unroll
+    for (int a = 0; a < DIM; a++) axn[a] = A.lxi[a][p] + s[DIM + a];
+    const R adv[3] = {axn[1] * P.dtd[1], DIM == 3 ? axn[2] * P.dtd[2] : s[ND - 1],
+                      axn[0] * P.dtd[0]};
     const R adu[3] = {A.ldu[0][p], A.ldu[1][p], A.ldu[2][p]};
     R ain[9];
 #pragma unroll
@@ -520,110 +552,122 @@ __global__ __launch_bounds__(256) void k_adj_particles_staged(StepK<R> P, Fields
       for (int c = 0; c < 3; c++) a += adu[c] * du9[c].d[k] + adv[c] * dv9[c].d[k];
       ain[k] = a;
     }
-    R axo[2] = {s[0] + axn0, s[1] + axn1};
 #pragma unroll
-    for (int m = 0; m < 2; m++)
+    for (int a = 0; a < DIM; a++) {
+      R axo = s[a] + axn[a];
 #pragma unroll
-      for (int c = 0; c < 3; c++) axo[m] += ain[c] * E2[c].d[m] + ain[3 + c] * B2[c].d[m];
-    A.lxi[0][p] = axo[0];
-    A.lxi[1][p] = axo[1];
+      for (int c = 0; c < 3; c++) axo += ain[c] * EG[c].d[a] + ain[3 + c] * BG[c].d[a];
+      A.lxi[a][p] = axo;
+    }
     A.ldu[0][p] = ain[6];
     A.ldu[1][p] = ain[7];
     A.ldu[2][p] = ain[8];
-    A.lw[p] += (double)s[4];
+    A.lw[p] += (double)s[2 * DIM];
     // gather transpose at the primal position
-    R xr[3] = {xi0, xi1, (R)0};
-    const Pos<R> e0p = add_xi<R, 2>(ion_at<R, 2>(b, r, P.D0), xr);
-    gather_transpose<R, ORDER>(LF.F, g, e0p, ain, ain + 3, gk);
+    const R xr[3] = {xi[0], xi[1], xi[2]};
+    const Pos<R> e0p = add_xi<R, DIM>(ion_at<R, DIM>(b, r, P.D0), xr);
+    gather_transpose<R, ORDER, DIM>(LF.F, g, e0p, ain, ain + 3, gk);
   }
 }
 
 // --------------------------------------------------------------------------
-// Transposes of the 2D Yee updates.  The forward updates are
+// Transposes of the Yee updates.  The forward updates are
 //   B half step (h = dt/2), rows [0, nrow):
-//     Bx(i)   += h (Ey(i+1) - Ey(i)) / dz                      [half-z rows]
-//     By(i,j) += h ((Ez(i,j+1) - Ez(i,j)) / dx - (Ex(i+1) - Ex(i)) / dz)  [half-z rows]
-//     Bz(i,j) -= h (Ey(i,j+1) - Ey(i,j)) / dx
+//     Bx += h ((Ey(i+1) - Ey(i)) / dz - (Ez(k+1) - Ez(k)) / dy)   [half-z rows]
+//     By += h ((Ez(j+1) - Ez(j)) / dx - (Ex(i+1) - Ex(i)) / dz)   [half-z rows]
+//     Bz += h ((Ex(k+1) - Ex(k)) / dy - (Ey(j+1) - Ey(j)) / dx)
 //   E step (h = dt), Ex, Ey on rows R (open z: 1..nz-1, the ends are Mur's):
-//     Ez(i,j) += h ((By(i,j) - By(i,j-1)) / dx - Jz)          [half-z rows]
-//     Ex(i)   += h (-(By(i) - By(i-1)) / dz - Jx)
-//     Ey(i,j) += h ((Bx(i) - Bx(i-1)) / dz - (Bz(i,j) - Bz(i,j-1)) / dx - Jy)
-// Adjoint arrays are zero outside each component's domain rows, so the
-// neighbour reads below need no row tests beyond R.
+//     Ez += h ((By(j) - By(j-1)) / dx - (Bx(k) - Bx(k-1)) / dy - Jz)   [half-z rows]
+//     Ex += h ((Bz(k) - Bz(k-1)) / dy - (By(i) - By(i-1)) / dz - Jx)
+//     Ey += h ((Bx(i) - Bx(i-1)) / dz - (Bz(j) - Bz(j-1)) / dx - Jy)
+// (the y differences only in 3D).  Adjoint arrays are zero outside each
+// component's domain rows, so the neighbour reads below need no row tests
+// beyond R.
 // --------------------------------------------------------------------------
 template <typename R>
 struct AdjYeeK {
   R* LE[3];
   R* LB[3];
   R* LJ[3];  // adjoint of the filtered current (written by the E transpose)
-  R idz, idx;
+  R idz, idx, idy;
   R h;
 };
 
 // lambda_E += h K_E^T lambda_B (the B half step's transpose; lambda_B unchanged)
-template <typename R>
+template <typename R, int DIM = 2>
 __global__ __launch_bounds__(256) void k_adj_yee_b(Geo g, AdjYeeK<R> Y) {
   const int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   const int nrow = g.periodic_z ? g.nz : g.nz + 1;
   if (v >= (int64_t)nrow * g.plane) return;
   const int i = (int)(v / g.plane);
-  const int j = (int)(v - (int64_t)i * g.plane);
-  const int64_t n = gidx(g, i, j, 0);
+  const int rem = (int)(v - (int64_t)i * g.plane);
+  const int j = rem / g.ny, k = rem - j * g.ny;
+  const int64_t n = gidx(g, i, j, k);
   const R* LBx = Y.LB[0];
   const R* LBy = Y.LB[1];
   const R* LBz = Y.LB[2];
   const R h = Y.h;
-  Y.LE[0][n] += h * Y.idz * (LBy[n] - at(g, LBy, i - 1, j, 0));
-  Y.LE[1][n] += h * Y.idz * (at(g, LBx, i - 1, j, 0) - LBx[n]) +
-                h * Y.idx * (LBz[n] - at(g, LBz, i, j - 1, 0));
-  if (i <= row_hi(g, 1)) Y.LE[2][n] += h * Y.idx * (at(g, LBy, i, j - 1, 0) - LBy[n]);
+  R ex = h * Y.idz * (LBy[n] - at(g, LBy, i - 1, j, k));
+  if (DIM == 3) ex += h * Y.idy * (at(g, LBz, i, j, k - 1) - LBz[n]);
+  Y.LE[0][n] += ex;
+  Y.LE[1][n] += h * Y.idz * (at(g, LBx, i - 1, j, k) - LBx[n]) +
+                h * Y.idx * (LBz[n] - at(g, LBz, i, j - 1, k));
+  if (i <= row_hi(g, 1)) {
+    R ez = h * Y.idx * (at(g, LBy, i, j - 1, k) - LBy[n]);
+    if (DIM == 3) ez += h * Y.idy * (LBx[n] - at(g, LBx, i, j, k - 1));
+    Y.LE[2][n] += ez;
+  }
 }
 
 // lambda_B += h K_B^T lambda_E|R ; lambda_J = -h lambda_E|R (lambda_E unchanged)
 template <typename R>
-__device__ __forceinline__ R lam_r(const Geo& g, const R* L, int i, int j) {
+__device__ __forceinline__ R lam_r(const Geo& g, const R* L, int i, int j, int k) {
   // lambda_E of Ex / Ey restricted to the rows the E step updates
   if (!g.periodic_z && (i <= 0 || i >= g.nz)) return (R)0;
-  return at(g, L, i, j, 0);
+  return at(g, L, i, j, k);
 }
 
-template <typename R>
+template <typename R, int DIM = 2>
 __global__ __launch_bounds__(256) void k_adj_yee_e(Geo g, AdjYeeK<R> Y) {
   const int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   const int nrow = g.periodic_z ? g.nz : g.nz + 1;
   if (v >= (int64_t)nrow * g.plane) return;
   const int i = (int)(v / g.plane);
-  const int j = (int)(v - (int64_t)i * g.plane);
-  const int64_t n = gidx(g, i, j, 0);
+  const int rem = (int)(v - (int64_t)i * g.plane);
+  const int j = rem / g.ny, k = rem - j * g.ny;
+  const int64_t n = gidx(g, i, j, k);
   const R* LEx = Y.LE[0];
   const R* LEy = Y.LE[1];
   const R* LEz = Y.LE[2];
   const R h = Y.h;
   if (i <= row_hi(g, 1)) {
-    Y.LB[1][n] += h * Y.idx * (LEz[n] - at(g, LEz, i, j + 1, 0)) +
-                  h * Y.idz * (lam_r(g, LEx, i + 1, j) - lam_r(g, LEx, i, j));
-    Y.LB[0][n] += h * Y.idz * (lam_r(g, LEy, i, j) - lam_r(g, LEy, i + 1, j));
+    Y.LB[1][n] += h * Y.idx * (LEz[n] - at(g, LEz, i, j + 1, k)) +
+                  h * Y.idz * (lam_r(g, LEx, i + 1, j, k) - lam_r(g, LEx, i, j, k));
+    R bx = h * Y.idz * (lam_r(g, LEy, i, j, k) - lam_r(g, LEy, i + 1, j, k));
+    if (DIM == 3) bx += h * Y.idy * (at(g, LEz, i, j, k + 1) - LEz[n]);
+    Y.LB[0][n] += bx;
     Y.LJ[2][n] = -h * LEz[n];
   }
-  Y.LB[2][n] += h * Y.idx * (lam_r(g, LEy, i, j + 1) - lam_r(g, LEy, i, j));
-  Y.LJ[0][n] = -h * lam_r(g, LEx, i, j);
-  Y.LJ[1][n] = -h * lam_r(g, LEy, i, j);
+  R bz = h * Y.idx * (lam_r(g, LEy, i, j + 1, k) - lam_r(g, LEy, i, j, k));
+  if (DIM == 3) bz += h * Y.idy * (lam_r(g, LEx, i, j, k) - lam_r(g, LEx, i, j, k + 1));
+  Y.LB[2][n] += bz;
+  Y.LJ[0][n] = -h * lam_r(g, LEx, i, j, k);
+  Y.LJ[1][n] = -h * lam_r(g, LEy, i, j, k);
 }
 
 // Mur at both z ends, forward: E(0) <- E_old(1) + m (E_new(1) - E_old(0)), the
 // same at nz from nz-1.  Transpose in two parts around the E transpose: first
 // the adjoint of E_new(1) takes m lambda(0) and lambda(0) becomes -m lambda(0)
 // (the adjoint of E_old(0)); after the E transpose the adjoint of E_old(1)
-// takes the saved lambda(0).
+// takes the saved lambda(0).  One thread per node q of a z plane.
 template <typename R>
 __global__ __launch_bounds__(256) void k_adj_mur_pre(Geo g, AdjYeeK<R> Y, R mur, R* save) {
   const int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (q >= g.plane) return;
-  const int j = (int)q;
+  const int64_t n0 = (int64_t)kGuard * g.plane + q, n1 = n0 + g.plane;
+  const int64_t m0 = (int64_t)(g.nz + kGuard) * g.plane + q, m1 = m0 - g.plane;
   for (int c = 0; c < 2; c++) {
     R* L = Y.LE[c];
-    const int64_t n0 = gidx(g, 0, j, 0), n1 = gidx(g, 1, j, 0);
-    const int64_t m0 = gidx(g, g.nz, j, 0), m1 = gidx(g, g.nz - 1, j, 0);
     const R t0 = L[n0], tm = L[m0];
     save[(0 * 2 + c) * g.plane + q] = t0;
     save[(1 * 2 + c) * g.plane + q] = tm;
@@ -638,11 +682,12 @@ template <typename R>
 __global__ __launch_bounds__(256) void k_adj_mur_post(Geo g, AdjYeeK<R> Y, const R* save) {
   const int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (q >= g.plane) return;
-  const int j = (int)q;
+  const int64_t n1 = (int64_t)(1 + kGuard) * g.plane + q;
+  const int64_t m1 = (int64_t)(g.nz - 1 + kGuard) * g.plane + q;
   for (int c = 0; c < 2; c++) {
     R* L = Y.LE[c];
-    L[gidx(g, 1, j, 0)] += save[(0 * 2 + c) * g.plane + q];
-    L[gidx(g, g.nz - 1, j, 0)] += save[(1 * 2 + c) * g.plane + q];
+    L[n1] += save[(0 * 2 + c) * g.plane + q];
+    L[m1] += save[(1 * 2 + c) * g.plane + q];
   }
 }
 
@@ -689,6 +734,19 @@ __global__ __launch_bounds__(256) void k_filter_grid_r3(Geo g, FiltK fk, Grid3R<
   const int bx = b % nbx, bz = b / nbx;
   GridSrcR<R> src{io.in[c], g};
   filter_tile<R, 2, FZ, FX, 1>(g, fk, c == 2 ? 1 : 0, bz * FZ, bx * FX, 0, src, io.out[c], lds);
+}
+
+// 3D: F x F x F output tiles (the filter's three axes in LDS).
+template <typename R, int F>
+__global__ __launch_bounds__(256) void k_filter_grid_r3d(Geo g, FiltK fk, Grid3R<R> io, int nbz,
+                                                         int nbx, int nby) {
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  R* lds = reinterpret_cast<R*>(smem_raw);
+  const int c = blockIdx.y;
+  const int b = blockIdx.x;
+  const int by = b % nby, bx = (b / nby) % nbx, bz = b / (nby * nbx);
+  GridSrcR<R> src{io.in[c], g};
+  filter_tile<R, 3, F, F, F>(g, fk, c == 2 ? 1 : 0, bz * F, bx * F, by * F, src, io.out[c], lds);
 }
 
 // --------------------------------------------------------------------------
@@ -751,18 +809,22 @@ __global__ __launch_bounds__(256) void k_copy_batch(CopyBatch cb) {
 }
 
 // --------------------------------------------------------------------------
-// Loss: the mean of Ez over a node box [i0, i1] x [j0, j1], scaled, added to
-// acc (forward) or added to the Ez adjoint (reverse).
+// Loss: the mean of Ez over a node box [i0, i1] x [j0, j1] (x [k0, k1] in 3D;
+// k0 = k1 = 0 in 2D), scaled, added to acc (forward) or added to the Ez
+// adjoint (reverse).
 // --------------------------------------------------------------------------
 template <typename R>
 __global__ __launch_bounds__(256) void k_loss_ez(Geo g, const R* Ez, int i0, int i1, int j0,
-                                                 int j1, double scale, double* acc) {
+                                                 int j1, int k0, int k1, double scale,
+                                                 double* acc) {
   __shared__ double sh[256];
-  const int ni = i1 - i0 + 1, nj = j1 - j0 + 1;
+  const int ni = i1 - i0 + 1, nj = j1 - j0 + 1, nk = k1 - k0 + 1;
   double s = 0.0;
-  for (int q = blockIdx.x * blockDim.x + threadIdx.x; q < ni * nj; q += gridDim.x * blockDim.x) {
-    const int i = i0 + q / nj, j = j0 + q % nj;
-    s += (double)Ez[gidx(g, i, j, 0)];
+  for (int q = blockIdx.x * blockDim.x + threadIdx.x; q < ni * nj * nk;
+       q += gridDim.x * blockDim.x) {
+    const int i = i0 + q / (nj * nk), rq = q % (nj * nk);
+    const int j = j0 + rq / nk, k = k0 + rq % nk;
+    s += (double)Ez[gidx(g, i, j, k)];
   }
   sh[threadIdx.x] = s;
   __syncthreads();
@@ -775,11 +837,12 @@ __global__ __launch_bounds__(256) void k_loss_ez(Geo g, const R* Ez, int i0, int
 
 template <typename R>
 __global__ __launch_bounds__(256) void k_loss_ez_adj(Geo g, R* LEz, int i0, int i1, int j0,
-                                                     int j1, R scale) {
-  const int ni = i1 - i0 + 1, nj = j1 - j0 + 1;
+                                                     int j1, int k0, int k1, R scale) {
+  const int ni = i1 - i0 + 1, nj = j1 - j0 + 1, nk = k1 - k0 + 1;
   const int q = blockIdx.x * blockDim.x + threadIdx.x;
-  if (q >= ni * nj) return;
-  LEz[gidx(g, i0 + q / nj, j0 + q % nj, 0)] += scale;
+  if (q >= ni * nj * nk) return;
+  const int rq = q % (nj * nk);
+  LEz[gidx(g, i0 + q / (nj * nk), j0 + rq / nk, k0 + rq % nk)] += scale;
 }
 
 // --------------------------------------------------------------------------

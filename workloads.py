@@ -99,9 +99,12 @@ def adjoint_setup(W, dz, beta, dt, beta_window=0.0):
     if i1 - i0 < 8:  # a box shorter than that: 9 rows centred on iL
         i0, i1 = int(max(0, iL - 4)), int(min(W["nz"] - 1, iL + 4))
     j0, j1 = W["nx"] // 2 - 4, W["nx"] // 2 + 4
+    box = (i0, i1, j0, j1)
+    if W["dim"] == 3:  # the same extent along y
+        box += (W["ny"] // 2 - 4, W["ny"] // 2 + 4)
     n = W["steps"]
     win = (n - W.get("loss_steps", max(1, n // 5)) + 1, n)
-    return dict(knots_z=kz, knots_n=kn, box=(i0, i1, j0, j1), window=win,
+    return dict(knots_z=kz, knots_n=kn, box=box, window=win,
                 interval=W.get("interval", 10))
 
 
@@ -125,6 +128,10 @@ WORKLOADS["adjoint_2d_small"] = small("adjoint_2d", nz=128, nx=32, ppc=2, steps=
                                       interval=10, nknots=5, loss_steps=20)
 WORKLOADS["adjoint_2d_tiny"] = small("adjoint_2d", nz=64, nx=16, ppc=2, steps=40,
                                      interval=10, nknots=4, loss_steps=10)
+# the adjoint's 3D case: the same physics in a 32 x 16 x 16 box (dy = dx),
+# 1 pair per cell, 24 steps, a checkpoint every 8
+WORKLOADS["adjoint_3d_tiny"] = small("adjoint_2d", dim=3, nz=32, nx=16, ny=16, dy_lambda0=0.5,
+                                     ppc=1, steps=24, interval=8, nknots=4, loss_steps=8)
 # Drifting cold plasma without laser, periodic z: the high-frequency numerical
 # instability of a plasma streaming through the grid at -beta_b, and its
 # mitigation by filtering the current.  An undisturbed pair deposits nothing,
