@@ -466,8 +466,7 @@ int bfpic_kernel_time(bfpic_ctx* h, int32_t cls, double* total_ms, int64_t* laun
  * segment of `interval` steps from its checkpoint.  Bound witness electrons
  * are carried: their states are taped, and with a witness term in the loss
  * their vector-Jacobian product (gather, push, move) is run backwards too,
- * its gathered-field part added to the field adjoint (2D; in 3D a witness
- * term in the loss is ERR_UNSUPPORTED).  With auto_window the
+ * its gathered-field part added to the field adjoint.  With auto_window the
  * taped run shifts the window as pic_step does (the loss reads each step's
  * shifted state) and the reverse sweep applies the shift's transpose;
  * particles are not re-sorted during a taped run.

@@ -1269,8 +1269,6 @@ struct Impl {
       return fail(h, BFPIC_ERR_ARG, "loss window or box out of range");
     if (DIM == 3 ? (L->k0 < 0 || L->k1 >= h->ny || L->k0 > L->k1) : (L->k0 != 0 || L->k1 != 0))
       return fail(h, BFPIC_ERR_ARG, "loss box y range out of range (2D: k0 = k1 = 0)");
-    if (DIM == 3 && L->witness_weight != 0.0)
-      return fail(h, BFPIC_ERR_UNSUPPORTED, "the witness term of the loss is built for 2D runs");
     if (!std::isfinite(L->witness_weight) || (L->witness_weight != 0.0 && h->nwit == 0))
       return fail(h, BFPIC_ERR_ARG, "witness weight needs bound witnesses");
     Tape T = tape_map(h, (uint8_t*)tape, nsteps, interval);
@@ -1470,6 +1468,12 @@ struct Impl {
             }
           } else {
             k_adj_particles_staged<R, ORDER, 3><<<nbq, 256, 0, h->stream>>>(P, F, TP, LJ, LF, A);
+            if (wit_adj) {
+              WitK W{(double*)(b + off_wit(h, false)), h->nwit,
+                     {h->dt / h->dz, h->dt / h->dx, h->dt / h->dy}, -0.5 * h->dt,
+                     h->cfg.gather_form};
+              k_adj_witness<R, ORDER, 3><<<nbw, 256, 0, h->stream>>>(g, F, W, T.wl, LF);
+            }
           }
           HIPCHK(h, hipGetLastError());
         }

@@ -950,7 +950,7 @@ __global__ __launch_bounds__(256) void k_witness_energy_seed(const double* s, in
 // with that of state), formed with dual numbers over the 12 input
 // directions; the E_p, B_p directions go to the field adjoint lf through the
 // gather's transpose.  W.s holds the taped start-of-step states.
-template <typename R, int ORDER>
+template <typename R, int ORDER, int DIM = 2>
 __global__ __launch_bounds__(256) void k_adj_witness(Geo g, Fields<R> F, WitK W, double* lam,
                                                      Fields<R> LF) {
   using D = Dual<double>;
@@ -968,7 +968,7 @@ __global__ __launch_bounds__(256) void k_adj_witness(Geo g, Fields<R> F, WitK W,
 #pragma unroll
     for (int a = 0; a < 6; a++) v[a] = D(s0[a]);
     if (dir < 6) v[dir].d = 1.0;
-    witness_advance<D, 2, ORDER>(f, g, W, v, SeedFields<double>{dir});
+    witness_advance<D, DIM, ORDER>(f, g, W, v, SeedFields<double>{dir});
     double acc = 0.0;
 #pragma unroll
     for (int a = 0; a < 6; a++) acc += lo[a] * v[a].d;
@@ -981,11 +981,11 @@ __global__ __launch_bounds__(256) void k_adj_witness(Geo g, Fields<R> F, WitK W,
   p.o[0] = (R)(s0[0] - (double)p.c[0]);
   p.c[1] = (int)floor(s0[1]);
   p.o[1] = (R)(s0[1] - (double)p.c[1]);
-  p.c[2] = 0;
-  p.o[2] = (R)0;
+  p.c[2] = DIM == 3 ? (int)floor(s0[2]) : 0;
+  p.o[2] = DIM == 3 ? (R)(s0[2] - (double)p.c[2]) : (R)0;
   const R gE[3] = {(R)gdir[6], (R)gdir[7], (R)gdir[8]};
   const R gB[3] = {(R)gdir[9], (R)gdir[10], (R)gdir[11]};
-  gather_transpose<R, ORDER>(LF.F, g, p, gE, gB, W.galerkin != 0);
+  gather_transpose<R, ORDER, DIM>(LF.F, g, p, gE, gB, W.galerkin != 0);
 }
 
 }  // namespace bfpic
