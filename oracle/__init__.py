@@ -94,6 +94,7 @@ def lib():
             "orc_create": (p, [C.POINTER(Config)]), "orc_destroy": (None, [p]),
             "orc_init": (C.c_int, [p, C.POINTER(Density), C.POINTER(Laser), i32]),
             "orc_step": (C.c_int, [p, i32]), "orc_window_shift": (C.c_int, [p, i32]),
+            "orc_set_antenna": (C.c_int, [p, C.POINTER(Laser), i32]),
             "orc_diagnostics": (C.c_int, [p, C.POINTER(Diag), p]),
             "orc_field_size": (i64, [p]), "orc_get_field": (C.c_int, [p, i32, p]),
             "orc_set_field": (C.c_int, [p, i32, p]), "orc_num_pairs": (i64, [p]),
@@ -216,6 +217,14 @@ class Sim:
 
     def step(self, n=1):
         assert lib().orc_step(self.h, n) == 0
+
+    def set_antenna(self, laser: Laser | None, row=-1):
+        """Laser antenna on grid row `row` (None removes it): each later step
+        adds the current sheet that emits the laser's boosted E_y there."""
+        self._antenna = laser
+        rc = lib().orc_set_antenna(self.h, C.byref(laser) if laser is not None else None,
+                                   int(row) if laser is not None else -1)
+        assert rc == 0, "antenna row out of range"
 
     def window_shift(self, n):
         assert lib().orc_window_shift(self.h, n) == 0

@@ -86,6 +86,9 @@ struct orc_sim {
    * deposits into tJ[t-1][comp]; thread 0 into the grid's own J) */
   int nthreads;
   double** tJ;
+  /* laser antenna: a current sheet on grid row ant_row (< 0: none) */
+  int ant_row;
+  orc_laser ant;
 };
 
 /* ------------------------------------------------------------------------ */
@@ -859,6 +862,7 @@ orc_sim* orc_create(const orc_config* cfg) {
   int64_t total = (int64_t)s->nzs * s->plane;
   for (int a = 0; a < ORC_NCOMP; a++) s->F[a] = (double*)calloc((size_t)total, sizeof(double));
   s->rho = (double*)calloc((size_t)total, sizeof(double));
+  s->ant_row = -1;
   return s;
 }
 
@@ -982,6 +986,51 @@ int32_t orc_max_threads(void) {
 
 /* One full step: inject -> (gather, Boris, move, deposit) per electron,
  * rigid drift + deposit per ion partner -> filter J -> Yee -> removal. */
+/* Laser antenna.  A sheet of current K (per unit transverse area) in the plane
+ * z = z_a radiates E_y = -K/2 on both sides in 1D vacuum (the jump of B_x
+ * across the sheet is K, split evenly between the two outgoing waves).  A
+ * sheet on one row of the grid carries K = J_y dz, so the current
+ * J_y = -2 E_target / dz, applied over the step n -> n+1 (time-centred at
+ * t' = (n + 1/2) dt), emits the target field E_y'(t', z_a, x[, y]) of the
+ * laser into both directions.  The target is the boosted laser of init (its
+ * lab potential evaluated at the boosted event), with the same transverse
+ * images; the row is fixed on the grid and z_a = (row + window) dz.  The
+ * current is added after the filter (the source is not smoothed). */
+static void antenna_source(orc_sim* s) {
+  const orc_config* c = &s->c;
+  const orc_laser* L = &s->ant;
+  int d3 = c->dim == 3;
+  double tp = ((double)s->step + 0.5) * c->dt;
+  double zp = ((double)s->ant_row + s->window_cells) * c->dz;
+  double xa = 0.5 * c->nx * c->dx, ya = d3 ? 0.5 * c->ny * c->dy : 0.0;
+  double Lx = c->nx * c->dx, Ly = d3 ? c->ny * c->dy : 0.0;
+  int my = d3 ? L->images_y : 0;
+  for (int64_t j = 0; j < c->nx; j++)
+    for (int64_t k = 0; k < s->nyy; k++) {
+      double x = (double)j * c->dx - xa;
+      double y = d3 ? ((double)k + 0.5) * c->dy - ya : 0.0;
+      double Es = 0.0;
+      for (int mx = -L->images_x; mx <= L->images_x; mx++)
+        for (int mm = -my; mm <= my; mm++) {
+          double a, e;
+          orc_laser_eval(L, c->dim, c->gamma_b, tp, zp, x + mx * Lx, y + mm * Ly, &a, &e);
+          Es += e;
+        }
+      s->F[ORC_JY][node(s, s->ant_row, j, k)] += -2.0 * Es / c->dz;
+    }
+}
+
+int orc_set_antenna(orc_sim* s, const orc_laser* laser, int32_t row) {
+  if (!laser || row < 0) {
+    s->ant_row = -1;
+    return 0;
+  }
+  if (row < 1 || row > s->c.nz - 1) return -1;
+  s->ant = *laser;
+  s->ant_row = row;
+  return 0;
+}
+
 int orc_step(orc_sim* s, int32_t nsteps) {
   const orc_config* c = &s->c;
   int d3 = c->dim == 3;
@@ -1048,6 +1097,7 @@ int orc_step(orc_sim* s, int32_t nsteps) {
     apply_filter(s, s->F[ORC_JX], SIG[ORC_JX][0]);
     apply_filter(s, s->F[ORC_JY], SIG[ORC_JY][0]);
     apply_filter(s, s->F[ORC_JZ], SIG[ORC_JZ][0]);
+    if (s->ant_row >= 0) antenna_source(s);
     yee_b(s, 0.5 * c->dt);
     yee_e(s, c->dt);
     yee_b(s, 0.5 * c->dt);

@@ -127,6 +127,10 @@ orc_sim* orc_create(const orc_config* cfg);
 void orc_destroy(orc_sim* s);
 int orc_init(orc_sim* s, const orc_density* dens, const orc_laser* laser, int32_t fill);
 int orc_step(orc_sim* s, int32_t nsteps);
+/* Laser antenna on grid row `row` (1 .. nz-1): every later step adds the
+ * current sheet J_y = -2 E_y'(t', z_a, x, y) / dz of `laser` after the filter.
+ * NULL or row < 0 removes it.  -1 for a row out of range. */
+int orc_set_antenna(orc_sim* s, const orc_laser* laser, int32_t row);
 int orc_window_shift(orc_sim* s, int32_t ncells);
 int orc_diagnostics(orc_sim* s, orc_diag* out, double* lineout /* nz or NULL */);
 /* Threads (OpenMP) of the particle loop, whose per-thread current buffers
