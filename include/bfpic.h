@@ -403,6 +403,22 @@ int pic_save(bfpic_ctx* h, void* blob_dev, int64_t blob_bytes);
  * (re-initialise or load again).  Synchronises. */
 int pic_load(bfpic_ctx* h, const void* blob_dev, int64_t blob_bytes);
 
+/* Laser antenna (an alternative to placing the laser in the box at init;
+ * the paper's boosted runs start with the laser in the box, section "Effect
+ * of the hyperbolic rotation", so the antenna extends the method rather than
+ * following a passage of it): from the next pic_step on, every step adds to the filtered current on grid
+ * row `row` (1 .. nz-1) the sheet J_y = -2 E_y'(t', z_a, x, y) / dz, which
+ * radiates the boosted field E_y' of `laser` (as init_boosted_plasma would
+ * place it, same parameters and images) into both directions: a surface
+ * current K radiates E_y = -K/2 on either side in 1D vacuum.  t' is the step's
+ * mid time and z_a = (row + window cells) dz (the row moves with the window).
+ * The source is not filtered.  laser = NULL removes the antenna;
+ * init_boosted_plasma removes it too, and pic_save does not record it.
+ * ERR_STATE before init, ERR_ARG for a row out of range or bad laser
+ * parameters.  A taped adjoint run refuses a context with an antenna
+ * (ERR_UNSUPPORTED). */
+int bfpic_antenna(bfpic_ctx* h, const bfpic_laser* laser, int32_t row);
+
 /* ---- state access (tests and tools; asynchronous unless stated) ---- */
 
 /* Copies component comp at integer time (domain rows 0..nz; row nz is zero

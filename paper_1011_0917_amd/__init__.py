@@ -96,7 +96,7 @@ EXPORTS = ["bfpic_beta", "bfpic_drift_u", "bfpic_group_gamma", "bfpic_boosted_gr
            "bfpic_set_field", "bfpic_num_slots", "bfpic_get_particles", "bfpic_sort",
            "bfpic_last_sort", "bfpic_sort_permutation", "bfpic_tile_shape", "bfpic_kernel_timing", "bfpic_kernel_time",
            "bfpic_adjoint_tape_bytes", "bfpic_forward_loss", "pic_step_adjoint",
-           "bfpic_adjoint_per_direction",
+           "bfpic_adjoint_per_direction", "bfpic_antenna",
            "bfpic_axis_record", "bfpic_back_transform", "bfpic_axis_spectrum",
            "bfpic_witness_bind", "bfpic_witness_lab", "bfpic_state_bytes", "pic_save",
            "pic_load"]
@@ -140,6 +140,7 @@ def lib():
         "bfpic_forward_loss": (C.c_int, [p, i32, i32, C.POINTER(Loss), p, i64, C.POINTER(d)]),
         "pic_step_adjoint": (C.c_int, [p, C.POINTER(d), C.POINTER(d), i32]),
         "bfpic_adjoint_per_direction": (C.c_int, [p, i32]),
+        "bfpic_antenna": (C.c_int, [p, C.POINTER(Laser), i32]),
         "bfpic_axis_record": (C.c_int, [p, i32, p, C.POINTER(AxisMeta)]),
         "bfpic_back_transform": (C.c_int, [p, p, p, p, i64, i32, d, d, d, d, i32, d, d, i32, d,
                                            p]),
@@ -249,6 +250,12 @@ class Simulation:
                                          C.byref(dens) if dens is not None else None,
                                          C.byref(laser) if laser is not None else None), self.h)
         self._wit = None  # init unbinds the witnesses
+
+    def antenna(self, laser: Laser | None = None, row=0):
+        """Laser antenna on grid row `row` emitting `laser` (None removes it)."""
+        self._antenna = laser
+        _check(lib().bfpic_antenna(self.h, C.byref(laser) if laser is not None else None,
+                                   int(row)), self.h)
 
     def pic_step(self, nsteps=1):
         _check(lib().pic_step(self.h, int(nsteps)), self.h)

@@ -199,6 +199,9 @@ struct bfpic_ctx {
   bool adj_ready = false;    // the tape holds a forward run
   bool adj_recompute = false;
   bool adj_per_direction = false;  // reverse particle step: one dual pass per direction
+  bool ant_on = false;             // laser antenna on grid row ant_row
+  int ant_row = 0;
+  LaserK ant_K{};
   int adj_nsteps = 0, adj_interval = 0;
   int64_t adj_slots = 0;     // slots created by the taped run
   int adj_nwit = 0;          // witnesses bound during the taped run
@@ -736,6 +739,60 @@ struct Impl {
     return P;
   }
 
+  // A laser's constants in this context's frame (beta_b of gamma_boost).
+  static LaserK laser_consts(bfpic_ctx* h, const bfpic_laser* laser, double gamma_boost) {
+    LaserK K;
+    K.a0 = laser->a0;
+    K.w0 = laser->w0;
+    K.L = laser->L;
+    K.zc = laser->z_center;
+    K.zf = laser->z_focus;
+    K.phase = laser->phase;
+    K.collimated = laser->collimated;
+    K.iz = laser->images_z;
+    K.ix = laser->images_x;
+    K.iy = laser->images_y;
+    K.dim = DIM;
+    K.gamma_b = gamma_boost;
+    K.gomb = 1.0 / (gamma_boost * (1.0 + h->beta_b));  // gamma (1 - beta)
+    K.gbeta = gamma_boost * h->beta_b;
+    K.Lz = h->nz * h->dz;
+    K.Lx = h->nx * h->dx;
+    K.Ly = h->ny * h->dy;
+    K.xa = 0.5 * h->nx * h->dx;
+    K.ya = DIM == 3 ? 0.5 * h->ny * h->dy : 0.0;
+    K.dz = h->dz;
+    K.dx = h->dx;
+    K.dy = h->dy;
+    return K;
+  }
+
+  static int set_antenna(bfpic_ctx* h, const bfpic_laser* laser, int row) {
+    if (!laser) {
+      h->ant_on = false;
+      return BFPIC_OK;
+    }
+    if (!h->inited) return fail(h, BFPIC_ERR_STATE, "init_boosted_plasma first");
+    if (row < 1 || row > h->nz - 1) return fail(h, BFPIC_ERR_ARG, "antenna row outside 1 .. nz-1");
+    if (!std::isfinite(laser->a0) || !(laser->L >= 0.0) || !(laser->w0 >= 0.0) ||
+        laser->images_x < 0 || laser->images_y < 0)
+      return fail(h, BFPIC_ERR_ARG, "antenna laser parameters");
+    h->ant_K = laser_consts(h, laser, h->gamma_b);
+    h->ant_row = row;
+    h->ant_on = true;
+    return BFPIC_OK;
+  }
+
+  // The antenna's current sheet for this step, onto the filtered current.
+  static int antenna(bfpic_ctx* h) {
+    const double tp = ((double)h->step + 0.5) * h->dt;
+    const double zp = ((double)h->ant_row + (double)h->window_cells) * h->dz;
+    k_antenna<R><<<(unsigned)cdiv(h->g.plane, 256), 256, 0, h->stream>>>(
+        h->g, h->ant_K, tp, zp, h->ant_row, (R*)h->Jf[1]);
+    HIPCHK(h, hipGetLastError());
+    return BFPIC_OK;
+  }
+
   static FoldK<R> fold_consts(bfpic_ctx* h, const StepK<R>& P) {
     FoldK<R> K;
     K.scratch = h->scratch;
@@ -976,6 +1033,10 @@ struct Impl {
       k_ovf_clear<R, DET><<<1024, 256, 0, h->stream>>>(g, O);
       k_ovf_reset<<<1, 1, 0, h->stream>>>(h->ovf_rows, h->counts + 4);
       HIPCHK(h, hipGetLastError());
+    }
+    if (h->ant_on) {
+      const int rc = antenna(h);
+      if (rc) return rc;
     }
     return BFPIC_OK;
   }
@@ -1254,6 +1315,7 @@ struct Impl {
 
   static int adjoint_check(bfpic_ctx* h, int nsteps, int interval) {
     if (!h->inited) return fail(h, BFPIC_ERR_STATE, "init_boosted_plasma first");
+    if (h->ant_on) return fail(h, BFPIC_ERR_UNSUPPORTED, "the adjoint is built without antenna");
     if (nsteps < 1 || interval < 1) return fail(h, BFPIC_ERR_ARG, "nsteps, interval >= 1");
     return BFPIC_OK;
   }
@@ -1589,6 +1651,7 @@ struct Impl {
     if (rca) return rca;
     // from here on a failure leaves the context needing a new init
     h->inited = false;
+    h->ant_on = false;  // init removes the antenna (its constants depend on the boost)
     h->gamma_b = gamma_boost;
     h->beta_b = bfpic_beta(gamma_boost);
     h->u_b = bfpic_drift_u(gamma_boost);
@@ -1609,29 +1672,7 @@ struct Impl {
     if (rc0) return rc0;
     const int64_t grid = g.rows * g.plane;
     if (laser) {
-      LaserK K;
-      K.a0 = laser->a0;
-      K.w0 = laser->w0;
-      K.L = laser->L;
-      K.zc = laser->z_center;
-      K.zf = laser->z_focus;
-      K.phase = laser->phase;
-      K.collimated = laser->collimated;
-      K.iz = laser->images_z;
-      K.ix = laser->images_x;
-      K.iy = laser->images_y;
-      K.dim = DIM;
-      K.gamma_b = gamma_boost;
-      K.gomb = 1.0 / (gamma_boost * (1.0 + h->beta_b));  // gamma (1 - beta)
-      K.gbeta = gamma_boost * h->beta_b;
-      K.Lz = h->nz * h->dz;
-      K.Lx = h->nx * h->dx;
-      K.Ly = h->ny * h->dy;
-      K.xa = 0.5 * h->nx * h->dx;
-      K.ya = DIM == 3 ? 0.5 * h->ny * h->dy : 0.0;
-      K.dz = h->dz;
-      K.dx = h->dx;
-      K.dy = h->dy;
+      const LaserK K = laser_consts(h, laser, gamma_boost);
       HIPCHK(h, hipMemsetAsync(h->g64a, 0, grid * 8, h->stream));
       HIPCHK(h, hipMemsetAsync(h->g64b, 0, grid * 8, h->stream));
       int64_t nrow = g.periodic_z ? h->nz : h->nz + 1;
@@ -2372,6 +2413,11 @@ extern "C" int bfpic_forward_loss(bfpic_ctx* h, int32_t nsteps, int32_t interval
                                   double* loss_out) {
   if (!h || !loss || !loss_out) return BFPIC_ERR_ARG;
   BFPIC_DISPATCH(h, I::forward_loss(h, nsteps, interval, loss, tape, tape_bytes, loss_out));
+}
+
+extern "C" int bfpic_antenna(bfpic_ctx* h, const bfpic_laser* laser, int32_t row) {
+  if (!h) return BFPIC_ERR_ARG;
+  BFPIC_DISPATCH(h, I::set_antenna(h, laser, row));
 }
 
 extern "C" int bfpic_adjoint_per_direction(bfpic_ctx* h, int32_t enable) {

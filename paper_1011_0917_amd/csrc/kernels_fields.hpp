@@ -993,6 +993,36 @@ __global__ __launch_bounds__(256) void k_laser_ez(Geo g, const double* Ey64, dou
   }
 }
 
+// --------------------------------------------------------------------------
+// Laser antenna: the current sheet J_y = -2 E_y'(t', z_a, x[, y]) / dz on one
+// grid row, which radiates the boosted laser's E_y into both directions (in
+// 1D vacuum a surface current K radiates E_y = -K/2 on either side; a sheet on
+// one row carries K = J_y dz).  Added to the filtered current; t' is the
+// step's mid time, the laser is evaluated at the boosted event (t', z_a) as in
+// k_laser_a, with its transverse images.  One thread per node of the row.
+// --------------------------------------------------------------------------
+template <typename R>
+__global__ __launch_bounds__(256) void k_antenna(Geo g, LaserK K, double tp, double zp, int row,
+                                                 R* Jy) {
+  const int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (q >= g.plane) return;
+  const int j = (int)(q / g.ny), k = (int)(q - (int64_t)j * g.ny);
+  const double x = (double)j * K.dx - K.xa;
+  const double y = K.dim == 3 ? ((double)k + 0.5) * K.dy - K.ya : 0.0;
+  const double xi = K.gomb * (zp - tp) - K.zc;
+  const double zeta = K.gamma_b * zp + K.gbeta * tp - K.zf;
+  const int my = K.dim == 3 ? K.iy : 0;
+  double Es = 0.0;
+  for (int mx = -K.ix; mx <= K.ix; mx++)
+    for (int mm = -my; mm <= my; mm++) {
+      double a, dxi, dze;
+      lab_potential(K, xi, zeta, x + mx * K.Lx, y + mm * K.Ly, a, dxi, dze);
+      Es += K.gomb * dxi - K.gbeta * dze;
+    }
+  Jy[gidx(g, row, j, k)] += (R)(-2.0 * Es / K.dz);
+}
+
+
 // Field copies between the internal real type and FP64 domain arrays.
 template <typename R>
 __global__ __launch_bounds__(256) void k_get_field(Geo g, const R* A, double* out, int half_z) {
