@@ -171,6 +171,7 @@ struct bfpic_ctx {
   int* tile_start = nullptr;
   int* tile_order = nullptr;
   void* scratch = nullptr;
+  unsigned* tbox = nullptr;  // 3D: box word of each tile region
   int* key = nullptr;
   int* rank = nullptr;
   int* perm = nullptr;
@@ -419,6 +420,8 @@ static int64_t plan(bfpic_ctx* h, int64_t cap, bfpic_ctx* fill, bfpic_sizes* sz)
                        (int64_t)ovf_bytes(h)
                  : 0);
   if (fill) fill->scratch = p;
+  p = P(h->tiled && h->dim == 3 ? h->maxtiles * 4 : 0);
+  if (fill) fill->tbox = (unsigned*)p;
   p = P(cap * 4);
   if (fill) fill->strag = (int*)p;
   p = P(cap * 4);
@@ -814,6 +817,7 @@ struct Impl {
     K.LY = h->LY;
     K.LV = h->LV;
     K.zero_base = h->maxtiles * 3 * (int64_t)h->LV;
+    K.box = h->tbox;
     K.o = ovf(h);
     return K;
   }
@@ -984,6 +988,7 @@ struct Impl {
       T.zc0 = h->zc0;
       T.strag = h->strag;
       T.nstrag = h->counts + 4;
+      T.box = h->tbox;
       if constexpr (DIM == 2)
         k_gpd_tiled<R, 2, ORDER, kT2Z, kT2X, 1, kExc, kGpdThreads<R>, DET>
             <<<T.ntiles, kGpdThreads<R>, h->lds_tiled, h->stream>>>(P, F, S, T, O, h->scratch);

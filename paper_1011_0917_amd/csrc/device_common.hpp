@@ -254,6 +254,13 @@ __device__ __forceinline__ int shape(int c, R o, int half, R w[ORDER + 1]) {
   }
 }
 
+// First node of shape(c, o, 0, w) on the integer lattice, without the weights.
+template <typename R, int ORDER>
+__device__ __forceinline__ int shape_base(int c, R o) {
+  if (ORDER == 1) return c;
+  return o >= (R)0.5 ? c : c - 1;
+}
+
 // Energy-conserving (Galerkin) gather: on the half-integer lattice the shape
 // of one order lower, written on the node window of shape(c, o, 1, w) so that
 // it reads the same nodes: order 0 (the half node c + 1/2 of the particle's
@@ -343,6 +350,29 @@ __device__ __forceinline__ int xcd_remap(int b, int n) {
   int per = n / X, rem = n % X;
   int x = b % X, idx = b / X;
   return x < rem ? x * (per + 1) + idx : rem * (per + 1) + (x - rem) * per + idx;
+}
+
+// Box of a 3D tile region's nonzero nodes, one word per tile: first node
+// and extent along z, x, y, 5 bits each (regions are under 32 nodes per
+// axis).  A zero word is the empty box.  The region's scratch slot holds
+// just the box, component-major, z-major within a component.
+struct RegionBox {
+  int z0, nz, x0, nx, y0, ny;
+  __device__ __forceinline__ int vol() const { return nz * nx * ny; }
+};
+__device__ __forceinline__ unsigned pack_box(int z0, int nz, int x0, int nx, int y0, int ny) {
+  return (unsigned)z0 | ((unsigned)nz << 5) | ((unsigned)x0 << 10) | ((unsigned)nx << 15) |
+         ((unsigned)y0 << 20) | ((unsigned)ny << 25);
+}
+__device__ __forceinline__ RegionBox unpack_box(unsigned w) {
+  RegionBox b;
+  b.z0 = (int)(w & 31u);
+  b.nz = (int)((w >> 5) & 31u);
+  b.x0 = (int)((w >> 10) & 31u);
+  b.nx = (int)((w >> 15) & 31u);
+  b.y0 = (int)((w >> 20) & 31u);
+  b.ny = (int)((w >> 25) & 31u);
+  return b;
 }
 
 }  // namespace bfpic

@@ -26,6 +26,8 @@ struct FoldK {
   int gz0, gx0, gy0;  // region origin of tile (0,0,0) in grid cells
   int TZ, TX, TY, LZ, LX, LY, LV;
   int64_t zero_base;    // element offset of the row of zero tiles past the last tile
+  const unsigned* box;  // 3D: per tile, the box of its region's nonzero nodes (the
+                        // slot holds just the box)
   Ovf<R> o;
 };
 
@@ -70,8 +72,17 @@ __device__ __forceinline__ R fold_at(const FoldK<R>& K, const Geo& g, int comp, 
           if (ty < 0) ty += K.nty;
           const bool v = vx && (DIM != 3 || ry < K.LY);
           const int t = (tz * K.ntx + tx) * K.nty + ty;
-          const int64_t e = v ? ((int64_t)t * 3 + comp) * K.LV + (rz * K.LX + rx) * K.LY + ry
-                              : K.zero_base;
+          int64_t e = K.zero_base;
+          if constexpr (DIM == 3) {
+            const unsigned w = K.box[v ? t : 0];
+            const RegionBox bx = unpack_box(v ? w : 0u);
+            const int oz = rz - bx.z0, ox = rx - bx.x0, oy = ry - bx.y0;
+            if ((unsigned)oz < (unsigned)bx.nz && (unsigned)ox < (unsigned)bx.nx &&
+                (unsigned)oy < (unsigned)bx.ny)
+              e = (int64_t)t * 3 * K.LV + comp * bx.vol() + (oz * bx.nx + ox) * bx.ny + oy;
+          } else {
+            if (v) e = ((int64_t)t * 3 + comp) * K.LV + (rz * K.LX + rx) * K.LY + ry;
+          }
           acc += scratch[e];
         }
       }
@@ -404,11 +415,11 @@ __global__ __launch_bounds__(256) void k_filt3_z(Geo g, FoldK<R> K, FiltK fk, Fi
 // z sweep with the fold, open z, windows aligned to the tile rows: window
 // rows start where a tile row's region starts (row gz0 + m TZ), so that each
 // window row's local row in a region, and with it the set of tile rows whose
-// regions hold it, are compile-time constants; only the regions that do
-// hold a node are read.  Along x the candidates are the same for a whole
-// thread column (NBX: 3 where some lane of the wave needs a third, else 2),
-// along y a lane without a third candidate reads its first one again and
-// discards it.  Same sums, in the same order, as fold_at.
+// regions hold it, are compile-time constants.  Along x the candidates are
+// the same for a whole thread column (NBX: 3 where some lane of the wave
+// needs a third, else 2).  A candidate is read only where the node lies in
+// its region's box of nonzero nodes.  Same sums, in the same order, as
+// fold_at.
 template <typename R, int NP, int SZ, int TZ, int TX, int TY, int LZ, int LX, int LY, bool DET,
           int NBX>
 __device__ __forceinline__ void filt3_z_aligned_body(const Geo& g, const FoldK<R>& K,
@@ -419,67 +430,73 @@ __device__ __forceinline__ void filt3_z_aligned_body(const Geo& g, const FoldK<R
   using A = typename std::conditional<DET, long long, R>::type;
   const A* scratch = reinterpret_cast<const A*>(K.scratch);
   const int hz = half_z_j(comp);
-  // x and y candidates of this column
+  // x and y candidates of this column: tile within a tile row, and whether
+  // the column lies in that tile's region
   const int qx = wrap_small(j - K.gx0, g.nx), qy = wrap_small(k - K.gy0, g.ny);
   const int hx = qx / TX, lx = qx - hx * TX;
   const int hy = qy / TY, ly = qy - hy * TY;
-  int off[NBX][3];
+  int tin[NBX][3];
   bool val[NBX][3];
 #pragma unroll
   for (int b = 0; b < NBX; b++) {
     int tx = hx - b;
     if (tx < 0) tx += K.ntx;
-    const int rx = lx + b * TX;
 #pragma unroll
     for (int c = 0; c < 3; c++) {
       int ty = hy - c;
       if (ty < 0) ty += K.nty;
-      const int ry = ly + c * TY;
-      val[b][c] = rx < LX && ry < LY;
-      off[b][c] = val[b][c] ? (tx * K.nty + ty) * 3 * LV + rx * LY + ry : 0;
+      val[b][c] = lx + b * TX < LX && ly + c * TY < LY;
+      tin[b][c] = tx * K.nty + ty;
     }
   }
-#pragma unroll
-  for (int b = 0; b < NBX; b++)
-#pragma unroll
-    for (int c = 0; c < 3; c++)
-      if (!val[b][c]) off[b][c] = off[0][0];
-  // tile rows m - 2 .. m + (L - 1) / TZ; outside [0, ntz) the zero row
+  // Tile rows m - 2 .. m + (L - 1) / TZ; row d holds window row r at local
+  // z r - (d - 2) TZ.  Taken from the top row down, so that each window row
+  // adds its candidates in the order of fold_at (z, then x, then y); only
+  // nodes inside a region's box are read.
   constexpr int NTR = (L - 1) / TZ + 3;
-  const int64_t tile_row = (int64_t)K.ntx * K.nty * 3 * LV;
-  const A* rowp[NTR];
+  const int row_tiles = K.ntx * K.nty;
+  A acc[L];
 #pragma unroll
-  for (int d = 0; d < NTR; d++) {
-    const int t = m + d - 2;
-    rowp[d] = scratch + (t >= 0 && t < K.ntz ? (int64_t)t * tile_row : K.zero_base) + comp * LV;
+  for (int r = 0; r < L; r++) acc[r] = (A)0;
+#pragma unroll
+  for (int d = NTR - 1; d >= 0; d--) {
+    const int tr = m + d - 2;
+    const bool row_ok = tr >= 0 && tr < K.ntz;
+#pragma unroll
+    for (int b = 0; b < NBX; b++)
+#pragma unroll
+      for (int c = 0; c < 3; c++) {
+        const bool ok = row_ok && val[b][c];
+        const int t = ok ? tr * row_tiles + tin[b][c] : 0;
+        const unsigned w = K.box[t];
+        const RegionBox bx = unpack_box(ok ? w : 0u);
+        const int ox = lx + b * TX - bx.x0, oy = ly + c * TY - bx.y0;
+        const bool in_xy = (unsigned)ox < (unsigned)bx.nx && (unsigned)oy < (unsigned)bx.ny;
+        const int64_t base = (int64_t)t * 3 * LV + comp * bx.vol() + ox * bx.ny + oy;
+        const int zs = bx.nx * bx.ny;
+#pragma unroll
+        for (int r = 0; r < L; r++) {
+          const int lz = r - (d - 2) * TZ;
+          if (lz < 0 || lz >= LZ) continue;  // compile-time
+          const int oz = lz - bx.z0;
+          if (in_xy && (unsigned)oz < (unsigned)bx.nz) acc[r] += scratch[base + oz * zs];
+        }
+      }
   }
   const int r0 = K.o.rows[0], r1 = K.o.rows[1];
   R v[L];
 #pragma unroll
   for (int r = 0; r < L; r++) {
-    const int lz = r % TZ, hzr = r / TZ;  // tile row m + hzr holds row r at local lz
-    A acc = (A)0;
-#pragma unroll
-    for (int a = 0; a < 3; a++) {
-      if (lz + a * TZ >= LZ) continue;  // compile-time
-      const A* rp = rowp[hzr - a + 2] + (lz + a * TZ) * LX * LY;
-#pragma unroll
-      for (int b = 0; b < NBX; b++)
-#pragma unroll
-        for (int c = 0; c < 3; c++) {
-          const A x = rp[off[b][c]];
-          acc += val[b][c] ? x : (A)0;
-        }
-    }
+    A a = acc[r];
     const int i = i0 - H + r;
     if (i >= r0 && i <= r1 && i >= -kGuard && i <= g.nz + kGuard) {
       const int64_t n = (int64_t)(i + kGuard) * g.plane + q;
-      if constexpr (DET) acc += K.o.Jq[comp][n];
-      else acc += K.o.J[comp][n];
+      if constexpr (DET) a += K.o.Jq[comp][n];
+      else a += K.o.J[comp][n];
     }
     R x;
-    if constexpr (DET) x = (R)((double)acc * K.inv_scale);
-    else x = acc;
+    if constexpr (DET) x = (R)((double)a * K.inv_scale);
+    else x = a;
     v[r] = in_domain(g, hz, i) ? x : (R)0;
   }
 #pragma unroll

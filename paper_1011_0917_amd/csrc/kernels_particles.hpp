@@ -935,6 +935,7 @@ struct TileK {
   int zc0;           // first co-moving z cell of tile row 0
   int* strag;        // straggler slots
   int* nstrag;       // their count
+  unsigned* box;     // 3D: per tile, the box of its region's nonzero nodes
 };
 
 // Region of a tile: its cells, the excursion margin EXC on each side, one row
@@ -1041,13 +1042,21 @@ k_gpd_tiled(StepK<R> P, Fields<R> F, PSoA<R> S, TileK T, Ovf<R> O, void* scratch
   for (int v = threadIdx.x; v < 3 * LV; v += NT) sJ[v] = (A)0;
   // overflow rows reached by far partners, gathered per tile
   __shared__ int far_rows[2];
+  // 3D: box of the region's nonzero nodes (first and last node per axis)
+  __shared__ int box_lo[3], box_hi[3];
   if (threadIdx.x == 0) {
     far_rows[0] = INT_MAX;
     far_rows[1] = INT_MIN;
+    for (int a = 0; a < 3; a++) {
+      box_lo[a] = INT_MAX;
+      box_hi[a] = INT_MIN;
+    }
   }
   __syncthreads();
   LdsSinkT<A, LX, LY, DET> ls{sJ, LV};
   const int p0 = T.start[t], p1 = T.start[t + 1];
+  // 3D: this thread's box of the region nodes its particles deposit to
+  int blo[3] = {INT_MAX, INT_MAX, INT_MAX}, bhi[3] = {INT_MIN, INT_MIN, INT_MIN};
   auto particles = [&](const auto& lf) {
     // the whole state of the next particle is loaded while this one is pushed
     int p = p0 + (int)threadIdx.x;
@@ -1096,6 +1105,29 @@ k_gpd_tiled(StepK<R> P, Fields<R> F, PSoA<R> S, TileK T, Ovf<R> O, void* scratch
       Pos<R> i1 = ion_at<R, DIM>(b, r, P.D1);
       int bc[3] = {rz, rx, ry};
       bool dead = particle_step<R, DIM, ORDER>(P, lf, ls, bc, e0, i0, i1, xi, du, w, NoHook(), near);
+      if constexpr (DIM == 3) {
+        // Per axis the deposit's nonzero values lie on the nodes from the
+        // lower to the higher of the old and new shape bases plus ORDER (the
+        // window's last node, one past the shapes, takes only zeros when the
+        // base does not change), at region index bc + (node - e0.c); the
+        // partner's nodes too when it deposits here.
+        const Pos<R> e1 = add_xi<R, DIM>(i1, xi);
+#pragma unroll
+        for (int a = 0; a < 3; a++) {
+          const int s = bc[a] - e0.c[a];
+          const int b0 = shape_base<R, ORDER>(e0.c[a], e0.o[a]);
+          const int b1 = shape_base<R, ORDER>(e1.c[a], e1.o[a]);
+          int lo = min(b0, b1), hi = max(b0, b1);
+          if (near) {
+            const int c0 = shape_base<R, ORDER>(i0.c[a], i0.o[a]);
+            const int c1 = shape_base<R, ORDER>(i1.c[a], i1.o[a]);
+            lo = min(lo, min(c0, c1));
+            hi = max(hi, max(c0, c1));
+          }
+          blo[a] = min(blo[a], lo + s);
+          bhi[a] = max(bhi[a], hi + ORDER + s);
+        }
+      }
       if (!near) {
         atomicMin(&far_rows[0], min(e0.c[0], i0.c[0]) - ORDER - 1);
         atomicMax(&far_rows[1], max(e0.c[0], i0.c[0]) + ORDER + 2);
@@ -1119,12 +1151,52 @@ k_gpd_tiled(StepK<R> P, Fields<R> F, PSoA<R> S, TileK T, Ovf<R> O, void* scratch
     atomicMin(&O.rows[0], g.periodic_z ? 0 : far_rows[0]);
     atomicMax(&O.rows[1], g.periodic_z ? g.nz : far_rows[1]);
   }
-  if constexpr (DET) {
-    long long* dst = reinterpret_cast<long long*>(scratch) + (int64_t)t * 3 * LV;
-    for (int v = threadIdx.x; v < 3 * LV; v += NT) dst[v] = sJ[v];
+  using D = typename std::conditional<DET, long long, R>::type;
+  D* dst = reinterpret_cast<D*>(scratch) + (int64_t)t * 3 * LV;
+  if constexpr (DIM == 3) {
+    // Only the box of the nodes the particles deposited to is stored
+    // (outside it every node of the region is zero), which cuts the flush
+    // and the fold's reads to what the tile's particles reached.
+    static_assert(LZ < 32 && LX < 32 && LY < 32, "box fields of 5 bits");
+    static_assert(3 * LV < (1 << 14), "exact FP32 index division");
+#pragma unroll
+    for (int a = 0; a < 3; a++) {
+#pragma unroll
+      for (int o = 32; o > 0; o >>= 1) {
+        blo[a] = min(blo[a], __shfl_xor(blo[a], o));
+        bhi[a] = max(bhi[a], __shfl_xor(bhi[a], o));
+      }
+    }
+    if ((threadIdx.x & 63) == 0 && bhi[0] != INT_MIN) {
+      for (int a = 0; a < 3; a++) {
+        atomicMin(&box_lo[a], blo[a]);
+        atomicMax(&box_hi[a], bhi[a]);
+      }
+    }
+    __syncthreads();
+    // clipped to the region (every deposit lies inside it)
+    const int z0 = max(box_lo[0], 0), x0 = max(box_lo[1], 0), y0 = max(box_lo[2], 0);
+    const int z1 = min(box_hi[0], LZ - 1), x1 = min(box_hi[1], LX - 1), y1 = min(box_hi[2], LY - 1);
+    const bool any = z0 <= z1 && x0 <= x1 && y0 <= y1;
+    const int nz = any ? z1 - z0 + 1 : 0, nx = any ? x1 - x0 + 1 : 0, ny = any ? y1 - y0 + 1 : 0;
+    const int nxy = nx * ny, vol = nz * nxy;
+    // u / n as floor((u + 1/2) (1/n)) in FP32: exact for u below 2^14 (the
+    // fraction of (u + 1/2) / n stays 1/(2n) away from an integer, far above
+    // the rounding of the product)
+    const float rvol = 1.0f / (float)max(vol, 1), rxy = 1.0f / (float)max(nxy, 1),
+                rny = 1.0f / (float)max(ny, 1);
+    for (int u = threadIdx.x; u < 3 * vol; u += NT) {
+      const int c = (int)(((float)u + 0.5f) * rvol);
+      const int e = u - c * vol;
+      const int z = (int)(((float)e + 0.5f) * rxy);
+      const int f = e - z * nxy;
+      const int x = (int)(((float)f + 0.5f) * rny);
+      const int y = f - x * ny;
+      dst[u] = (D)sJ[c * LV + ((z0 + z) * LX + (x0 + x)) * LY + (y0 + y)];
+    }
+    if (threadIdx.x == 0) T.box[t] = any ? pack_box(z0, nz, x0, nx, y0, ny) : 0u;
   } else {
-    R* dst = reinterpret_cast<R*>(scratch) + (int64_t)t * 3 * LV;
-    for (int v = threadIdx.x; v < 3 * LV; v += NT) dst[v] = (R)sJ[v];
+    for (int v = threadIdx.x; v < 3 * LV; v += NT) dst[v] = (D)sJ[v];
   }
 }
 
