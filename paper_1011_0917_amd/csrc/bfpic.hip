@@ -100,6 +100,15 @@ constexpr int kGpdThreads = sizeof(R) == 4 ? BFPIC_GPD_THREADS32 : BFPIC_GPD_THR
 #define BFPIC_GPD3_THREADS 512
 #endif
 constexpr int kGpd3Threads = BFPIC_GPD3_THREADS;
+// Row stride along y of their LDS current region (0: its extent).  A wave's
+// lanes hold particles of one tile plane, 8 x 8 cells; at the extent's 17
+// nodes their FP64 adds share LDS banks, at 22 (the largest stride whose
+// 18 x 17 x 22 FP64 region fits the 160 KB) far fewer: 2.94 against 3.13 ms
+// per launch at 512 x 128 x 128 (20 nodes: 2.96 ms).
+#ifndef BFPIC_GPD3_LDS_Y
+#define BFPIC_GPD3_LDS_Y 22
+#endif
+constexpr int kGpd3LdsY = BFPIC_GPD3_LDS_Y;
 // Tiles dispatched largest first (1) or in XCD-aware grid order (0)
 #ifndef BFPIC_TILE_ORDER
 #define BFPIC_TILE_ORDER 1
@@ -941,7 +950,7 @@ struct Impl {
       return (const void*)k_gpd_tiled<R, 3, ORDER, kT3, kT3, kT3, kExc, kGpdThreads<R>, DET>;
     else
       return (const void*)k_gpd_tiled<R, 3, ORDER, kT3, kT3, kT3, kExc, kGpd3Threads, DET,
-                                      false>;
+                                      false, kGpd3LdsY>;
   }
 
   // Per-configuration kernel set-up at create: opt in to large dynamic LDS.
@@ -996,7 +1005,7 @@ struct Impl {
         k_gpd_tiled<R, 3, ORDER, kT3, kT3, kT3, kExc, kGpdThreads<R>, DET>
             <<<T.ntiles, kGpdThreads<R>, h->lds_tiled, h->stream>>>(P, F, S, T, O, h->scratch);
       else
-        k_gpd_tiled<R, 3, ORDER, kT3, kT3, kT3, kExc, kGpd3Threads, DET, false>
+        k_gpd_tiled<R, 3, ORDER, kT3, kT3, kT3, kExc, kGpd3Threads, DET, false, kGpd3LdsY>
             <<<T.ntiles, kGpd3Threads, h->lds_tiled, h->stream>>>(P, F, S, T, O, h->scratch);
       HIPCHK(h, hipGetLastError());
     }
@@ -1945,7 +1954,7 @@ extern "C" int bfpic_create(const bfpic_config* cfg, int64_t cap, void* workspac
     // 3D tiles whose staged fields do not fit: gather from global memory and
     // keep only the FP64 (or int64) currents in LDS
     h->stage = false;
-    h->lds_tiled = (size_t)3 * h->LV * 8;
+    h->lds_tiled = (size_t)3 * h->LZ * h->LX * std::max(h->LY, kGpd3LdsY) * 8;
   }
   if (h->lds_tiled > h->lds_limit) h->tiled = false;
   // the filter kernels may need more than 64 KB of LDS (3D, FP64, many passes)

@@ -958,12 +958,16 @@ struct TileGeom {
 // The variant that gathers from global memory runs one workgroup per CU (its
 // LDS region), two waves per SIMD: it may spend the registers that leaves to
 // keep a whole stencil's loads in flight.
+// SYP: row stride (nodes) of the 3D LDS current region along y when larger
+// than its extent LY, to spread a wave's adds over the LDS banks.
 template <typename R, int DIM, int ORDER, int TZ, int TX, int TY, int EXC, int NT, bool DET,
-          bool STAGE = true>
+          bool STAGE = true, int SYP = 0>
 __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(1, STAGE ? 8 : NT / 256))) void
 k_gpd_tiled(StepK<R> P, Fields<R> F, PSoA<R> S, TileK T, Ovf<R> O, void* scratch) {
   using TG = TileGeom<DIM, ORDER, TZ, TX, TY, EXC>;
   constexpr int LZ = TG::LZ, LX = TG::LX, LY = TG::LY, LV = TG::LV;
+  constexpr int SY = (DIM == 3 && !STAGE && SYP > LY) ? SYP : LY;  // LDS row stride
+  constexpr int LVS = LZ * LX * SY;                                  // LDS component stride
   using A = LdsAcc<R, DIM, DET, STAGE>;
   extern __shared__ __align__(16) unsigned char smem_raw[];
   R* sF = reinterpret_cast<R*>(smem_raw);
@@ -1039,7 +1043,7 @@ k_gpd_tiled(StepK<R> P, Fields<R> F, PSoA<R> S, TileK T, Ovf<R> O, void* scratch
       }
     }
   }
-  for (int v = threadIdx.x; v < 3 * LV; v += NT) sJ[v] = (A)0;
+  for (int v = threadIdx.x; v < 3 * LVS; v += NT) sJ[v] = (A)0;
   // overflow rows reached by far partners, gathered per tile
   __shared__ int far_rows[2];
   // 3D: box of the region's nonzero nodes (first and last node per axis)
@@ -1053,7 +1057,7 @@ k_gpd_tiled(StepK<R> P, Fields<R> F, PSoA<R> S, TileK T, Ovf<R> O, void* scratch
     }
   }
   __syncthreads();
-  LdsSinkT<A, LX, LY, DET> ls{sJ, LV};
+  LdsSinkT<A, LX, SY, DET> ls{sJ, LVS};
   const int p0 = T.start[t], p1 = T.start[t + 1];
   // 3D: this thread's box of the region nodes its particles deposit to
   int blo[3] = {INT_MAX, INT_MAX, INT_MAX}, bhi[3] = {INT_MIN, INT_MIN, INT_MIN};
@@ -1192,10 +1196,11 @@ k_gpd_tiled(StepK<R> P, Fields<R> F, PSoA<R> S, TileK T, Ovf<R> O, void* scratch
       const int f = e - z * nxy;
       const int x = (int)(((float)f + 0.5f) * rny);
       const int y = f - x * ny;
-      dst[u] = (D)sJ[c * LV + ((z0 + z) * LX + (x0 + x)) * LY + (y0 + y)];
+      dst[u] = (D)sJ[c * LVS + ((z0 + z) * LX + (x0 + x)) * SY + (y0 + y)];
     }
     if (threadIdx.x == 0) T.box[t] = any ? pack_box(z0, nz, x0, nx, y0, ny) : 0u;
   } else {
+    static_assert(SY == LY, "padded rows in 3D only");
     for (int v = threadIdx.x; v < 3 * LV; v += NT) dst[v] = (D)sJ[v];
   }
 }
