@@ -919,9 +919,26 @@ struct Impl {
     k_filt3_x<R, NP, SX>
         <<<dim3((unsigned)cdiv((int64_t)(h->nz + 1) * nsx * h->ny, 256), 1, 3), 256, 0,
            h->stream>>>(g, fk, T1, T2, nsx);
-    const int nsy = (int)cdiv(h->ny, FY);
-    k_filt3_y<R, NP><<<dim3((unsigned)cdiv((int64_t)(h->nz + 1) * h->nx * nsy, 4), 1, 3), 256, 0,
-                       h->stream>>>(g, fk, T2, Jf, nsy);
+    const unsigned nlines = (unsigned)cdiv((int64_t)(h->nz + 1) * h->nx, 4);
+    switch (h->ny % 64 == 0 ? h->ny / 64 : 0) {
+      case 1:
+        k_filt3_y_line<R, NP, 1><<<dim3(nlines, 1, 3), 256, 0, h->stream>>>(g, fk, T2, Jf);
+        break;
+      case 2:
+        k_filt3_y_line<R, NP, 2><<<dim3(nlines, 1, 3), 256, 0, h->stream>>>(g, fk, T2, Jf);
+        break;
+      case 3:
+        k_filt3_y_line<R, NP, 3><<<dim3(nlines, 1, 3), 256, 0, h->stream>>>(g, fk, T2, Jf);
+        break;
+      case 4:
+        k_filt3_y_line<R, NP, 4><<<dim3(nlines, 1, 3), 256, 0, h->stream>>>(g, fk, T2, Jf);
+        break;
+      default: {
+        const int nsy = (int)cdiv(h->ny, FY);
+        k_filt3_y<R, NP><<<dim3((unsigned)cdiv((int64_t)(h->nz + 1) * h->nx * nsy, 4), 1, 3),
+                           256, 0, h->stream>>>(g, fk, T2, Jf, nsy);
+      }
+    }
   }
   template <bool DET>
   static bool fold_filter3(bfpic_ctx* h, const FoldK<R>& K, const FiltK& fk,
