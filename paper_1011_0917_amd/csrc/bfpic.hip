@@ -1113,8 +1113,8 @@ struct Impl {
       Y.idy = (R)(1.0 / h->dy);
       Y.mur = (R)((h->dt - h->dz) / (h->dt + h->dz));
       Y.save = (R*)h->mur_save;
-      int64_t nrow = g.periodic_z ? h->nz : h->nz + 1;
-      unsigned nb = (unsigned)cdiv(nrow * g.plane, 256);
+      const unsigned nrow = (unsigned)(g.periodic_z ? h->nz : h->nz + 1);
+      const dim3 nb((unsigned)cdiv(g.plane, 256), nrow);
       Y.h = (R)(0.5 * h->dt);
       k_yee_b<R, DIM><<<nb, 256, 0, h->stream>>>(g, Y);
       Y.h = (R)h->dt;

@@ -702,57 +702,82 @@ __device__ __forceinline__ R at(const Geo& g, const R* A, int i, int j, int k) {
   return n < 0 ? (R)0 : A[n];
 }
 
+// Node (i, j, k) of a Yee update: row i = blockIdx.y, plane index from x;
+// the storage index of a neighbour one node away along each axis (periodic
+// in x, y, and in z when the grid is; open z reads the guard rows).
+struct YeeNode {
+  int i, j, k;
+  int64_t n;            // this node
+  int64_t zp, zm;       // rows i + 1, i - 1
+  int64_t xp, xm, yp, ym;
+};
+__device__ __forceinline__ bool yee_node(const Geo& g, YeeNode& d) {
+  const int q = blockIdx.x * blockDim.x + threadIdx.x;
+  if (q >= g.plane) return false;
+  d.i = blockIdx.y;
+  d.j = q / g.ny;
+  d.k = q - d.j * g.ny;
+  const int64_t row = (int64_t)(d.i + kGuard) * g.plane;
+  d.n = row + q;
+  int ip = d.i + 1, im = d.i - 1;
+  if (g.periodic_z) {
+    if (ip == g.nz) ip = 0;
+    if (im < 0) im = g.nz - 1;
+  }
+  d.zp = (int64_t)(ip + kGuard) * g.plane + q;
+  d.zm = (int64_t)(im + kGuard) * g.plane + q;
+  const int jp = d.j + 1 == g.nx ? 0 : d.j + 1, jm = d.j == 0 ? g.nx - 1 : d.j - 1;
+  const int kp = d.k + 1 == g.ny ? 0 : d.k + 1, km = d.k == 0 ? g.ny - 1 : d.k - 1;
+  d.xp = row + (int64_t)jp * g.ny + d.k;
+  d.xm = row + (int64_t)jm * g.ny + d.k;
+  d.yp = row + (int64_t)d.j * g.ny + kp;
+  d.ym = row + (int64_t)d.j * g.ny + km;
+  return true;
+}
+
+// Launched with grid (cdiv(plane, 256), rows): rows nz + 1 (open z) or nz.
 template <typename R, int DIM>
 __global__ __launch_bounds__(256) void k_yee_b(Geo g, YeeK<R> Y) {
-  int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  int nrow = g.periodic_z ? g.nz : g.nz + 1;
-  if (v >= (int64_t)nrow * g.plane) return;
-  int i = (int)(v / g.plane);
-  int rem = (int)(v - (int64_t)i * g.plane);
-  int j = rem / g.ny, k = rem - j * g.ny;
-  int64_t n = gidx(g, i, j, k);
+  YeeNode d;
+  if (!yee_node(g, d)) return;
+  const int64_t n = d.n;
   const R* Ex = Y.E[0];
   const R* Ey = Y.E[1];
   const R* Ez = Y.E[2];
   R ey = Ey[n];
-  if (i <= row_hi(g, 1)) {
-    R dEz_dy = DIM == 3 ? (at(g, Ez, i, j, k + 1) - Ez[n]) * Y.idy : (R)0;
-    Y.B[0][n] += Y.h * ((at(g, Ey, i + 1, j, k) - ey) * Y.idz - dEz_dy);
-    Y.B[1][n] += Y.h * ((at(g, Ez, i, j + 1, k) - Ez[n]) * Y.idx -
-                        (at(g, Ex, i + 1, j, k) - Ex[n]) * Y.idz);
+  if (d.i <= row_hi(g, 1)) {
+    R dEz_dy = DIM == 3 ? (Ez[d.yp] - Ez[n]) * Y.idy : (R)0;
+    Y.B[0][n] += Y.h * ((Ey[d.zp] - ey) * Y.idz - dEz_dy);
+    Y.B[1][n] += Y.h * ((Ez[d.xp] - Ez[n]) * Y.idx - (Ex[d.zp] - Ex[n]) * Y.idz);
   }
-  R dEx_dy = DIM == 3 ? (at(g, Ex, i, j, k + 1) - Ex[n]) * Y.idy : (R)0;
-  Y.B[2][n] += Y.h * (dEx_dy - (at(g, Ey, i, j + 1, k) - ey) * Y.idx);
+  R dEx_dy = DIM == 3 ? (Ex[d.yp] - Ex[n]) * Y.idy : (R)0;
+  Y.B[2][n] += Y.h * (dEx_dy - (Ey[d.xp] - ey) * Y.idx);
 }
 
 template <typename R, int DIM>
 __global__ __launch_bounds__(256) void k_yee_e(Geo g, YeeK<R> Y) {
-  int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  int nrow = g.periodic_z ? g.nz : g.nz + 1;
-  if (v >= (int64_t)nrow * g.plane) return;
-  int i = (int)(v / g.plane);
-  int rem = (int)(v - (int64_t)i * g.plane);
-  int j = rem / g.ny, k = rem - j * g.ny;
-  int64_t n = gidx(g, i, j, k);
+  YeeNode d;
+  if (!yee_node(g, d)) return;
+  const int64_t n = d.n;
+  const int i = d.i;
   const R* Bx = Y.B[0];
   const R* By = Y.B[1];
   const R* Bz = Y.B[2];
   bool open = !g.periodic_z;
   if (i <= row_hi(g, 1)) {
-    R dBx_dy = DIM == 3 ? (Bx[n] - at(g, Bx, i, j, k - 1)) * Y.idy : (R)0;
-    Y.E[2][n] += Y.h * ((By[n] - at(g, By, i, j - 1, k)) * Y.idx - dBx_dy - Y.J[2][n]);
+    R dBx_dy = DIM == 3 ? (Bx[n] - Bx[d.ym]) * Y.idy : (R)0;
+    Y.E[2][n] += Y.h * ((By[n] - By[d.xm]) * Y.idx - dBx_dy - Y.J[2][n]);
   }
   if (open && (i == 0 || i == g.nz)) return;  // Mur planes
   if (open && (i == 1 || i == g.nz - 1)) {
     int r = i == 1 ? 0 : 1;
-    int64_t q = (int64_t)rem;
+    int64_t q = n - (int64_t)(i + kGuard) * g.plane;
     Y.save[(r * 2 + 0) * g.plane + q] = Y.E[0][n];
     Y.save[(r * 2 + 1) * g.plane + q] = Y.E[1][n];
   }
-  R dBz_dy = DIM == 3 ? (Bz[n] - at(g, Bz, i, j, k - 1)) * Y.idy : (R)0;
-  Y.E[0][n] += Y.h * (dBz_dy - (By[n] - at(g, By, i - 1, j, k)) * Y.idz - Y.J[0][n]);
-  Y.E[1][n] += Y.h * ((Bx[n] - at(g, Bx, i - 1, j, k)) * Y.idz -
-                      (Bz[n] - at(g, Bz, i, j - 1, k)) * Y.idx - Y.J[1][n]);
+  R dBz_dy = DIM == 3 ? (Bz[n] - Bz[d.ym]) * Y.idy : (R)0;
+  Y.E[0][n] += Y.h * (dBz_dy - (By[n] - By[d.zm]) * Y.idz - Y.J[0][n]);
+  Y.E[1][n] += Y.h * ((Bx[n] - Bx[d.zm]) * Y.idz - (Bz[n] - Bz[d.xm]) * Y.idx - Y.J[1][n]);
 }
 
 // 2D Yee step fused into one kernel: B half step, E step with the filtered
