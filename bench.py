@@ -332,8 +332,8 @@ def main():
                     help="after the run, copy MIB MiB three times (counter calibration)")
     args = ap.parse_args()
     if args.gpus != 1:
-        print("bench.py measures one GPU: this build runs on a single MI355X "
-              "(multi-GPU sharding is a design note, not built)", file=sys.stderr)
+        print("bench.py measures one GPU: the library runs on a single MI355X "
+              "(sharding across GPUs is described, not built)", file=sys.stderr)
         sys.exit(2)
     from workloads import WORKLOADS
     explicit_steps = args.steps
