@@ -123,7 +123,7 @@ __global__ __launch_bounds__(256) void k_sort_scatter(const int* counts, const i
 // loaded in two independent rounds, then an odd-even transposition network
 // orders them); a fuller one by insertion through memory.  Ids are distinct,
 // so both give the same order.
-constexpr int kCellReg = 16;
+constexpr int kCellReg = 32;
 
 __global__ __launch_bounds__(256) void k_sort_cells(const int* off, const int* id, int* perm,
                                                     int nkeys) {
